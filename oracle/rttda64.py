@@ -1,0 +1,385 @@
+"""FP64 oracle for the RT-TDA hot path (test infrastructure only).
+
+What it computes, and where the paper defines it (Knoll & Levine, "GPU-accelerated
+real-time Tamm-Dancoff approximation", arxiv 2601.16949):
+
+* The TDA matrix A (Theory and Methods, eq. A_matrix_element2), taken in
+  density-fitted form with a hybrid exchange term and without the f_xc kernel:
+      A_{ia,jb} = delta_ij delta_ab (e_a - e_i) + 2 sum_Q B^Q_ia B^Q_jb
+                  - c_x sum_Q B^Q_ij B^Q_ab
+  with ia in virtuals-run-fastest order (text after eq. A_matrix_element2).
+* The extended space with the Kohn-Sham ground state as element 0 and
+  A_{0,ia} = 0 (Real-Time TDA subsection, text after eq. ode_rt_tda).  A_00 is
+  read as 0 so that spectral peaks sit at the excitation energies (the
+  F-coronene excitation-energy table compares peaks with TI-TDA energies).
+* The dipole coupling (eqs. e_field, sigmas): H(t) = A_0 - E(t) mu.d, with mu
+  mapped from the MO basis to CSFs by the Slater-Condon rules (eqs. sc1-sc6).
+  The constant <Phi0|mu|Phi0> (sc1, sc3) acts as a multiple of the identity on
+  the whole space and is dropped.
+* The time-dependent Schroedinger equation i dX/dt = H(t) X (eq. ode_rt_tda),
+  integrated with the classic 4-stage Runge-Kutta method (the paper uses a
+  split-operator integrator; this path uses RK4), with fields evaluated at
+  t, t+dt/2, t+dt/2, t+dt where t = n dt.
+* Pulses (eqs. delta_pulse, continuous wave, transform_limited, chirped_pulse),
+  sigma = FWHM / 2.35482.  The delta pulse is applied as a first-order kick
+  X <- X + i kappa mu.d X before the first step (text on the delta pulse in the
+  Propagation Algorithm subsection: the response stays linear in the pulse).
+* The observable: the dipole trace mu(t_n) = Re <X_n | mu.d | X_n>, and the norm.
+
+Arrays: a state is (c0, C) with c0 complex scalar and C complex (o, v).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+SQRT2 = math.sqrt(2.0)
+FWHM_TO_SIGMA = 2.35482
+
+PULSE_NONE, PULSE_DELTA, PULSE_CW, PULSE_GAUSS, PULSE_CHIRP = 0, 1, 2, 3, 4
+
+
+class Operator:
+    """FP64 copies of the stored inputs of one molecule."""
+
+    def __init__(self, e_occ, e_virt, b_ov, b_oo, b_vv, mu, cx):
+        self.e_occ = np.asarray(e_occ, dtype=np.float64)
+        self.e_virt = np.asarray(e_virt, dtype=np.float64)
+        self.b_ov = np.asarray(b_ov, dtype=np.float64)
+        self.b_oo = np.asarray(b_oo, dtype=np.float64)
+        self.b_vv = np.asarray(b_vv, dtype=np.float64)
+        self.mu = np.asarray(mu, dtype=np.float64)
+        self.cx = float(cx)
+        self.o = self.e_occ.shape[0]
+        self.v = self.e_virt.shape[0]
+        self.nq = self.b_ov.shape[0]
+
+    @classmethod
+    def from_problem(cls, p):
+        return cls(p.e_occ, p.e_virt, p.b_ov, p.b_oo, p.b_vv, p.mu, p.cx)
+
+
+# ----------------------------------------------------------------------------------------
+# A applied to a real o x v amplitude matrix (eq. A_matrix_element2, DF form)
+# ----------------------------------------------------------------------------------------
+def orbital_gaps(op: Operator) -> np.ndarray:
+    """D_ia = e_a - e_i: the diagonal term delta_ij delta_ab (e_a - e_i)."""
+    return op.e_virt[None, :] - op.e_occ[:, None]
+
+
+def coulomb(op: Operator, C: np.ndarray) -> np.ndarray:
+    """J_ia = 2 sum_jb (ia|jb) C_jb with (ia|jb) = sum_Q B^Q_ia B^Q_jb."""
+    d = np.einsum("qjb,jb->q", op.b_ov, C)
+    return 2.0 * np.einsum("q,qia->ia", d, op.b_ov)
+
+
+def exchange(op: Operator, C: np.ndarray, q_chunk: int = 64) -> np.ndarray:
+    """K_ia = sum_jb (ij|ab) C_jb = sum_Q (B^Q_oo C B^Q_vv)_ia, (ij|ab) = sum_Q B^Q_ij B^Q_ab."""
+    K = np.zeros_like(C)
+    for q0 in range(0, op.nq, q_chunk):
+        q1 = min(op.nq, q0 + q_chunk)
+        V = np.matmul(op.b_oo[q0:q1], C)  # (nq_chunk, o, v)
+        K += np.matmul(V, op.b_vv[q0:q1]).sum(axis=0)
+    return K
+
+
+def apply_A_real(op: Operator, C: np.ndarray) -> np.ndarray:
+    return orbital_gaps(op) * C + coulomb(op, C) - op.cx * exchange(op, C)
+
+
+def apply_A(op: Operator, C: np.ndarray) -> np.ndarray:
+    """A is real, so it acts on the real and imaginary parts of C separately."""
+    if np.iscomplexobj(C):
+        return apply_A_real(op, C.real) + 1j * apply_A_real(op, C.imag)
+    return apply_A_real(op, C)
+
+
+# ----------------------------------------------------------------------------------------
+# Dipole coupling (eqs. e_field, sc1-sc6)
+# ----------------------------------------------------------------------------------------
+def dipole_along(op: Operator, direction) -> np.ndarray:
+    d = np.asarray(direction, dtype=np.float64)
+    return np.einsum("k,kpq->pq", d, op.mu)
+
+
+def dipole_blocks(op: Operator, direction):
+    m = dipole_along(op, direction)
+    o = op.o
+    return m[:o, :o], m[:o, o:], m[o:, o:]
+
+
+def apply_dipole(blocks, c0, C):
+    """(M X) for X = (c0, C), M the CSF-basis dipole from the Slater-Condon rules:
+    (M X)_0  = sqrt2 sum_ia mu_ia c_ia                              (sc2)
+    (M X)_ia = sqrt2 mu_ia c0 + sum_b mu_ab c_ib - sum_j mu_ij c_ja  (sc2, sc3-sc5; sc6 -> 0)
+    The i=j, a=b terms of the last two sums give the diagonal mu_aa - mu_ii (sc3)."""
+    moo, mov, mvv = blocks
+    g = SQRT2 * np.sum(mov * C)
+    F = C @ mvv - moo @ C + SQRT2 * mov * c0
+    return g, F
+
+
+def dense_dipole_csf(op: Operator, direction) -> np.ndarray:
+    """Dense (1+ov) x (1+ov) CSF-basis dipole written rule by rule (eqs. sc1-sc6),
+    with <Phi0|mu|Phi0> dropped.  Pure Python loops: tiny inputs only."""
+    moo, mov, mvv = dipole_blocks(op, direction)
+    o, v = op.o, op.v
+    n = o * v
+    M = np.zeros((n + 1, n + 1))
+    for i in range(o):
+        for a in range(v):
+            ia = 1 + i * v + a
+            M[0, ia] = M[ia, 0] = SQRT2 * mov[i, a]  # sc2
+            for j in range(o):
+                for b in range(v):
+                    jb = 1 + j * v + b
+                    if i == j and a == b:
+                        M[ia, jb] = mvv[a, a] - moo[i, i]  # sc3 minus <Phi0|mu|Phi0>
+                    elif i == j:
+                        M[ia, jb] = mvv[a, b]  # sc4
+                    elif a == b:
+                        M[ia, jb] = -moo[i, j]  # sc5
+                    # else sc6: 0
+    return M
+
+
+def dense_dipole_csf_fast(op: Operator, direction) -> np.ndarray:
+    """Same matrix as dense_dipole_csf, assembled with Kronecker products (for larger ov)."""
+    moo, mov, mvv = dipole_blocks(op, direction)
+    o, v = op.o, op.v
+    n = o * v
+    M = np.zeros((n + 1, n + 1))
+    M[0, 1:] = SQRT2 * mov.reshape(-1)
+    M[1:, 0] = M[0, 1:]
+    M[1:, 1:] = np.kron(np.eye(o), mvv) - np.kron(moo, np.eye(v))
+    return M
+
+
+# ----------------------------------------------------------------------------------------
+# Dense A (explicit four-index integrals) -- the definition written out
+# ----------------------------------------------------------------------------------------
+def eri_ovov(op: Operator) -> np.ndarray:
+    """(ia|jb) = sum_Q B^Q_ia B^Q_jb as a 4-index array [i,a,j,b]."""
+    return np.einsum("qia,qjb->iajb", op.b_ov, op.b_ov)
+
+
+def eri_oovv(op: Operator) -> np.ndarray:
+    """(ij|ab) = sum_Q B^Q_ij B^Q_ab as a 4-index array [i,j,a,b]."""
+    return np.einsum("qij,qab->ijab", op.b_oo, op.b_vv)
+
+
+def dense_A(op: Operator) -> np.ndarray:
+    o, v = op.o, op.v
+    A = 2.0 * eri_ovov(op) - op.cx * eri_oovv(op).transpose(0, 2, 1, 3)
+    A = A.reshape(o * v, o * v)
+    A[np.diag_indices(o * v)] += orbital_gaps(op).reshape(-1)
+    return A
+
+
+def dense_A_blas(op: Operator) -> np.ndarray:
+    """dense_A assembled through two GEMMs (for ov in the tens of thousands)."""
+    o, v, nq = op.o, op.v, op.nq
+    Bov = op.b_ov.reshape(nq, o * v)
+    A = 2.0 * (Bov.T @ Bov)
+    X = (op.b_oo.reshape(nq, o * o).T @ op.b_vv.reshape(nq, v * v))  # [(i,j),(a,b)]
+    A -= op.cx * X.reshape(o, o, v, v).transpose(0, 2, 1, 3).reshape(o * v, o * v)
+    A[np.diag_indices(o * v)] += orbital_gaps(op).reshape(-1)
+    return A
+
+
+# ----------------------------------------------------------------------------------------
+# Pulses (eqs. delta_pulse .. chirped_pulse)
+# ----------------------------------------------------------------------------------------
+def field_value(p, t: float) -> float:
+    """E(t) of a continuous pulse; 0 for the delta pulse (it acts as a kick at t = 0)."""
+    kind = p.kind
+    if kind in (PULSE_NONE, PULSE_DELTA):
+        return 0.0
+    if kind == PULSE_CW:
+        return p.e0 * math.sin(p.omega * t + p.phase)
+    s = p.fwhm / FWHM_TO_SIGMA
+    tau = t - p.t0
+    env = math.exp(-tau * tau / (2.0 * s * s))
+    if kind == PULSE_GAUSS:
+        return p.e0 * env * math.sin(p.omega * tau + p.phase)
+    if kind == PULSE_CHIRP:
+        return p.e0 * env * math.sin((p.omega + 0.5 * p.beta * tau) * tau + p.phase)
+    raise ValueError(f"unknown pulse kind {kind}")
+
+
+# ----------------------------------------------------------------------------------------
+# H(t) X, kick, observables
+# ----------------------------------------------------------------------------------------
+def apply_H(op: Operator, blocks, E: float, c0, C):
+    """H X with H = diag(0, A) - E M (eq. e_field): returns ((H X)_0, (H X)_C)."""
+    g, F = apply_dipole(blocks, c0, C)
+    return -E * g, apply_A(op, C) - E * F
+
+
+def kick(blocks, kappa: float, c0, C):
+    """First-order delta kick X <- X + i kappa M X."""
+    g, F = apply_dipole(blocks, c0, C)
+    return c0 + 1j * kappa * g, C + 1j * kappa * F
+
+
+def dipole_expectation(blocks, c0, C) -> float:
+    """Re <X | M | X>."""
+    g, F = apply_dipole(blocks, c0, C)
+    return float((np.conj(c0) * g).real + np.sum(np.conj(C) * F).real)
+
+
+def norm2(c0, C) -> float:
+    return float(abs(c0) ** 2 + np.sum(np.abs(C) ** 2))
+
+
+def energy(op: Operator, c0, C) -> float:
+    """<X | diag(0, A) | X>."""
+    return float(np.sum(np.conj(C) * apply_A(op, C)).real)
+
+
+# ----------------------------------------------------------------------------------------
+# RK4 propagation, direct route (O1)
+# ----------------------------------------------------------------------------------------
+RK4_NODES = (0.0, 0.5, 0.5, 1.0)
+
+
+def rk4_step(op: Operator, blocks, pulse, dt: float, n: int, c0, C):
+    """One classic RK4 step of dX/dt = -i H(t) X from t = n dt."""
+
+    def f(frac, y0, Y):
+        t = (n + frac) * dt
+        h0, hC = apply_H(op, blocks, field_value(pulse, t), y0, Y)
+        return -1j * h0, -1j * hC
+
+    k1 = f(0.0, c0, C)
+    k2 = f(0.5, c0 + 0.5 * dt * k1[0], C + 0.5 * dt * k1[1])
+    k3 = f(0.5, c0 + 0.5 * dt * k2[0], C + 0.5 * dt * k2[1])
+    k4 = f(1.0, c0 + dt * k3[0], C + dt * k3[1])
+    c0n = c0 + dt / 6.0 * (k1[0] + 2.0 * k2[0] + 2.0 * k3[0] + k4[0])
+    Cn = C + dt / 6.0 * (k1[1] + 2.0 * k2[1] + 2.0 * k3[1] + k4[1])
+    return c0n, Cn
+
+
+def propagate(op: Operator, pulse, dt: float, n_steps: int, c0=1.0 + 0j, C=None, step0: int = 0,
+              want_norm: bool = False):
+    """Propagate one right-hand side; returns (trace[n_steps+1], c0, C[, norms]).
+
+    Starts from the Kohn-Sham ground state (c0 = 1, C = 0) unless given.  A delta
+    pulse kicks the state once when step0 == 0."""
+    if C is None:
+        C = np.zeros((op.o, op.v), dtype=np.complex128)
+    c0 = complex(c0)
+    C = np.array(C, dtype=np.complex128)
+    blocks = dipole_blocks(op, pulse.direction)
+    if pulse.kind == PULSE_DELTA and step0 == 0:
+        c0, C = kick(blocks, pulse.e0, c0, C)
+    trace = np.empty(n_steps + 1)
+    norms = np.empty(n_steps + 1)
+    trace[0] = dipole_expectation(blocks, c0, C)
+    norms[0] = norm2(c0, C)
+    for n in range(n_steps):
+        c0, C = rk4_step(op, blocks, pulse, dt, step0 + n, c0, C)
+        trace[n + 1] = dipole_expectation(blocks, c0, C)
+        norms[n + 1] = norm2(c0, C)
+    if want_norm:
+        return trace, c0, C, norms
+    return trace, c0, C
+
+
+# ----------------------------------------------------------------------------------------
+# Eigen route (O2): dense A, eigh, and RK4 in the eigenbasis
+# ----------------------------------------------------------------------------------------
+def rk4_amplification(z):
+    """Stability polynomial of classic RK4: R(z) = 1 + z + z^2/2 + z^3/6 + z^4/24."""
+    return 1.0 + z + z * z / 2.0 + z ** 3 / 6.0 + z ** 4 / 24.0
+
+
+class EigenRoute:
+    """Extended-space eigen decomposition: w[0] = 0 (ground state), w[1:] = eig(A)."""
+
+    def __init__(self, op: Operator, A=None):
+        if A is None:
+            A = dense_A_blas(op) if op.o * op.v > 600 else dense_A(op)
+        w, U = np.linalg.eigh(A)
+        n = op.o * op.v
+        self.op = op
+        self.w = np.concatenate([[0.0], w])
+        self.U = np.zeros((n + 1, n + 1))
+        self.U[0, 0] = 1.0
+        self.U[1:, 1:] = U
+
+    def to_eig(self, c0, C):
+        x = np.concatenate([[complex(c0)], np.asarray(C, dtype=np.complex128).reshape(-1)])
+        return self.U.T @ x
+
+    def from_eig(self, y):
+        x = self.U @ y
+        return x[0], x[1:].reshape(self.op.o, self.op.v)
+
+    def dipole_eig(self, direction):
+        M = dense_dipole_csf_fast(self.op, direction)
+        return self.U.T @ M @ self.U
+
+    def propagate_field_free(self, pulse, dt: float, n_steps: int, c0=1.0 + 0j, C=None,
+                             want_state: bool = False):
+        """Exact RK4 map for field-free steps: y_n = R(-i w dt)^n y_0 (after the kick)."""
+        if C is None:
+            C = np.zeros((self.op.o, self.op.v), dtype=np.complex128)
+        blocks = dipole_blocks(self.op, pulse.direction)
+        if pulse.kind == PULSE_DELTA:
+            c0, C = kick(blocks, pulse.e0, complex(c0), np.asarray(C, dtype=np.complex128))
+        elif pulse.kind != PULSE_NONE:
+            raise ValueError("field-free route takes only delta or no pulse")
+        y = self.to_eig(c0, C)
+        Me = self.dipole_eig(pulse.direction)
+        R = rk4_amplification(-1j * self.w * dt)
+        trace = np.empty(n_steps + 1)
+        for n in range(n_steps + 1):
+            trace[n] = float(np.real(np.conj(y) @ (Me @ y)))
+            if n < n_steps:
+                y = R * y
+        if want_state:
+            return trace, y
+        return trace
+
+    def propagate_rk4(self, pulse, dt: float, n_steps: int, c0=1.0 + 0j, C=None):
+        """RK4 with a field, run in the eigenbasis (RK4 commutes with the change of basis)."""
+        if C is None:
+            C = np.zeros((self.op.o, self.op.v), dtype=np.complex128)
+        blocks = dipole_blocks(self.op, pulse.direction)
+        c0, C = complex(c0), np.asarray(C, dtype=np.complex128)
+        if pulse.kind == PULSE_DELTA:
+            c0, C = kick(blocks, pulse.e0, c0, C)
+        y = self.to_eig(c0, C)
+        Me = self.dipole_eig(pulse.direction)
+        w = self.w
+
+        def f(t, y):
+            return -1j * (w * y - field_value(pulse, t) * (Me @ y))
+
+        trace = np.empty(n_steps + 1)
+        trace[0] = float(np.real(np.conj(y) @ (Me @ y)))
+        for n in range(n_steps):
+            k1 = f(n * dt, y)
+            k2 = f((n + 0.5) * dt, y + 0.5 * dt * k1)
+            k3 = f((n + 0.5) * dt, y + 0.5 * dt * k2)
+            k4 = f((n + 1.0) * dt, y + dt * k3)
+            y = y + dt / 6.0 * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
+            trace[n + 1] = float(np.real(np.conj(y) @ (Me @ y)))
+        return trace, y
+
+
+# ----------------------------------------------------------------------------------------
+# Sampled single elements (for full-size checks where whole arrays are too costly)
+# ----------------------------------------------------------------------------------------
+def sigma_element(op: Operator, C_real: np.ndarray, i: int, a: int, d: np.ndarray = None) -> float:
+    """(A C)_ia for one (i, a) of a real C, by direct sums over Q, j, b."""
+    if d is None:
+        d = np.einsum("qjb,jb->q", op.b_ov, C_real)
+    diag = (op.e_virt[a] - op.e_occ[i]) * C_real[i, a]
+    J = 2.0 * float(np.dot(op.b_ov[:, i, a], d))
+    # K_ia = sum_Q sum_j B_oo[Q,i,j] sum_b C[j,b] B_vv[Q,b,a]
+    t = np.einsum("qj,jb,qb->q", op.b_oo[:, i, :], C_real, op.b_vv[:, :, a])
+    K = float(t.sum())
+    return diag + J - op.cx * K

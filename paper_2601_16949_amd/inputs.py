@@ -1,0 +1,284 @@
+"""Seeded synthetic inputs for RT-TDA propagation problems.
+
+This module is shared by the FP64 CPU oracle and the HIP path: it only draws
+random numbers and rounds them to the storage dtype. It holds none of the
+method's arithmetic (no sigma vector, no field term, no integrator).
+
+Recipe (stand-ins for the paper's molecules, whose geometries and integrals are
+not available):
+
+* orbital energies: e_i ~ U[-1.0, -0.3] Ha (occupied), e_a ~ U[0.05, 1.5] Ha
+  (virtual), each sorted ascending, kept in FP64;
+* density-fitting factors B^Q_ov (o x v), B^Q_oo (o x o, symmetric),
+  B^Q_vv (v x v, symmetric): N(0,1) * s_eff drawn in FP32, one independent
+  stream per (seed, tensor, Q) so any single Q slice can be regenerated alone;
+  the symmetric factors keep the upper triangle (with the diagonal) of a full
+  square draw and mirror it;
+* s_eff = min(s, 1.547 / (sqrt(o v) + sqrt(N_Q))): the literal scale makes the
+  Coulomb block's top eigenvalue (Marchenko-Pastur edge 2 s^2 (sqrt(ov) +
+  sqrt(N_Q))^2) so large that RK4 at the requested dt diverges; the cap holds
+  that edge at 4.79 Ha, which is the value of the smallest configuration;
+* dipole matrices: three symmetric (o+v) x (o+v) matrices N(0,1) * 0.5 in FP64,
+  one per Cartesian direction (x, y, z);
+* storage rounding: FP32 (round to nearest) or BF16 (round to nearest even of
+  the FP32 value); the oracle reads exactly the rounded values.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+SEED_BASE = 16949
+TENSOR_E_OCC, TENSOR_E_VIRT, TENSOR_B_OV, TENSOR_B_OO, TENSOR_B_VV, TENSOR_MU, TENSOR_PULSE = range(7)
+
+# Pulse kinds (the four pulses of the paper's pulse equations, plus none).
+PULSE_NONE, PULSE_DELTA, PULSE_CW, PULSE_GAUSS, PULSE_CHIRP = 0, 1, 2, 3, 4
+
+
+@dataclass
+class Pulse:
+    """One right-hand side's external field.
+
+    kind:  PULSE_* code.  For PULSE_DELTA, e0 is the kick strength kappa.
+    e0:    peak field (au).  omega: carrier (Ha).  t0: envelope centre (au).
+    fwhm:  envelope full width at half maximum (au), sigma = fwhm / 2.35482.
+    beta:  chirp rate (Ha/au).  phase: carrier phase (rad; pi/2 turns sin into cos).
+    direction: polarisation unit vector (3,).
+    """
+
+    kind: int = PULSE_NONE
+    e0: float = 0.0
+    omega: float = 0.0
+    t0: float = 0.0
+    fwhm: float = 1.0
+    beta: float = 0.0
+    phase: float = 0.0
+    direction: tuple = (0.0, 0.0, 1.0)
+
+
+@dataclass
+class Shape:
+    o: int
+    v: int
+    nq: int
+    b_scale: float = 0.05
+    mu_scale: float = 0.5
+    cx: float = 0.2
+    storage: str = "f32"  # "f32" | "bf16"
+    rescale: bool = True
+
+    @property
+    def s_eff(self) -> float:
+        if not self.rescale:
+            return self.b_scale
+        cap = 1.547 / (math.sqrt(self.o * self.v) + math.sqrt(max(self.nq, 0)))
+        return min(self.b_scale, cap)
+
+
+@dataclass
+class Problem:
+    """Stored (rounded) inputs. Float arrays hold exactly the stored values."""
+
+    shape: Shape
+    seed: int
+    e_occ: np.ndarray  # f64 (o,)
+    e_virt: np.ndarray  # f64 (v,)
+    b_ov: np.ndarray  # f32 (nq, o, v), values exactly representable in `storage`
+    b_oo: np.ndarray  # f32 (nq, o, o)
+    b_vv: np.ndarray  # f32 (nq, v, v)
+    mu: np.ndarray  # f64 (3, o+v, o+v)
+
+    @property
+    def o(self):
+        return self.shape.o
+
+    @property
+    def v(self):
+        return self.shape.v
+
+    @property
+    def nq(self):
+        return self.shape.nq
+
+    @property
+    def cx(self):
+        return self.shape.cx
+
+
+def _rng(seed: int, tensor: int, q: int = 0) -> np.random.Generator:
+    return np.random.default_rng(np.random.SeedSequence([int(seed), int(tensor), int(q)]))
+
+
+def round_bf16(x: np.ndarray) -> np.ndarray:
+    """Round FP32 values to the nearest BF16 (ties to even); returns FP32."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    u = x.view(np.uint32).astype(np.uint64)
+    lsb = (u >> 16) & 1
+    r = ((u + 0x7FFF + lsb) >> 16) << 16
+    out = r.astype(np.uint32).view(np.float32)
+    # NaN/Inf are not produced by this generator; keep them untouched anyway
+    bad = ~np.isfinite(x)
+    if bad.any():
+        out = out.copy()
+        out[bad] = x[bad]
+    return out
+
+
+def bf16_bits(x: np.ndarray) -> np.ndarray:
+    """Upper 16 bits of FP32 values that are exactly BF16-representable."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    return (x.view(np.uint32) >> 16).astype(np.uint16)
+
+
+def _store(x: np.ndarray, storage: str) -> np.ndarray:
+    if storage == "f32":
+        return x.astype(np.float32, copy=False)
+    if storage == "bf16":
+        return round_bf16(x)
+    raise ValueError(f"unknown storage dtype {storage!r}")
+
+
+def _sym(m: np.ndarray) -> np.ndarray:
+    up = np.triu(m)
+    return up + np.triu(m, 1).T
+
+
+def gen_b_ov(shape: Shape, seed: int, q: int) -> np.ndarray:
+    s = np.float32(shape.s_eff)
+    x = _rng(seed, TENSOR_B_OV, q).standard_normal((shape.o, shape.v), dtype=np.float32) * s
+    return _store(x, shape.storage)
+
+
+def gen_b_oo(shape: Shape, seed: int, q: int) -> np.ndarray:
+    s = np.float32(shape.s_eff)
+    x = _sym(_rng(seed, TENSOR_B_OO, q).standard_normal((shape.o, shape.o), dtype=np.float32)) * s
+    return _store(x, shape.storage)
+
+
+def gen_b_vv(shape: Shape, seed: int, q: int) -> np.ndarray:
+    s = np.float32(shape.s_eff)
+    x = _sym(_rng(seed, TENSOR_B_VV, q).standard_normal((shape.v, shape.v), dtype=np.float32)) * s
+    return _store(x, shape.storage)
+
+
+def gen_mu(shape: Shape, seed: int) -> np.ndarray:
+    n = shape.o + shape.v
+    out = np.empty((3, n, n), dtype=np.float64)
+    for k in range(3):
+        out[k] = _sym(_rng(seed, TENSOR_MU, k).standard_normal((n, n))) * shape.mu_scale
+    return out
+
+
+def gen_energies(shape: Shape, seed: int):
+    e_occ = np.sort(_rng(seed, TENSOR_E_OCC).uniform(-1.0, -0.3, size=shape.o))
+    e_virt = np.sort(_rng(seed, TENSOR_E_VIRT).uniform(0.05, 1.5, size=shape.v))
+    return e_occ.astype(np.float64), e_virt.astype(np.float64)
+
+
+def make_problem(shape: Shape, seed: int) -> Problem:
+    e_occ, e_virt = gen_energies(shape, seed)
+    o, v, nq = shape.o, shape.v, shape.nq
+    b_ov = np.empty((nq, o, v), dtype=np.float32)
+    b_oo = np.empty((nq, o, o), dtype=np.float32)
+    b_vv = np.empty((nq, v, v), dtype=np.float32)
+    for q in range(nq):
+        b_ov[q] = gen_b_ov(shape, seed, q)
+        b_oo[q] = gen_b_oo(shape, seed, q)
+        b_vv[q] = gen_b_vv(shape, seed, q)
+    return Problem(shape, seed, e_occ, e_virt, b_ov, b_oo, b_vv, gen_mu(shape, seed))
+
+
+def random_state(o: int, v: int, nrhs: int, seed: int, c0_scale: float = 1.0, c_scale: float = 1.0):
+    """Random complex amplitudes for sigma-vector tests: c0 (nrhs,), c (nrhs, o, v)."""
+    rng = _rng(seed, 100, nrhs)
+    c0 = (rng.standard_normal(nrhs) + 1j * rng.standard_normal(nrhs)) * c0_scale
+    c = (rng.standard_normal((nrhs, o, v)) + 1j * rng.standard_normal((nrhs, o, v))) * c_scale
+    return c0.astype(np.complex128), c.astype(np.complex128)
+
+
+# --------------------------------------------------------------------------------------
+# The five workloads (shapes, pulses, time steps).
+# --------------------------------------------------------------------------------------
+KAPPA = 1e-4
+AXES = ((1.0, 0.0, 0.0), (0.0, 1.0, 0.0), (0.0, 0.0, 1.0))
+
+
+@dataclass
+class Workload:
+    name: str
+    shape: Shape
+    seed: int
+    dt: float
+    n_steps: int
+    pulses: List[Pulse] = field(default_factory=list)
+    precision: str = "fp32"  # "fp32" | "mixed"
+
+
+def kick_pulses(axes=AXES, kappa: float = KAPPA) -> List[Pulse]:
+    return [Pulse(kind=PULSE_DELTA, e0=kappa, direction=tuple(a)) for a in axes]
+
+
+def gauss_cos_scan(omega_low: float, e0: float, n: int = 64, fwhm: float = 400.0, t0: float = 400.0,
+                   lo: float = 0.5, hi: float = 1.2) -> List[Pulse]:
+    """Gaussian-envelope cosine pulses along z, carriers spanning [lo, hi] x omega_low."""
+    out = []
+    for r in range(n):
+        w = omega_low * (lo + (hi - lo) * r / max(n - 1, 1))
+        out.append(Pulse(kind=PULSE_GAUSS, e0=e0, omega=w, t0=t0, fwhm=fwhm, phase=math.pi / 2,
+                         direction=(0.0, 0.0, 1.0)))
+    return out
+
+
+def workload(k: int) -> Workload:
+    """k = 1..4: the single-molecule workloads (5 is the serving stream, see serving_requests)."""
+    seed = SEED_BASE + k
+    if k == 1:
+        return Workload("o10_v40_nq120_kick_z", Shape(10, 40, 120, 0.05), seed, 0.05, 2000,
+                        kick_pulses(axes=(AXES[2],)))
+    if k == 2:
+        return Workload("o60_v400_nq1500_kick_xyz", Shape(60, 400, 1500, 0.05), seed, 0.05, 20000,
+                        kick_pulses())
+    if k == 3:
+        return Workload("o240_v1800_nq5000_kick_xyz_mixed", Shape(240, 1800, 5000, 0.02, storage="bf16"),
+                        seed, 0.1, 4000, kick_pulses(), precision="mixed")
+    if k == 4:
+        # omega_low (lowest eigenvalue of A) is filled in by the caller that knows it
+        return Workload("o40_v300_nq1000_gauss_cos_scan64", Shape(40, 300, 1000, 0.05), seed, 0.05, 16000, [])
+    raise ValueError(k)
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float
+    shape: Shape
+    seed: int
+    n_steps: int
+    dt: float
+    pulse: Pulse
+
+
+def serving_requests(n: int, rate: float = 20.0, seed: int = SEED_BASE + 5, o_min: int = 10,
+                     o_max: int = 240) -> List[Request]:
+    """Poisson arrivals of mixed-size requests: o ~ U{o_min..o_max}, v = floor(7.5 o),
+    N_Q = 20 o, steps ~ U{500..8000}, dt 0.05, half delta kicks (z) and half Gaussian-sine
+    pulses with E0 ~ U[0.001, 0.03], omega ~ U[0.3, 0.8], FWHM 400 au, t0 = half the run."""
+    rng = _rng(seed, TENSOR_PULSE, 0)
+    t = 0.0
+    out = []
+    for rid in range(n):
+        t += rng.exponential(1.0 / rate)
+        o = int(rng.integers(o_min, o_max + 1))
+        v = int(math.floor(7.5 * o))
+        steps = int(rng.integers(500, 8001))
+        dt = 0.05
+        if rng.uniform() < 0.5:
+            p = Pulse(kind=PULSE_DELTA, e0=KAPPA, direction=(0.0, 0.0, 1.0))
+        else:
+            p = Pulse(kind=PULSE_GAUSS, e0=float(rng.uniform(0.001, 0.03)), omega=float(rng.uniform(0.3, 0.8)),
+                      t0=0.5 * steps * dt, fwhm=400.0, direction=(0.0, 0.0, 1.0))
+        out.append(Request(rid, t, Shape(o, v, 20 * o, 0.02, storage="bf16"), seed * 1000 + rid, steps, dt, p))
+    return out

@@ -1,0 +1,462 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix (CPU only).
+
+Each test names the passage of arxiv 2601.16949 it follows.  None of them calls
+the HIP path.
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+from oracle import rttda64 as O
+from oracle import spectrum as S
+from paper_2601_16949_amd import inputs as I
+
+
+def tiny_op(o=2, v=3, nq=3, cx=0.2, seed=7, scale=0.3, mu_scale=0.5):
+    shape = I.Shape(o, v, nq, b_scale=scale, mu_scale=mu_scale, cx=cx, rescale=False)
+    return O.Operator.from_problem(I.make_problem(shape, seed))
+
+
+def custom_op(e_occ, e_virt, b_ov, b_oo, b_vv, mu=None, cx=0.2):
+    o, v = len(e_occ), len(e_virt)
+    if mu is None:
+        mu = np.zeros((3, o + v, o + v))
+    return O.Operator(e_occ, e_virt, b_ov, b_oo, b_vv, mu, cx)
+
+
+def pulse(kind, **kw):
+    return I.Pulse(kind=kind, **kw)
+
+
+# ------------------------------------------------------------------------------------------
+# P1/P15: density-fitted sigma against the four-index definition (eq. A_matrix_element2, eq. eri)
+# ------------------------------------------------------------------------------------------
+def test_p1_df_sigma_matches_four_index_brute_force():
+    op = tiny_op(o=3, v=4, nq=5)
+    rng = np.random.default_rng(1)
+    C = rng.standard_normal((3, 4))
+    # brute force: explicit sums over i,a,j,b,Q
+    ref = np.zeros((3, 4))
+    for i, a, j, b in itertools.product(range(3), range(4), range(3), range(4)):
+        eri_iajb = sum(op.b_ov[q, i, a] * op.b_ov[q, j, b] for q in range(op.nq))
+        eri_ijab = sum(op.b_oo[q, i, j] * op.b_vv[q, a, b] for q in range(op.nq))
+        Aij = (op.e_virt[a] - op.e_occ[i]) * (i == j and a == b) + 2.0 * eri_iajb - op.cx * eri_ijab
+        ref[i, a] += Aij * C[j, b]
+    np.testing.assert_allclose(O.apply_A(op, C), ref, rtol=0, atol=1e-13)
+    np.testing.assert_allclose((O.dense_A(op) @ C.reshape(-1)).reshape(3, 4), ref, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(O.dense_A_blas(op), O.dense_A(op), rtol=0, atol=1e-13)
+
+
+def test_p15_exchange_alone_brute_force():
+    op = tiny_op(o=3, v=5, nq=4)
+    C = np.random.default_rng(2).standard_normal((3, 5))
+    ref = np.zeros((3, 5))
+    for i, a, j, b, q in itertools.product(range(3), range(5), range(3), range(5), range(4)):
+        ref[i, a] += op.b_oo[q, i, j] * op.b_vv[q, a, b] * C[j, b]
+    np.testing.assert_allclose(O.exchange(op, C), ref, rtol=0, atol=1e-13)
+
+
+# ------------------------------------------------------------------------------------------
+# P2: A is real symmetric -> unitary dynamics
+# ------------------------------------------------------------------------------------------
+def test_p2_generator_symmetric():
+    op = tiny_op(o=3, v=6, nq=5)
+    rng = np.random.default_rng(3)
+    u, w = rng.standard_normal((2, 3, 6))
+    assert abs(np.sum(u * O.apply_A(op, w)) - np.sum(O.apply_A(op, u) * w)) < 1e-13
+    ev = np.linalg.eigvals(O.dense_A(op))
+    assert np.max(np.abs(ev.imag)) < 1e-12
+
+
+# ------------------------------------------------------------------------------------------
+# P3: special cases with closed forms
+# ------------------------------------------------------------------------------------------
+def test_p3_no_aux_functions_is_diagonal_rk4_closed_form():
+    rng = np.random.default_rng(4)
+    o, v = 3, 4
+    e_occ, e_virt = np.sort(rng.uniform(-1, -0.3, o)), np.sort(rng.uniform(0.05, 1.5, v))
+    op = custom_op(e_occ, e_virt, np.zeros((0, o, v)), np.zeros((0, o, o)), np.zeros((0, v, v)))
+    C0 = rng.standard_normal((o, v)) + 1j * rng.standard_normal((o, v))
+    dt, n = 0.05, 200
+    p = pulse(I.PULSE_NONE)
+    _, c0, C = O.propagate(op, p, dt, n, c0=0.3 + 0.1j, C=C0)
+    gap = e_virt[None, :] - e_occ[:, None]  # e_a - e_i
+    Rz = O.rk4_amplification(-1j * gap * dt)
+    np.testing.assert_allclose(C, Rz ** n * C0, rtol=0, atol=1e-12)
+    assert abs(c0 - (0.3 + 0.1j)) < 1e-15  # A_00 = 0: the ground coefficient does not move
+
+
+def test_p3_rank_one_coulomb_secular_equation():
+    """c_x = 0, N_Q = 1: A = D + 2 b b^T; eigenvalues solve 1 + 2 sum_k b_k^2 / (d_k - lam) = 0."""
+    rng = np.random.default_rng(5)
+    o, v = 2, 3
+    e_occ, e_virt = np.sort(rng.uniform(-1, -0.3, o)), np.sort(rng.uniform(0.05, 1.5, v))
+    b = rng.standard_normal((1, o, v)) * 0.3
+    op = custom_op(e_occ, e_virt, b, rng.standard_normal((1, o, o)), rng.standard_normal((1, v, v)), cx=0.0)
+    lam = np.linalg.eigvalsh(O.dense_A(op))
+    d = (e_virt[None, :] - e_occ[:, None]).reshape(-1)
+    bb = b.reshape(-1) ** 2
+    sec = 1.0 + 2.0 * np.array([np.sum(bb / (d - l)) for l in lam])
+    assert np.max(np.abs(sec)) < 1e-9
+    # and via the DF sigma: each eigenvector is reproduced
+    w, U = np.linalg.eigh(O.dense_A(op))
+    for k in range(o * v):
+        u = U[:, k].reshape(o, v)
+        np.testing.assert_allclose(O.apply_A(op, u), w[k] * u, atol=1e-13)
+
+
+def test_p3_exchange_kronecker_spectra():
+    """Degenerate gaps delta and c_x-only coupling: A = delta I - c_x (B_oo x B_vv) for N_Q = 1,
+    so eig(A) = delta - c_x eig(B_oo) eig(B_vv) (all products).  Pins the sign of c_x and
+    that B_oo acts on the occupied and B_vv on the virtual index."""
+    rng = np.random.default_rng(6)
+    o, v = 3, 4
+    delta = 0.7
+    e_occ, e_virt = np.full(o, -0.2), np.full(v, delta - 0.2)
+    Boo = rng.standard_normal((o, o)); Boo = Boo + Boo.T
+    Bvv = rng.standard_normal((v, v)); Bvv = Bvv + Bvv.T
+    cx = 0.3
+    op = custom_op(e_occ, e_virt, np.zeros((1, o, v)), Boo[None], Bvv[None], cx=cx)
+    lam = np.sort(np.linalg.eigvalsh(O.dense_A(op)))
+    expect = np.sort(delta - cx * np.outer(np.linalg.eigvalsh(Boo), np.linalg.eigvalsh(Bvv)).reshape(-1))
+    np.testing.assert_allclose(lam, expect, atol=1e-12)
+    # an eigenvector is u (x) w of the factors: K(u w^T) = (Boo u)(Bvv w)^T = a b u w^T
+    a, U = np.linalg.eigh(Boo)
+    bvals, W = np.linalg.eigh(Bvv)
+    X = np.outer(U[:, 0], W[:, -1])
+    np.testing.assert_allclose(O.apply_A(op, X), (delta - cx * a[0] * bvals[-1]) * X, atol=1e-13)
+
+
+# ------------------------------------------------------------------------------------------
+# P4: Slater-Condon rules (eqs. sc1-sc6) against second quantisation on determinants
+# ------------------------------------------------------------------------------------------
+def _apply_excitation(state, p, q):
+    """a+_p a_q on a dict {bitmask: coeff} of determinants (spin orbitals ordered by index)."""
+    out = {}
+    for det, c in state.items():
+        if not (det >> q) & 1:
+            continue
+        s = (-1) ** bin(det & ((1 << q) - 1)).count("1")
+        d1 = det & ~(1 << q)
+        if (d1 >> p) & 1:
+            continue
+        s *= (-1) ** bin(d1 & ((1 << p) - 1)).count("1")
+        d2 = d1 | (1 << p)
+        out[d2] = out.get(d2, 0.0) + s * c
+    return out
+
+
+def _add(a, b, f=1.0):
+    out = dict(a)
+    for k, c in b.items():
+        out[k] = out.get(k, 0.0) + f * c
+    return out
+
+
+def _dot(a, b):
+    return sum(c * b.get(k, 0.0) for k, c in a.items())
+
+
+def test_p4_slater_condon_from_determinants():
+    o, v = 2, 3
+    op = tiny_op(o=o, v=v, nq=1)
+    d = np.array([0.3, -0.5, 0.8]); d /= np.linalg.norm(d)
+    mu = O.dipole_along(op, d)
+    n = o + v
+    spin = lambda p, s: 2 * p + s  # noqa: E731
+    phi0 = {sum(1 << spin(i, s) for i in range(o) for s in (0, 1)): 1.0}
+    basis = [phi0]
+    for i in range(o):
+        for a in range(o, n):
+            st = {}
+            for s in (0, 1):
+                st = _add(st, _apply_excitation(phi0, spin(a, s), spin(i, s)), 1.0 / math.sqrt(2.0))
+            basis.append(st)
+
+    def apply_mu(st):
+        out = {}
+        for p in range(n):
+            for q in range(n):
+                if mu[p, q] == 0.0:
+                    continue
+                for s in (0, 1):
+                    out = _add(out, _apply_excitation(st, spin(p, s), spin(q, s)), mu[p, q])
+        return out
+
+    Mb = np.array([[_dot(bi, apply_mu(bj)) for bj in basis] for bi in basis])
+    mu00 = Mb[0, 0]
+    assert abs(mu00 - 2.0 * np.trace(mu[:o, :o])) < 1e-13  # sc1 over both spins
+    Mb -= mu00 * np.eye(len(basis))  # <Phi0|mu|Phi0> acts as a multiple of identity: dropped
+    np.testing.assert_allclose(O.dense_dipole_csf(op, d), Mb, atol=1e-13)
+    np.testing.assert_allclose(O.dense_dipole_csf_fast(op, d), Mb, atol=1e-13)
+    # the factorised product equals the dense matrix on a random complex state
+    rng = np.random.default_rng(8)
+    x = rng.standard_normal(1 + o * v) + 1j * rng.standard_normal(1 + o * v)
+    g, F = O.apply_dipole(O.dipole_blocks(op, d), x[0], x[1:].reshape(o, v))
+    y = Mb @ x
+    assert abs(g - y[0]) < 1e-13
+    np.testing.assert_allclose(F.reshape(-1), y[1:], atol=1e-13)
+
+
+def test_dropped_ground_dipole_only_offsets_trace():
+    """Adding mu00 * I to M changes Re<X|M|X> by mu00 |X|^2 and nothing else."""
+    op = tiny_op(o=2, v=3, nq=2)
+    d = (0.0, 0.0, 1.0)
+    M = O.dense_dipole_csf(op, d)
+    rng = np.random.default_rng(9)
+    x = rng.standard_normal(7) + 1j * rng.standard_normal(7)
+    mu00 = 0.37
+    t1 = np.real(np.conj(x) @ M @ x)
+    t2 = np.real(np.conj(x) @ (M + mu00 * np.eye(7)) @ x)
+    assert abs((t2 - t1) - mu00 * np.vdot(x, x).real) < 1e-13
+
+
+# ------------------------------------------------------------------------------------------
+# P5/P6/P13: field-free RK4 in the eigenbasis (eq. ode_rt_tda)
+# ------------------------------------------------------------------------------------------
+def test_p5_eigenvector_evolves_by_rk4_factor_and_near_exact_phase():
+    op = tiny_op(o=2, v=4, nq=3)
+    w, U = np.linalg.eigh(O.dense_A(op))
+    k = 3
+    X0 = U[:, k].reshape(2, 4).astype(np.complex128)
+    dt, n = 0.05, 400
+    _, c0, C = O.propagate(op, pulse(I.PULSE_NONE), dt, n, c0=0.0, C=X0)
+    Rn = O.rk4_amplification(-1j * w[k] * dt) ** n
+    np.testing.assert_allclose(C, Rn * X0, atol=1e-12)
+    assert abs(c0) == 0.0
+    exact = np.exp(-1j * w[k] * n * dt) * X0
+    bound = n * (w[k] * dt) ** 5 / 120.0 * 1.01 + 1e-13
+    assert np.max(np.abs(C - exact)) <= bound
+
+
+def test_p6_p13_norm_and_energy_follow_rk4_closed_form():
+    op = tiny_op(o=2, v=3, nq=3)
+    route = O.EigenRoute(op)
+    rng = np.random.default_rng(10)
+    C0 = (rng.standard_normal((2, 3)) + 1j * rng.standard_normal((2, 3))) * 0.3
+    c00 = 0.8 + 0.1j
+    dt, n = 0.05, 300
+    _, c0, C = O.propagate(op, pulse(I.PULSE_NONE), dt, n, c0=c00, C=C0)
+    y0 = route.to_eig(c00, C0)
+    amp = np.abs(O.rk4_amplification(-1j * route.w * dt)) ** (2 * n)
+    assert abs(O.norm2(c0, C) - np.sum(np.abs(y0) ** 2 * amp)) < 1e-12
+    assert abs(O.energy(op, c0, C) - np.sum(route.w * np.abs(y0) ** 2 * amp)) < 1e-12
+
+
+def test_p6_norm_conserved_to_1e10_at_small_step():
+    op = tiny_op(o=2, v=3, nq=3)
+    _, c0, C, norms = O.propagate(op, pulse(I.PULSE_DELTA, e0=1e-2, direction=(0, 0, 1)), 0.01, 2000,
+                                  want_norm=True)
+    assert np.max(np.abs(norms - norms[0])) < 1e-10
+
+
+# ------------------------------------------------------------------------------------------
+# P7: direct route == eigen route (both are the same RK4 map)
+# ------------------------------------------------------------------------------------------
+def test_p7_direct_equals_eigen_route_cfg1_shape():
+    wl = I.workload(1)
+    prob = I.make_problem(wl.shape, wl.seed)
+    op = O.Operator.from_problem(prob)
+    p = wl.pulses[0]
+    n = 300
+    tr1, _, _ = O.propagate(op, p, wl.dt, n)
+    tr2 = O.EigenRoute(op).propagate_field_free(p, wl.dt, n)
+    scale = np.max(np.abs(tr1))
+    assert np.max(np.abs(tr1 - tr2)) / scale < 1e-11
+
+
+def test_p7_direct_equals_eigen_route_with_pulse():
+    op = tiny_op(o=2, v=4, nq=3)
+    p = pulse(I.PULSE_CHIRP, e0=0.05, omega=0.6, t0=3.0, fwhm=4.0, beta=0.01, phase=0.3, direction=(0.6, 0.0, 0.8))
+    tr1, c0, C = O.propagate(op, p, 0.05, 200)
+    tr2, y = O.EigenRoute(op).propagate_rk4(p, 0.05, 200)
+    np.testing.assert_allclose(tr1, tr2, atol=1e-12)
+
+
+# ------------------------------------------------------------------------------------------
+# P8: static two-level system, closed form (field coupling with the sqrt2 of sc2)
+# ------------------------------------------------------------------------------------------
+def test_p8_static_two_level_closed_form():
+    w, mu_ia, E0 = 0.4, 0.7, 0.02
+    mu = np.zeros((3, 2, 2)); mu[2, 0, 1] = mu[2, 1, 0] = mu_ia
+    op = custom_op(np.array([-0.5]), np.array([w - 0.5]), np.zeros((0, 1, 1)), np.zeros((0, 1, 1)),
+                   np.zeros((0, 1, 1)), mu=mu)
+    p = pulse(I.PULSE_CW, e0=E0, omega=0.0, phase=math.pi / 2, direction=(0, 0, 1))  # constant E0
+    dt, n = 0.01, 3000
+    blocks = O.dipole_blocks(op, p.direction)
+    c0, C = 1.0 + 0j, np.zeros((1, 1), complex)
+    g = math.sqrt(2.0) * mu_ia * E0
+    Om = math.sqrt(w * w + 4 * g * g)
+    worst = 0.0
+    for k in range(n):
+        c0, C = O.rk4_step(op, blocks, p, dt, k, c0, C)
+        t = (k + 1) * dt
+        P1 = 4 * g * g / (Om * Om) * math.sin(Om * t / 2) ** 2
+        worst = max(worst, abs(abs(C[0, 0]) ** 2 - P1))
+    assert worst < 1e-10
+
+
+# ------------------------------------------------------------------------------------------
+# P9: Rabi periods of the paper (Rabi Oscillations subsection, table tab:rabi_periods)
+# ------------------------------------------------------------------------------------------
+def _load_rabi_golden():
+    import os
+
+    path = os.path.join(os.path.dirname(__file__), "golden", "rabi_periods.txt")
+    rows = []
+    meta = {}
+    for line in open(path):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            if line.startswith("# param"):
+                _, _, k, val = line.split()
+                meta[k] = float(val)
+            continue
+        rows.append([float(x) for x in line.split()])
+    return meta, np.array(rows)
+
+
+def test_p9_paper_rabi_periods_and_units():
+    meta, rows = _load_rabi_golden()
+    E0 = math.sqrt(meta["intensity_w_cm2"] / 3.50944758e16)
+    T_au = 2.0 * math.pi / (meta["tdm_au"] * E0)
+    T_fs = T_au * S.AU_FS
+    assert round(T_fs, 2) == rows[0, 2]
+    for k, (idx, rt, exact, err) in enumerate(rows, start=1):
+        assert abs(k * round(T_fs, 2) - exact) < 1e-9  # the paper's exact column is k x 18.22
+        assert abs(abs(rt - exact) - err) < 1e-9
+
+
+def test_p9_resonant_cw_rabi_period_two_level():
+    """Resonant CW drive of a two-level system: population returns to the ground state after
+    2 pi / (|M_01| E0) (rotating-wave result the paper compares against), |M_01| = sqrt2 mu_ia."""
+    w, mu_ia, E0 = 0.43, 1.5624 / math.sqrt(2.0), 5.338e-3
+    mu = np.zeros((3, 2, 2)); mu[2, 0, 1] = mu[2, 1, 0] = mu_ia
+    op = custom_op(np.array([-0.5]), np.array([w - 0.5]), np.zeros((0, 1, 1)), np.zeros((0, 1, 1)),
+                   np.zeros((0, 1, 1)), mu=mu)
+    p = pulse(I.PULSE_CW, e0=E0, omega=w, direction=(0, 0, 1))
+    T = 2 * math.pi / (1.5624 * E0)
+    dt = 0.1
+    n = int(1.2 * T / dt)
+    blocks = O.dipole_blocks(op, p.direction)
+    c0, C = 1.0 + 0j, np.zeros((1, 1), complex)
+    pop = np.empty(n)
+    for k in range(n):
+        c0, C = O.rk4_step(op, blocks, p, dt, k, c0, C)
+        pop[k] = abs(c0) ** 2
+    half = np.argmin(pop[: int(0.75 * T / dt)])
+    assert pop[half] < 0.01  # complete inversion at T/2
+    k_back = int(0.75 * T / dt) + np.argmax(pop[int(0.75 * T / dt):])
+    assert abs((k_back + 1) * dt - T) / T < 0.01
+
+
+# ------------------------------------------------------------------------------------------
+# P10/P11/P14: kick spectrum (Propagation Algorithm, Absorption spectrum subsections)
+# ------------------------------------------------------------------------------------------
+def test_p10_kick_peaks_at_rk4_frequencies():
+    op = tiny_op(o=2, v=3, nq=2, scale=0.2)
+    route = O.EigenRoute(op)
+    d = (0.0, 0.0, 1.0)
+    kappa, dt, n = 1e-4, 0.2, 100000
+    tr = route.propagate_field_free(pulse(I.PULSE_DELTA, e0=kappa, direction=d), dt, n)
+    wI = route.w[1:]
+    Me = route.dipole_eig(d)
+    strength = wI * Me[0, 1:] ** 2
+    wt = -np.angle(O.rk4_amplification(-1j * wI * dt)) / dt  # RK4-modified frequencies
+    pk = S.peaks(tr, dt, kappa, rel_height=0.05, refine=True)
+    expect = [w for w, s in zip(wt, strength) if s >= 0.1 * strength.max()]
+    for w in expect:
+        dist = min(abs(p - w) for p, _ in pk)
+        assert dist < 1e-6, (w, pk)
+    # heights follow w_I |M_0I|^2 (up to window normalisation): compare ratios of the two largest
+    order = np.argsort(strength)[::-1][:2]
+    h = [S.dtft(tr, dt, kappa, wt[k]) for k in order]
+    assert abs(h[1] / h[0] - strength[order[1]] / strength[order[0]]) < 2e-3
+
+
+def test_p11_trace_linear_in_kick_and_initial_slope_positive():
+    op = tiny_op(o=2, v=4, nq=3)
+    d = (0.0, 0.0, 1.0)
+    tr1, _, _ = O.propagate(op, pulse(I.PULSE_DELTA, e0=1e-4, direction=d), 0.05, 100)
+    tr2, _, _ = O.propagate(op, pulse(I.PULSE_DELTA, e0=2e-4, direction=d), 0.05, 100)
+    lin1, lin2 = tr1 - tr1[0], tr2 - tr2[0]
+    assert np.max(np.abs(lin2 - 2 * lin1)) < 1e-3 * np.max(np.abs(lin2))
+    assert tr1[1] - tr1[0] > 0  # mu(t) ~ +2 kappa sum |M_0I|^2 sin(w_I t)
+    # kicked norm: 1 + 2 kappa^2 |mu_ov|^2 exactly
+    blocks = O.dipole_blocks(op, d)
+    c0, C = O.kick(blocks, 1e-4, 1.0 + 0j, np.zeros((2, 4), complex))
+    assert abs(O.norm2(c0, C) - (1 + 2e-8 * np.sum(blocks[1] ** 2))) < 1e-15
+
+
+def test_p14_resolution_matches_paper():
+    # Absorption spectrum subsection: 3000 au gives an energy resolution of 0.057 eV
+    assert round(S.resolution(3000.0) * S.HARTREE_EV, 3) == 0.057
+
+
+# ------------------------------------------------------------------------------------------
+# P12: RK4 global error is fourth order, also with a time-dependent field
+# ------------------------------------------------------------------------------------------
+def test_p12_global_error_fourth_order_with_pulse():
+    op = tiny_op(o=2, v=3, nq=2)
+    p = pulse(I.PULSE_GAUSS, e0=0.05, omega=0.8, t0=2.0, fwhm=3.0, phase=0.4, direction=(0, 0, 1))
+    T = 4.0
+    H0 = np.zeros((7, 7)); H0[1:, 1:] = O.dense_A(op)
+    M = O.dense_dipole_csf(op, p.direction)
+    from scipy.integrate import solve_ivp
+
+    def rhs(t, x):
+        return -1j * ((H0 - O.field_value(p, t) * M) @ x)
+
+    x0 = np.zeros(7, complex); x0[0] = 1.0
+    ref = solve_ivp(rhs, (0, T), x0, method="DOP853", rtol=1e-13, atol=1e-14).y[:, -1]
+    errs, dts = [], [0.2, 0.1, 0.05, 0.025]
+    blocks = O.dipole_blocks(op, p.direction)
+    for dt in dts:
+        c0, C = 1.0 + 0j, np.zeros((2, 3), complex)
+        for k in range(int(round(T / dt))):
+            c0, C = O.rk4_step(op, blocks, p, dt, k, c0, C)
+        x = np.concatenate([[c0], C.reshape(-1)])
+        errs.append(np.linalg.norm(x - ref))
+    slope = np.polyfit(np.log(dts), np.log(errs), 1)[0]
+    assert abs(slope - 4.0) < 0.1, (slope, errs)
+
+
+def test_exact_propagator_agrees_at_small_step():
+    """Field-free RK4 against exp(-i A t) (matrix exponential) within the RK4 error bound."""
+    op = tiny_op(o=2, v=3, nq=3)
+    A = O.dense_A(op)
+    C0 = np.random.default_rng(11).standard_normal((2, 3)).astype(complex)
+    dt, n = 0.02, 500
+    _, _, C = O.propagate(op, pulse(I.PULSE_NONE), dt, n, c0=0.0, C=C0)
+    ex = scipy.linalg.expm(-1j * A * n * dt) @ C0.reshape(-1)
+    rho = np.max(np.abs(np.linalg.eigvalsh(A)))
+    assert np.max(np.abs(C.reshape(-1) - ex)) < n * (rho * dt) ** 5 / 120 * np.linalg.norm(C0) + 1e-12
+
+
+# ------------------------------------------------------------------------------------------
+# Pulses (eqs. delta_pulse .. chirped_pulse) and sampled elements
+# ------------------------------------------------------------------------------------------
+def test_pulse_shapes():
+    sig = 400.0 / 2.35482
+    g = pulse(I.PULSE_GAUSS, e0=0.02, omega=0.5, t0=400.0, fwhm=400.0)
+    # half maximum of the envelope at t0 +- FWHM/2 (sin factor divided out)
+    for t in (200.0, 600.0):
+        env = O.field_value(g, t) / (0.02 * math.sin(0.5 * (t - 400.0)))
+        assert abs(env - 0.5) < 1e-5
+    c = pulse(I.PULSE_CHIRP, e0=0.02, omega=0.5, t0=400.0, fwhm=400.0, beta=0.0)
+    assert O.field_value(c, 123.0) == O.field_value(g, 123.0)
+    cw = pulse(I.PULSE_CW, e0=0.3, omega=0.7)
+    assert abs(O.field_value(cw, 2.0) - 0.3 * math.sin(1.4)) < 1e-16
+    assert O.field_value(pulse(I.PULSE_DELTA, e0=1.0), 0.0) == 0.0
+    assert abs(sig - 169.8652) < 1e-3
+
+
+def test_sigma_element_matches_full():
+    op = tiny_op(o=3, v=5, nq=4)
+    C = np.random.default_rng(12).standard_normal((3, 5))
+    full = O.apply_A(op, C)
+    for i, a in [(0, 0), (2, 4), (1, 3)]:
+        assert abs(O.sigma_element(op, C, i, a) - full[i, a]) < 1e-14
