@@ -1,0 +1,198 @@
+/*
+ * rttda.h -- C ABI of the MI355X (gfx950) RT-TDA propagation library.
+ *
+ * The library evaluates the Hamiltonian-amplitude product of real-time
+ * Tamm-Dancoff (RT-TDA) electron dynamics and integrates the time-dependent
+ * Schroedinger equation with it (Knoll & Levine, arxiv 2601.16949):
+ *
+ *   i dX/dt = H(t) X,   H(t) = diag(0, A) - E(t) M_d                 (eqs. ode_rt_tda, e_field)
+ *
+ * on the extended amplitude space X = (c0, C): c0 is the Kohn-Sham ground-state
+ * coefficient (Real-Time TDA subsection: A_{0,ia} = 0, A_00 taken as 0) and
+ * C[i][a] the singles amplitudes in virtuals-run-fastest order (text after eq.
+ * A_matrix_element2).  A is given in density-fitted form:
+ *
+ *   (A C)_ia = (e_a - e_i) C_ia + 2 sum_Q B^Q_ia sum_jb B^Q_jb C_jb
+ *              - c_x sum_Q (B^Q_oo C B^Q_vv)_ia                       (eq. A_matrix_element2, DF form)
+ *
+ * and M_d is the CSF-basis dipole along the unit vector d, mapped from the MO
+ * basis by the Slater-Condon rules (eqs. sc1-sc6), without the constant
+ * <Phi0|mu|Phi0>:
+ *
+ *   (M_d X)_0  = sqrt2 sum_ia mu_ia C_ia
+ *   (M_d X)_ia = (C mu_vv - mu_oo C)_ia + sqrt2 mu_ia c0.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All array arguments are DEVICE pointers owned by the caller (host pointers
+ *    are marked "host").  Device arrays must be 16-byte aligned and stay alive
+ *    for as long as a context that refers to them.
+ *  - Complex amplitudes are stored as separate real planes:
+ *        c0 : f64 [nrhs][2]           (re, im)
+ *        c  : f64 [nrhs][2][o][v]     (plane 0 = Re C, plane 1 = Im C)
+ *  - Every call is asynchronous on the context's stream (hipStream_t, NULL =
+ *    the null stream).  Device faults surface at the next synchronisation.
+ *  - The library never allocates device memory: all scratch space lives in
+ *    the caller-supplied workspace (size from rttda_workspace_bytes()).
+ *  - Errors: a negative rttda_status; rttda_last_error() returns a
+ *    thread-local message describing the last failure on the calling thread.
+ *    Arguments are validated before anything is enqueued, so a failed call
+ *    leaves all device arrays untouched.
+ *  - A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef RTTDA_H
+#define RTTDA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rttda_ctx rttda_ctx;
+
+typedef enum {
+  RTTDA_OK = 0,
+  RTTDA_E_INVAL = -1,       /* bad argument (null/misaligned pointer, bad size, bad dtype)  */
+  RTTDA_E_NOMEM = -2,       /* workspace too small                                          */
+  RTTDA_E_DEVICE = -3,      /* a HIP runtime call failed                                    */
+  RTTDA_E_STATE = -4,       /* context in the wrong state (e.g. destroyed, no kernel)      */
+  RTTDA_E_UNSTABLE = -5,    /* norm guard tripped: non-finite or growing amplitudes        */
+  RTTDA_E_UNSUPPORTED = -6  /* shape or option not supported by this build                 */
+} rttda_status;
+
+typedef enum { RTTDA_F64 = 0, RTTDA_F32 = 1, RTTDA_BF16 = 2 } rttda_dtype;
+
+typedef enum {
+  RTTDA_PREC_FP32 = 1,       /* FP32 factors, FP32 MFMA Coulomb/exchange, FP64 state        */
+  RTTDA_PREC_MIXED_BF16 = 2  /* BF16 factors, split BF16 (hi+lo) exchange products with     */
+                             /* FP32 accumulation, FP32 Coulomb, FP64 state                  */
+} rttda_precision;
+
+/* Pulse shapes: eqs. delta_pulse, continuous wave, transform_limited, chirped_pulse. */
+typedef enum {
+  RTTDA_PULSE_NONE = 0,
+  RTTDA_PULSE_DELTA = 1,  /* first-order kick X <- X + i e0 M_d X applied when step0 == 0   */
+  RTTDA_PULSE_CW = 2,     /* E(t) = e0 sin(omega t + phase)                                  */
+  RTTDA_PULSE_GAUSS = 3,  /* E(t) = e0 exp(-(t-t0)^2 / 2 s^2) sin(omega (t-t0) + phase)      */
+  RTTDA_PULSE_CHIRP = 4   /* E(t) = e0 exp(-(t-t0)^2 / 2 s^2)                                */
+                          /*        sin((omega + beta (t-t0)/2)(t-t0) + phase)               */
+} rttda_pulse_kind;       /* s = fwhm / 2.35482; phase = pi/2 turns sin into cos             */
+
+typedef struct rttda_pulse {
+  int32_t kind;     /* rttda_pulse_kind                                          */
+  int32_t reserved; /* must be 0                                                 */
+  double e0;        /* peak field (au); kick strength kappa for DELTA            */
+  double omega;     /* carrier angular frequency (Ha)                            */
+  double t0;        /* envelope centre (au)                                      */
+  double fwhm;      /* envelope full width at half maximum (au), > 0            */
+  double beta;      /* chirp rate (Ha/au)                                        */
+  double phase;     /* carrier phase (rad)                                       */
+  double dir[3];    /* polarisation, unit vector (|dir| = 1 within 1e-12)        */
+} rttda_pulse;
+
+/* One molecule (operator).  All pointers are device pointers. */
+typedef struct rttda_desc {
+  int32_t n_occ;      /* o >= 1                                                          */
+  int32_t n_virt;     /* v >= 1                                                          */
+  int32_t n_aux;      /* N_Q >= 0                                                        */
+  int32_t precision;  /* rttda_precision                                                 */
+  int32_t b_dtype;    /* RTTDA_F32 with PREC_FP32, RTTDA_BF16 with PREC_MIXED_BF16       */
+  int32_t max_rhs;    /* largest nrhs any call will pass (1..4096)                       */
+  double cx;          /* fraction of exact exchange c_x                                  */
+  const double *e_occ;  /* f64 [o]   occupied orbital energies (Ha)                      */
+  const double *e_virt; /* f64 [v]   virtual orbital energies (Ha)                       */
+  const void *b_ov;     /* b_dtype [N_Q][o][v]  factors B^Q_ia                           */
+  const void *b_oo;     /* b_dtype [N_Q][o][o]  factors B^Q_ij, symmetric in (i, j)      */
+  const void *b_vv;     /* b_dtype [N_Q][v][v]  factors B^Q_ab, symmetric in (a, b)      */
+  const double *mu;     /* f64 [3][o+v][o+v]    MO dipole matrices (x, y, z), symmetric  */
+  void *workspace;      /* >= rttda_workspace_bytes(desc) bytes, 256-byte aligned        */
+  size_t workspace_bytes;
+  void *stream;         /* hipStream_t for every call on this context (NULL allowed)     */
+} rttda_desc;
+
+/* Bytes of workspace a context with this descriptor needs (pointers may be NULL here). */
+rttda_status rttda_workspace_bytes(const rttda_desc *desc, size_t *bytes);
+
+/* Validate the descriptor, carve the workspace and precompute the orbital-gap
+ * diagonal.  The context keeps the descriptor's pointers (not copies of the
+ * arrays).  Enqueues work on desc->stream. */
+rttda_status rttda_create(const rttda_desc *desc, rttda_ctx **out);
+
+/* Release the host-side context (and its cached HIP graphs).  Synchronises the stream. */
+rttda_status rttda_destroy(rttda_ctx *ctx);
+
+/* Change the stream of later calls. */
+rttda_status rttda_set_stream(rttda_ctx *ctx, void *stream);
+
+/* s = H X for nrhs independent states (no factor -i), with field strengths
+ * field[r] (host, au) along the unit vectors dir[r] (host, [nrhs][3]):
+ *   s0[r] = -field[r] (M_dr X_r)_0,  s[r] = A C_r - field[r] (M_dr X_r)_C.
+ * c0, c: inputs as described above; s0 (f64 [nrhs][2]) and s (f64
+ * [nrhs][2][o][v]) are outputs and may not alias the inputs. */
+rttda_status rttda_sigma(rttda_ctx *ctx, int32_t nrhs, const double *field, const double *dir,
+                         const double *c0, const double *c, double *s0, double *s);
+
+/* Advance nrhs states by n_steps classic RK4 steps of size dt, in place.
+ * pulses (host, [nrhs]) gives each state's field; step0 is the index of the
+ * current time (t = step0 * dt), so a run split into several calls gives the
+ * same result as one call.  Delta pulses kick their state before the first
+ * step when step0 == 0.  If trace is not NULL it receives the dipole trace
+ *   trace[k][r] = Re <X_r | M_dr | X_r> at step step0 + k, k = 0..n_steps
+ * (f64 [n_steps+1][nrhs]); norms likewise receives |c0|^2 + |C|^2 if not NULL.
+ * The norm guard records the first step at which a norm is non-finite or more
+ * than twice its value at the start of the call; read it with rttda_guard(). */
+rttda_status rttda_propagate(rttda_ctx *ctx, int32_t nrhs, const rttda_pulse *pulses, double dt,
+                             int64_t step0, int64_t n_steps, double *c0, double *c, double *trace,
+                             double *norms);
+
+/* out[r] = Re <X_r | M_dr | X_r> (f64 [nrhs]) for states c0, c and host unit
+ * vectors dir ([nrhs][3]): the observable behind every trace sample. */
+rttda_status rttda_dipole_trace(rttda_ctx *ctx, int32_t nrhs, const double *dir, const double *c0,
+                                const double *c, double *out);
+
+/* Synchronise the context's stream and report the norm guard of the last
+ * rttda_propagate: *first_bad_step = -1 if it never tripped, else the absolute
+ * step index; returns RTTDA_E_UNSTABLE in the latter case. */
+rttda_status rttda_guard(rttda_ctx *ctx, int64_t *first_bad_step);
+
+/* Launch configuration knobs (for the autotuner).  Zero fields keep the
+ * library's choice.  Returns RTTDA_E_UNSUPPORTED for a tile variant this build
+ * does not have, RTTDA_E_NOMEM when the splits do not fit the workspace. */
+typedef struct rttda_tuning {
+  int32_t exchange_variant; /* index into the exchange tile table (1-based), 0 = auto      */
+  int32_t exchange_splits;  /* number of Q ranges the exchange is split into               */
+  int32_t coulomb_splits;   /* number of Q ranges the second Coulomb product is split into */
+  int32_t use_graph;        /* 1 = replay RK4 steps from a captured HIP graph, 2 = direct  */
+  int32_t steps_per_graph;  /* RK4 steps captured in one graph                              */
+} rttda_tuning;
+rttda_status rttda_set_tuning(rttda_ctx *ctx, const rttda_tuning *t);
+rttda_status rttda_get_tuning(const rttda_ctx *ctx, rttda_tuning *t);
+
+/* Per-kernel-class timing with HIP events on the context's stream.  While profiling is
+ * on, rttda_propagate launches kernels directly (no graph replay) and brackets each
+ * launch group with an event pair; rttda_get_profile synchronises and returns the
+ * launch counts and summed durations since profiling was last switched on.
+ * Classes: 0 exchange, 1 Coulomb pair, 2 field/trace, 3 RK4 epilogue + stage scalars. */
+typedef struct rttda_profile {
+  int64_t launches[4];
+  double ms[4];
+} rttda_profile;
+rttda_status rttda_set_profiling(rttda_ctx *ctx, int32_t on);
+rttda_status rttda_get_profile(rttda_ctx *ctx, rttda_profile *out);
+
+/* Number of exchange tile variants and a description of variant k (1-based). */
+int32_t rttda_exchange_variants(int32_t precision);
+const char *rttda_exchange_variant_name(int32_t precision, int32_t k);
+
+/* Thread-local message for the last failed call on this thread ("" if none). */
+const char *rttda_last_error(void);
+
+/* Library version string. */
+const char *rttda_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RTTDA_H */

@@ -1,0 +1,101 @@
+"""Exchange tile autotuner: times every exchange tile variant and Q split that fits a shape.
+
+For a context (one operator, a fixed RHS count), each candidate (variant, splits) runs a few
+propagation steps with the library's per-kernel-class event profiling on, and the candidate
+with the smallest average exchange launch time wins.  Results are cached in a JSON file keyed
+by (precision, o, v, N_Q, nrhs) so later contexts of the same shape reuse the choice.
+
+    from paper_2601_16949_amd import autotune
+    best = autotune.tune(ctx, pulses, dt, nrhs)      # applies the best setting to ctx
+"""
+from __future__ import annotations
+
+import json
+import os
+from typing import Dict, List, Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_CACHE = os.path.join(HERE, "autotune_cache.json")
+
+
+def _key(ctx, nrhs: int) -> str:
+    d = ctx.desc
+    return f"p{d.precision}_o{d.n_occ}_v{d.n_virt}_nq{d.n_aux}_r{nrhs}"
+
+
+def load_cache(path: str = DEFAULT_CACHE) -> Dict[str, dict]:
+    if os.path.exists(path):
+        with open(path) as f:
+            return json.load(f)
+    return {}
+
+
+def save_cache(cache: Dict[str, dict], path: str = DEFAULT_CACHE):
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def candidates(ctx, max_per_variant: int = 4) -> List[tuple]:
+    """(variant, splits) pairs: every variant holding o, with splits around the library's default."""
+    lib = ctx.lib
+    prec = ctx.desc.precision
+    n = lib.rttda_exchange_variants(prec)
+    base = ctx.get_tuning()
+    out = []
+    for k in range(1, n + 1):
+        try:
+            ctx.set_tuning(exchange_variant=k)
+        except Exception:
+            continue  # variant does not hold o
+        s0 = ctx.get_tuning()["exchange_splits"]
+        for s in sorted({max(1, s0 // 2), s0, s0 * 2, s0 * 3})[:max_per_variant]:
+            out.append((k, s))
+    ctx.set_tuning(exchange_variant=base["exchange_variant"], exchange_splits=base["exchange_splits"])
+    return out
+
+
+def measure(ctx, pulses, dt: float, c0, c, steps: int = 3) -> float:
+    """Average exchange launch time (ms) over `steps` RK4 steps."""
+    import torch
+
+    ctx.set_profiling(True)
+    ctx.propagate(pulses, dt, steps, c0, c, want_trace=False)
+    torch.cuda.synchronize()
+    prof = ctx.get_profile()
+    ctx.set_profiling(False)
+    ex = prof["exchange"]
+    return ex["ms"] / max(ex["launches"], 1)
+
+
+def tune(ctx, pulses, dt: float, nrhs: Optional[int] = None, steps: int = 3, cache_path: str = DEFAULT_CACHE,
+         use_cache: bool = True, verbose: bool = False) -> dict:
+    from . import rttda
+
+    nrhs = nrhs or len(pulses)
+    key = _key(ctx, nrhs)
+    cache = load_cache(cache_path) if use_cache else {}
+    if key in cache:
+        best = cache[key]
+        ctx.set_tuning(exchange_variant=best["variant"], exchange_splits=best["splits"])
+        return best
+    c0, c = rttda.ground_state(nrhs, ctx.o, ctx.v, device=ctx.device)
+    results = []
+    for k, s in candidates(ctx):
+        try:
+            ctx.set_tuning(exchange_variant=k, exchange_splits=s)
+        except rttda.RttdaError:
+            continue
+        measure(ctx, pulses, dt, c0, c, steps=1)  # warm
+        ms = measure(ctx, pulses, dt, c0, c, steps=steps)
+        results.append({"variant": k, "name": ctx.variant_name(k), "splits": s, "ms": ms})
+        if verbose:
+            print(f"  {ctx.variant_name(k):24s} splits {s:3d}: {ms * 1e3:9.1f} us", flush=True)
+    best = min(results, key=lambda r: r["ms"])
+    ctx.set_tuning(exchange_variant=best["variant"], exchange_splits=best["splits"])
+    best = dict(best, candidates=len(results))
+    if use_cache:
+        cache[key] = best
+        save_cache(cache, cache_path)
+    return best

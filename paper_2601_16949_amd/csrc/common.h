@@ -1,0 +1,96 @@
+// Internal declarations of the RT-TDA gfx950 library (kernels + runtime).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "rttda.h"
+
+namespace rttda {
+
+// Device copy of rttda_pulse (identical layout, checked by static_assert in the runtime).
+struct DevPulse {
+  int32_t kind;
+  int32_t reserved;
+  double e0, omega, t0, fwhm, beta, phase;
+  double dir[3];
+};
+
+// Device-resident propagation scalars.
+struct DevState {
+  long long step;      // absolute step index of the current state c
+  long long step0;     // step index at the start of the current propagate call
+  long long bad_step;  // first step at which the norm guard tripped, -1 if none
+  long long pad;
+  double *trace;       // trace row of step0 ([n_steps+1][nrhs]) or NULL; set per call, so a
+  double *norms;       // captured step graph stays valid across calls with new output arrays
+};
+
+// Per-RHS scalar slots (f64): g_re, g_im, E(t_stage), spare.
+constexpr int SC_STRIDE = 4;
+constexpr int SC_GRE = 0, SC_GIM = 1, SC_E = 2;
+// Per-block partial sums of the field kernel (f64): g_re, g_im, <X|F>, |X|^2.
+constexpr int PART_STRIDE = 4;
+
+// Field-kernel tile (i x a) and its grid per RHS.
+constexpr int FT_I = 16, FT_A = 64;
+inline int field_blocks_a(int v) { return (v + FT_A - 1) / FT_A; }
+inline int field_blocks_i(int o) { return (o + FT_I - 1) / FT_I; }
+
+// k_scalar modes (bit mask).
+enum : int {
+  SM_TRACE = 1,     // write trace/norm samples at index step - step0, update the guard
+  SM_C0 = 2,        // RK4 stage update of c0 with k0 = i E g
+  SM_INC = 4,       // step += 1 once the stage is done
+  SM_EFIELD = 8,    // E = pulse field at (step + node) dt (else E = 0 unless SM_KEEP_E)
+  SM_SIGMA0 = 16,   // s0 = -E g with E preset by the host
+  SM_OUT = 32,      // out[r] = <X|M|X>  (dipole_trace entry point)
+  SM_KEEP_E = 64,   // keep the E slots written by the host
+};
+
+// Epilogue modes.
+enum : int { EP_RK4 = 0, EP_SIGMA = 1 };
+
+// ---------------------------------------------------------------------------------------------
+// Kernel launchers (all enqueue on `s`, return hipError_t of the launch)
+// ---------------------------------------------------------------------------------------------
+hipError_t launch_mu_blocks(hipStream_t s, const double *mu, const DevPulse *pulses, int o, int v, int R,
+                            double *moo, double *mov, double *mvv);
+hipError_t launch_gaps(hipStream_t s, const double *e_occ, const double *e_virt, int o, int v, double *D);
+hipError_t launch_to_f32(hipStream_t s, const double *c, long long n, float *x32);
+hipError_t launch_to_bf16x2(hipStream_t s, const double *c, long long n, float *x32, __hip_bfloat16 *hi,
+                            __hip_bfloat16 *lo);
+hipError_t launch_gemv1(hipStream_t s, int b_dtype, const void *B, const float *X, int nq, int ov, int ns,
+                        float *dvec);
+hipError_t launch_gemv2(hipStream_t s, int b_dtype, const void *B, const float *dvec, int nq, int ov, int ns,
+                        int nsplit, float *P);
+hipError_t launch_field(hipStream_t s, const double *X, const double *X0, const double *moo, const double *mov,
+                        const double *mvv, int o, int v, int R, double *F, double *part);
+hipError_t launch_scalar(hipStream_t s, int R, int nbf, int stage, int mode, double dt, const DevPulse *pulses,
+                         DevState *st, const double *part, double *sc, double *c0, double *acc0, double *xs0,
+                         double *out, double *normref, double *s0);
+hipError_t launch_epilogue(hipStream_t s, int prec, int R, int o, int v, int nslab, int stage, int mode,
+                           int use_field, double dt, const double *D, const float *P, const double *F,
+                           const double *sc, const double *Xin, double *c, double *acc, double *xs64, float *x32,
+                           __hip_bfloat16 *xhi, __hip_bfloat16 *xlo, double *s_out);
+hipError_t launch_kick(hipStream_t s, int R, int ov, const DevPulse *pulses, const double *F, const double *sc,
+                       double *c, double *c0);
+hipError_t launch_set_state(hipStream_t s, DevState *st, long long step0, double *trace, double *norms);
+
+// Exchange: K partials P[split][slice][o][v] = scale * sum_{Q in split} B_oo^Q X_slice B_vv^Q.
+struct ExchangeVariant {
+  int precision;  // RTTDA_PREC_*
+  int o16;        // padded occupied count handled (o <= o16)
+  int ks;         // slices per workgroup
+  int nt;         // virtual columns per workgroup
+  const char *name;
+  hipError_t (*launch)(hipStream_t s, const void *Boo, const void *Bvv, const void *X, const void *Xlo, int o,
+                       int v, int nq, int ns, int nsplit, float scale, float *P);
+  size_t lds_bytes;
+  hipError_t (*prepare)();  // one-time kernel attributes (dynamic LDS size); call outside graph capture
+};
+
+}  // namespace rttda

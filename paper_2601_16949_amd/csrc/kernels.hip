@@ -1,0 +1,574 @@
+// Bandwidth- and latency-bound kernels of the RT-TDA step on gfx950:
+// dipole blocks, Coulomb GEMV pair, FP64 field/trace, stage scalars, RK4 epilogue, kick.
+#include "common.h"
+
+namespace rttda {
+
+namespace {
+
+constexpr double SQRT2 = 1.4142135623730951;
+constexpr double FWHM_TO_SIGMA = 2.35482;
+
+__device__ __forceinline__ float load_b(const float *p, size_t i) { return p[i]; }
+__device__ __forceinline__ float load_b(const __hip_bfloat16 *p, size_t i) { return __bfloat162float(p[i]); }
+
+// Field of one pulse at time t (eqs. continuous wave, transform_limited, chirped_pulse).
+// Delta pulses act as a kick at t = 0 and contribute no continuous field.
+__device__ double pulse_field(const DevPulse &p, double t) {
+  if (p.kind == RTTDA_PULSE_CW) return p.e0 * sin(p.omega * t + p.phase);
+  if (p.kind == RTTDA_PULSE_GAUSS || p.kind == RTTDA_PULSE_CHIRP) {
+    const double s = p.fwhm / FWHM_TO_SIGMA;
+    const double tau = t - p.t0;
+    const double env = exp(-tau * tau / (2.0 * s * s));
+    const double arg = (p.kind == RTTDA_PULSE_GAUSS) ? p.omega * tau + p.phase
+                                                      : (p.omega + 0.5 * p.beta * tau) * tau + p.phase;
+    return p.e0 * env * sin(arg);
+  }
+  return 0.0;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
+// ------------------------------------------------------------------------------------------------
+// mu_d = sum_k d_k mu_k, split into the oo, ov and vv blocks, one copy per right-hand side.
+// ------------------------------------------------------------------------------------------------
+__global__ void k_mu_blocks(const double *__restrict__ mu, const DevPulse *__restrict__ pulses, int o, int v,
+                            int R, double *__restrict__ moo, double *__restrict__ mov, double *__restrict__ mvv) {
+  const long long n = o + v, nn = n * n, total = (long long)R * nn;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int r = (int)(e / nn);
+    const long long pq = e - r * nn;
+    const int p = (int)(pq / n), q = (int)(pq - p * n);
+    const double *d = pulses[r].dir;
+    const double m = d[0] * mu[pq] + d[1] * mu[nn + pq] + d[2] * mu[2 * nn + pq];
+    if (p < o && q < o)
+      moo[(size_t)r * o * o + (size_t)p * o + q] = m;
+    else if (p < o)
+      mov[(size_t)r * o * v + (size_t)p * v + (q - o)] = m;
+    else if (q >= o)
+      mvv[(size_t)r * v * v + (size_t)(p - o) * v + (q - o)] = m;
+  }
+}
+
+// D_ia = e_a - e_i (diagonal of A, eq. A_matrix_element2).
+__global__ void k_gaps(const double *__restrict__ e_occ, const double *__restrict__ e_virt, int o, int v,
+                       double *__restrict__ D) {
+  const long long total = (long long)o * v;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(e / v), a = (int)(e - (long long)i * v);
+    D[e] = e_virt[a] - e_occ[i];
+  }
+}
+
+__global__ void k_to_f32(const double *__restrict__ c, long long n, float *__restrict__ x) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
+    x[e] = (float)c[e];
+}
+
+__device__ __forceinline__ void split_bf16(double x, __hip_bfloat16 &hi, __hip_bfloat16 &lo) {
+  hi = __float2bfloat16((float)x);
+  lo = __float2bfloat16((float)(x - (double)__bfloat162float(hi)));
+}
+
+__global__ void k_to_bf16x2(const double *__restrict__ c, long long n, float *__restrict__ x,
+                            __hip_bfloat16 *__restrict__ hi, __hip_bfloat16 *__restrict__ lo) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+    x[e] = (float)c[e];
+    split_bf16(c[e], hi[e], lo[e]);
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Coulomb, first product: d[Q][s] = sum_ia B_ov[Q][ia] X[s][ia]   (B streamed once from HBM)
+// Block = QT rows of B x ST slices; 256 threads stride over ia, then a deterministic block sum.
+// ------------------------------------------------------------------------------------------------
+template <typename TB, int QT, int ST>
+__global__ __launch_bounds__(256) void k_gemv1(const TB *__restrict__ B, const float *__restrict__ X, int nq, int ov,
+                                               int ns, float *__restrict__ dvec) {
+  const int q0 = blockIdx.x * QT, s0 = blockIdx.y * ST;
+  float acc[QT][ST];
+#pragma unroll
+  for (int a = 0; a < QT; ++a)
+#pragma unroll
+    for (int b = 0; b < ST; ++b) acc[a][b] = 0.f;
+  for (int e = threadIdx.x; e < ov; e += 256) {
+    float bq[QT], xs[ST];
+#pragma unroll
+    for (int a = 0; a < QT; ++a) bq[a] = (q0 + a < nq) ? load_b(B, (size_t)(q0 + a) * ov + e) : 0.f;
+#pragma unroll
+    for (int b = 0; b < ST; ++b) xs[b] = (s0 + b < ns) ? X[(size_t)(s0 + b) * ov + e] : 0.f;
+#pragma unroll
+    for (int a = 0; a < QT; ++a)
+#pragma unroll
+      for (int b = 0; b < ST; ++b) acc[a][b] += bq[a] * xs[b];
+  }
+  __shared__ float red[4][QT * ST];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int a = 0; a < QT; ++a)
+#pragma unroll
+    for (int b = 0; b < ST; ++b) {
+      const float t = wave_sum(acc[a][b]);
+      if (lane == 0) red[wave][a * ST + b] = t;
+    }
+  __syncthreads();
+  for (int k = threadIdx.x; k < QT * ST; k += 256) {
+    const int a = k / ST, b = k % ST;
+    if (q0 + a < nq && s0 + b < ns)
+      dvec[(size_t)(q0 + a) * ns + s0 + b] = (red[0][k] + red[1][k]) + (red[2][k] + red[3][k]);
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Coulomb, second product: P[split][s][ia] = 2 sum_{Q in split} B_ov[Q][ia] d[Q][s]
+// One thread per ia (coalesced along ia), d staged in LDS.
+// ------------------------------------------------------------------------------------------------
+template <typename TB, int ST>
+__global__ __launch_bounds__(256) void k_gemv2(const TB *__restrict__ B, const float *__restrict__ dvec, int nq,
+                                               int ov, int ns, int nsplit, float *__restrict__ P) {
+  constexpr int QCH = 64;
+  __shared__ float dsh[QCH][ST];
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  const int s0 = blockIdx.y * ST, sp = blockIdx.z;
+  const int qa = (int)((long long)sp * nq / nsplit), qb = (int)((long long)(sp + 1) * nq / nsplit);
+  float acc[ST];
+#pragma unroll
+  for (int b = 0; b < ST; ++b) acc[b] = 0.f;
+  for (int qc = qa; qc < qb; qc += QCH) {
+    const int nqc = min(QCH, qb - qc);
+    __syncthreads();
+    for (int k = threadIdx.x; k < QCH * ST; k += 256) {
+      const int qq = k / ST, b = k % ST;
+      dsh[qq][b] = (qq < nqc && s0 + b < ns) ? dvec[(size_t)(qc + qq) * ns + s0 + b] : 0.f;
+    }
+    __syncthreads();
+    if (e < ov) {
+      for (int qq = 0; qq < nqc; ++qq) {
+        const float bq = load_b(B, (size_t)(qc + qq) * ov + e);
+#pragma unroll
+        for (int b = 0; b < ST; ++b) acc[b] += bq * dsh[qq][b];
+      }
+    }
+  }
+  if (e < ov) {
+#pragma unroll
+    for (int b = 0; b < ST; ++b)
+      if (s0 + b < ns) P[((size_t)sp * ns + s0 + b) * ov + e] = 2.f * acc[b];
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Field product (FP64), eqs. sc2-sc5 in factorised form, both planes of one RHS per block:
+//   F_p = X_p mu_vv - mu_oo X_p + sqrt2 mu_ov c0_p
+// plus per-block partial sums g_p = sqrt2 <mu_ov, X_p>, <X, F> and |X|^2.
+// Tile FT_I x FT_A = 16 x 64; 256 threads, 4 columns x 2 planes per thread.
+// ------------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_field(const double *__restrict__ X, const double *__restrict__ X0,
+                                               const double *__restrict__ moo, const double *__restrict__ mov,
+                                               const double *__restrict__ mvv, int o, int v,
+                                               double *__restrict__ F, double *__restrict__ part) {
+  __shared__ double sh[2 * 32 * 65 + 16 * 33];
+  const int at = blockIdx.x, it = blockIdx.y, r = blockIdx.z;
+  const int nbf = gridDim.x * gridDim.y, blk = it * gridDim.x + at;
+  const int i0 = it * FT_I, a0 = at * FT_A;
+  const int tid = threadIdx.x, ti = tid >> 4, ta = (tid & 15) * 4;
+  const size_t ov = (size_t)o * v;
+  const double *Xr = X + (size_t)r * 2 * ov;
+  const double *moo_r = moo + (size_t)r * o * o;
+  const double *mov_r = mov + (size_t)r * ov;
+  const double *mvv_r = mvv + (size_t)r * v * v;
+  double acc[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+
+  // X_p mu_vv
+  {
+    double(*Xs)[16][33] = reinterpret_cast<double(*)[16][33]>(sh);        // [2][16][33]
+    double(*Ms)[65] = reinterpret_cast<double(*)[65]>(sh + 2 * 16 * 33);  // [32][65]
+    for (int b0 = 0; b0 < v; b0 += 32) {
+      __syncthreads();
+      for (int k = tid; k < 2 * 16 * 32; k += 256) {
+        const int p = k >> 9, rr = (k >> 5) & 15, bb = k & 31, i = i0 + rr, b = b0 + bb;
+        Xs[p][rr][bb] = (i < o && b < v) ? Xr[p * ov + (size_t)i * v + b] : 0.0;
+      }
+      for (int k = tid; k < 32 * 64; k += 256) {
+        const int bb = k >> 6, aa = k & 63, b = b0 + bb, a = a0 + aa;
+        Ms[bb][aa] = (b < v && a < v) ? mvv_r[(size_t)b * v + a] : 0.0;
+      }
+      __syncthreads();
+#pragma unroll 8
+      for (int bb = 0; bb < 32; ++bb) {
+        const double x0 = Xs[0][ti][bb], x1 = Xs[1][ti][bb];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const double m = Ms[bb][ta + k];
+          acc[0][k] += x0 * m;
+          acc[1][k] += x1 * m;
+        }
+      }
+    }
+  }
+  // - mu_oo X_p
+  {
+    double(*Os)[33] = reinterpret_cast<double(*)[33]>(sh);                // [16][33]
+    double(*XJ)[32][65] = reinterpret_cast<double(*)[32][65]>(sh + 16 * 33);  // [2][32][65]
+    for (int j0 = 0; j0 < o; j0 += 32) {
+      __syncthreads();
+      for (int k = tid; k < 16 * 32; k += 256) {
+        const int rr = k >> 5, jj = k & 31, i = i0 + rr, j = j0 + jj;
+        Os[rr][jj] = (i < o && j < o) ? moo_r[(size_t)i * o + j] : 0.0;
+      }
+      for (int k = tid; k < 2 * 32 * 64; k += 256) {
+        const int p = k >> 11, jj = (k >> 6) & 31, aa = k & 63, j = j0 + jj, a = a0 + aa;
+        XJ[p][jj][aa] = (j < o && a < v) ? Xr[p * ov + (size_t)j * v + a] : 0.0;
+      }
+      __syncthreads();
+#pragma unroll 8
+      for (int jj = 0; jj < 32; ++jj) {
+        const double m = Os[ti][jj];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          acc[0][k] -= m * XJ[0][jj][ta + k];
+          acc[1][k] -= m * XJ[1][jj][ta + k];
+        }
+      }
+    }
+  }
+  // + sqrt2 mu_ov c0, outputs and partial sums
+  const double c0r = X0[2 * r], c0i = X0[2 * r + 1];
+  const int i = i0 + ti;
+  double pg0 = 0, pg1 = 0, ptr = 0, pnr = 0;
+  double *Fr = F + (size_t)r * 2 * ov;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int a = a0 + ta + k;
+    if (i < o && a < v) {
+      const size_t ia = (size_t)i * v + a;
+      const double m = mov_r[ia];
+      const double x0 = Xr[ia], x1 = Xr[ov + ia];
+      const double f0 = acc[0][k] + SQRT2 * m * c0r;
+      const double f1 = acc[1][k] + SQRT2 * m * c0i;
+      Fr[ia] = f0;
+      Fr[ov + ia] = f1;
+      pg0 += SQRT2 * m * x0;
+      pg1 += SQRT2 * m * x1;
+      ptr += x0 * f0 + x1 * f1;
+      pnr += x0 * x0 + x1 * x1;
+    }
+  }
+  __syncthreads();
+  double *red = sh;  // [4 waves][4]
+  pg0 = wave_sum(pg0);
+  pg1 = wave_sum(pg1);
+  ptr = wave_sum(ptr);
+  pnr = wave_sum(pnr);
+  const int lane = tid & 63, wave = tid >> 6;
+  if (lane == 0) {
+    red[wave * 4 + 0] = pg0;
+    red[wave * 4 + 1] = pg1;
+    red[wave * 4 + 2] = ptr;
+    red[wave * 4 + 3] = pnr;
+  }
+  __syncthreads();
+  if (tid < 4) {
+    part[((size_t)r * nbf + blk) * PART_STRIDE + tid] = (red[tid] + red[4 + tid]) + (red[8 + tid] + red[12 + tid]);
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Stage scalars (one block): pulse fields E_r(t_stage), the ground-row product g, the trace and
+// norm samples with the norm guard, and the RK4 update of c0 (dc0/dt = -i(-E g) = i E g).
+// ------------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_scalar(int R, int nbf, int stage, int mode, double dt,
+                                                const DevPulse *__restrict__ pulses, DevState *__restrict__ st,
+                                                const double *__restrict__ part, double *__restrict__ sc,
+                                                double *__restrict__ c0, double *__restrict__ acc0,
+                                                double *__restrict__ xs0, double *__restrict__ out,
+                                                double *__restrict__ normref, double *__restrict__ s0) {
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  const long long step = st->step;
+  const long long k = step - st->step0;
+  double *trace = st->trace;
+  double *norms = st->norms;
+  const double node = (stage == 0) ? 0.0 : (stage == 3 ? 1.0 : 0.5);
+  for (int r = threadIdx.x; r < R; r += blockDim.x) {
+    double g0 = 0.0, g1 = 0.0, tr = 0.0, nr = 0.0;
+    for (int b = 0; b < nbf; ++b) {
+      const double *pp = part + ((size_t)r * nbf + b) * PART_STRIDE;
+      g0 += pp[0];
+      g1 += pp[1];
+      tr += pp[2];
+      nr += pp[3];
+    }
+    double E = 0.0;
+    if (mode & SM_EFIELD)
+      E = pulse_field(pulses[r], ((double)step + node) * dt);
+    else if (mode & SM_KEEP_E)
+      E = sc[r * SC_STRIDE + SC_E];
+    sc[r * SC_STRIDE + SC_GRE] = g0;
+    sc[r * SC_STRIDE + SC_GIM] = g1;
+    sc[r * SC_STRIDE + SC_E] = E;
+    // X0 of this stage (c0 at stage 0, else the stage value)
+    const double x0r = (stage == 0) ? c0[2 * r] : xs0[2 * r];
+    const double x0i = (stage == 0) ? c0[2 * r + 1] : xs0[2 * r + 1];
+    if (mode & (SM_TRACE | SM_OUT)) {
+      const double t = tr + (x0r * g0 + x0i * g1);
+      const double n2 = nr + (x0r * x0r + x0i * x0i);
+      if (mode & SM_OUT) out[r] = t;
+      if (mode & SM_TRACE) {
+        if (trace) trace[k * R + r] = t;
+        if (norms) norms[k * R + r] = n2;
+        if (k == 0) {
+          normref[r] = n2;
+        } else if (!(n2 <= 2.0 * normref[r])) {  // also catches NaN
+          bad = 1;
+        }
+      }
+    }
+    if (mode & SM_SIGMA0) {
+      s0[2 * r] = -E * g0;
+      s0[2 * r + 1] = -E * g1;
+    }
+    if (mode & SM_C0) {
+      // k0 = -i * (H X)_0 = -i * (-E g) = i E g
+      const double kr = -E * g1, ki = E * g0;
+      const double cr = c0[2 * r], ci = c0[2 * r + 1];
+      if (stage == 0) {
+        acc0[2 * r] = cr + dt / 6.0 * kr;
+        acc0[2 * r + 1] = ci + dt / 6.0 * ki;
+        xs0[2 * r] = cr + 0.5 * dt * kr;
+        xs0[2 * r + 1] = ci + 0.5 * dt * ki;
+      } else if (stage == 1) {
+        acc0[2 * r] += dt / 3.0 * kr;
+        acc0[2 * r + 1] += dt / 3.0 * ki;
+        xs0[2 * r] = cr + 0.5 * dt * kr;
+        xs0[2 * r + 1] = ci + 0.5 * dt * ki;
+      } else if (stage == 2) {
+        acc0[2 * r] += dt / 3.0 * kr;
+        acc0[2 * r + 1] += dt / 3.0 * ki;
+        xs0[2 * r] = cr + dt * kr;
+        xs0[2 * r + 1] = ci + dt * ki;
+      } else {
+        c0[2 * r] = acc0[2 * r] + dt / 6.0 * kr;
+        c0[2 * r + 1] = acc0[2 * r + 1] + dt / 6.0 * ki;
+      }
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (bad && st->bad_step < 0) st->bad_step = step;
+    if (mode & SM_INC) st->step = step + 1;
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+// RK4 epilogue (FP64): sigma = D X + sum of Coulomb/exchange partials - E F;  k = -i sigma;
+// stage accumulation into acc, next stage input (FP64 + FP32 or BF16 hi/lo copy), c at stage 4.
+// One thread per (r, i, a), both planes.
+// ------------------------------------------------------------------------------------------------
+template <int PREC>
+__global__ __launch_bounds__(256) void k_epilogue(int R, int o, int v, int nslab, int stage, int mode, int use_field,
+                                                  double dt, const double *__restrict__ D,
+                                                  const float *__restrict__ P, const double *__restrict__ F,
+                                                  const double *__restrict__ sc, const double *__restrict__ Xin,
+                                                  double *__restrict__ c, double *__restrict__ acc,
+                                                  double *__restrict__ xs64, float *__restrict__ x32,
+                                                  __hip_bfloat16 *__restrict__ xhi, __hip_bfloat16 *__restrict__ xlo,
+                                                  double *__restrict__ s_out) {
+  const size_t ov = (size_t)o * v;
+  const size_t total = (size_t)R * ov;
+  const size_t slab = 2 * (size_t)R * ov;  // floats per partial slab
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const size_t r = e / ov, ia = e - r * ov;
+    const size_t i0 = r * 2 * ov + ia, i1 = i0 + ov;
+    const double x0 = Xin[i0], x1 = Xin[i1];
+    const double d = D[ia];
+    double p0 = 0.0, p1 = 0.0;
+    for (int sl = 0; sl < nslab; ++sl) {
+      p0 += (double)P[sl * slab + i0];
+      p1 += (double)P[sl * slab + i1];
+    }
+    double s0v = d * x0 + p0, s1v = d * x1 + p1;
+    if (use_field) {
+      const double E = sc[r * SC_STRIDE + SC_E];
+      s0v -= E * F[i0];
+      s1v -= E * F[i1];
+    }
+    if (mode == EP_SIGMA) {
+      s_out[i0] = s0v;
+      s_out[i1] = s1v;
+      continue;
+    }
+    // k = -i sigma: Re k = Im sigma, Im k = -Re sigma
+    const double k0 = s1v, k1 = -s0v;
+    double n0, n1;
+    if (stage == 0) {
+      acc[i0] = x0 + dt / 6.0 * k0;
+      acc[i1] = x1 + dt / 6.0 * k1;
+      n0 = x0 + 0.5 * dt * k0;
+      n1 = x1 + 0.5 * dt * k1;
+    } else if (stage == 3) {
+      n0 = acc[i0] + dt / 6.0 * k0;
+      n1 = acc[i1] + dt / 6.0 * k1;
+      c[i0] = n0;
+      c[i1] = n1;
+    } else {
+      acc[i0] += dt / 3.0 * k0;
+      acc[i1] += dt / 3.0 * k1;
+      const double h = (stage == 1) ? 0.5 * dt : dt;
+      n0 = c[i0] + h * k0;
+      n1 = c[i1] + h * k1;
+    }
+    if (stage != 3) {
+      xs64[i0] = n0;
+      xs64[i1] = n1;
+    }
+    x32[i0] = (float)n0;
+    x32[i1] = (float)n1;
+    if (PREC == 1) {
+      split_bf16(n0, xhi[i0], xlo[i0]);
+      split_bf16(n1, xhi[i1], xlo[i1]);
+    }
+  }
+}
+
+// First-order delta kick X <- X + i kappa M X for RHS with a delta pulse.
+__global__ void k_kick(int R, int ov, const DevPulse *__restrict__ pulses, const double *__restrict__ F,
+                       const double *__restrict__ sc, double *__restrict__ c, double *__restrict__ c0) {
+  const size_t total = (size_t)R * ov;
+  const size_t gid = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  for (size_t e = gid; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const size_t r = e / ov, ia = e - r * ov;
+    if (pulses[r].kind != RTTDA_PULSE_DELTA) continue;
+    const double kap = pulses[r].e0;
+    const size_t i0 = r * 2 * ov + ia, i1 = i0 + ov;
+    const double f0 = F[i0], f1 = F[i1];
+    c[i0] -= kap * f1;
+    c[i1] += kap * f0;
+  }
+  if (gid < (size_t)R && pulses[gid].kind == RTTDA_PULSE_DELTA) {
+    const double kap = pulses[gid].e0;
+    const double g0 = sc[gid * SC_STRIDE + SC_GRE], g1 = sc[gid * SC_STRIDE + SC_GIM];
+    c0[2 * gid] -= kap * g1;
+    c0[2 * gid + 1] += kap * g0;
+  }
+}
+
+__global__ void k_set_state(DevState *st, long long step0, double *trace, double *norms) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    st->step = step0;
+    st->step0 = step0;
+    st->bad_step = -1;
+    st->trace = trace;
+    st->norms = norms;
+  }
+}
+
+inline int grid_for(long long n, int block = 256, int cap = 8192) {
+  long long g = (n + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+}  // namespace
+
+hipError_t launch_mu_blocks(hipStream_t s, const double *mu, const DevPulse *pulses, int o, int v, int R,
+                            double *moo, double *mov, double *mvv) {
+  const long long n = (long long)(o + v) * (o + v) * R;
+  hipLaunchKernelGGL(k_mu_blocks, dim3(grid_for(n)), dim3(256), 0, s, mu, pulses, o, v, R, moo, mov, mvv);
+  return hipGetLastError();
+}
+
+hipError_t launch_gaps(hipStream_t s, const double *e_occ, const double *e_virt, int o, int v, double *D) {
+  hipLaunchKernelGGL(k_gaps, dim3(grid_for((long long)o * v)), dim3(256), 0, s, e_occ, e_virt, o, v, D);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_f32(hipStream_t s, const double *c, long long n, float *x32) {
+  hipLaunchKernelGGL(k_to_f32, dim3(grid_for(n)), dim3(256), 0, s, c, n, x32);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_bf16x2(hipStream_t s, const double *c, long long n, float *x32, __hip_bfloat16 *hi,
+                            __hip_bfloat16 *lo) {
+  hipLaunchKernelGGL(k_to_bf16x2, dim3(grid_for(n)), dim3(256), 0, s, c, n, x32, hi, lo);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemv1(hipStream_t s, int b_dtype, const void *B, const float *X, int nq, int ov, int ns,
+                        float *dvec) {
+  constexpr int QT = 4, ST = 8;
+  dim3 grid((nq + QT - 1) / QT, (ns + ST - 1) / ST);
+  if (b_dtype == RTTDA_BF16)
+    hipLaunchKernelGGL((k_gemv1<__hip_bfloat16, QT, ST>), grid, dim3(256), 0, s,
+                       static_cast<const __hip_bfloat16 *>(B), X, nq, ov, ns, dvec);
+  else
+    hipLaunchKernelGGL((k_gemv1<float, QT, ST>), grid, dim3(256), 0, s, static_cast<const float *>(B), X, nq, ov,
+                       ns, dvec);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemv2(hipStream_t s, int b_dtype, const void *B, const float *dvec, int nq, int ov, int ns,
+                        int nsplit, float *P) {
+  constexpr int ST = 8;
+  dim3 grid((ov + 255) / 256, (ns + ST - 1) / ST, nsplit);
+  if (b_dtype == RTTDA_BF16)
+    hipLaunchKernelGGL((k_gemv2<__hip_bfloat16, ST>), grid, dim3(256), 0, s, static_cast<const __hip_bfloat16 *>(B),
+                       dvec, nq, ov, ns, nsplit, P);
+  else
+    hipLaunchKernelGGL((k_gemv2<float, ST>), grid, dim3(256), 0, s, static_cast<const float *>(B), dvec, nq, ov, ns,
+                       nsplit, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_field(hipStream_t s, const double *X, const double *X0, const double *moo, const double *mov,
+                        const double *mvv, int o, int v, int R, double *F, double *part) {
+  dim3 grid(field_blocks_a(v), field_blocks_i(o), R);
+  hipLaunchKernelGGL(k_field, grid, dim3(256), 0, s, X, X0, moo, mov, mvv, o, v, F, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_scalar(hipStream_t s, int R, int nbf, int stage, int mode, double dt, const DevPulse *pulses,
+                         DevState *st, const double *part, double *sc, double *c0, double *acc0, double *xs0,
+                         double *out, double *normref, double *s0) {
+  hipLaunchKernelGGL(k_scalar, dim3(1), dim3(256), 0, s, R, nbf, stage, mode, dt, pulses, st, part, sc, c0, acc0,
+                     xs0, out, normref, s0);
+  return hipGetLastError();
+}
+
+hipError_t launch_epilogue(hipStream_t s, int prec, int R, int o, int v, int nslab, int stage, int mode,
+                           int use_field, double dt, const double *D, const float *P, const double *F,
+                           const double *sc, const double *Xin, double *c, double *acc, double *xs64, float *x32,
+                           __hip_bfloat16 *xhi, __hip_bfloat16 *xlo, double *s_out) {
+  const long long n = (long long)R * o * v;
+  dim3 grid(grid_for(n, 256, 65536));
+  if (prec == RTTDA_PREC_MIXED_BF16)
+    hipLaunchKernelGGL((k_epilogue<1>), grid, dim3(256), 0, s, R, o, v, nslab, stage, mode, use_field, dt, D, P, F,
+                       sc, Xin, c, acc, xs64, x32, xhi, xlo, s_out);
+  else
+    hipLaunchKernelGGL((k_epilogue<0>), grid, dim3(256), 0, s, R, o, v, nslab, stage, mode, use_field, dt, D, P, F,
+                       sc, Xin, c, acc, xs64, x32, xhi, xlo, s_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_kick(hipStream_t s, int R, int ov, const DevPulse *pulses, const double *F, const double *sc,
+                       double *c, double *c0) {
+  const long long n = (long long)R * ov;
+  hipLaunchKernelGGL(k_kick, dim3(grid_for(n)), dim3(256), 0, s, R, ov, pulses, F, sc, c, c0);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_state(hipStream_t s, DevState *st, long long step0, double *trace, double *norms) {
+  hipLaunchKernelGGL(k_set_state, dim3(1), dim3(64), 0, s, st, step0, trace, norms);
+  return hipGetLastError();
+}
+
+}  // namespace rttda

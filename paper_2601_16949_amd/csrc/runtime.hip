@@ -1,0 +1,698 @@
+// Host runtime of the RT-TDA library: argument validation, workspace layout, the RK4 step
+// sequence (direct launches or replay of a captured HIP graph) and the C ABI.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace rttda {
+int exchange_f32_variant_count();
+const ExchangeVariant *exchange_f32_variant(int k);
+int exchange_bf16_variant_count();
+const ExchangeVariant *exchange_bf16_variant(int k);
+}  // namespace rttda
+
+using namespace rttda;
+
+static_assert(sizeof(DevPulse) == sizeof(rttda_pulse), "pulse layout");
+static_assert(offsetof(DevPulse, dir) == offsetof(rttda_pulse, dir), "pulse layout");
+
+namespace {
+
+thread_local std::string g_last_error;
+
+rttda_status fail(rttda_status st, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+rttda_status fail(rttda_status st, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                             \
+  do {                                                                                            \
+    hipError_t e_ = (expr);                                                                       \
+    if (e_ != hipSuccess) return fail(RTTDA_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_));    \
+  } while (0)
+
+constexpr int MAX_RHS = 4096;
+constexpr int SJ_MAX = 8;    // Coulomb second-product Q splits
+constexpr int SK_MAX = 96;   // exchange Q splits
+constexpr size_t ALIGN = 256;
+
+inline size_t up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+inline bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+struct Layout {
+  size_t D, moo, mov, mvv, xs64, xs0, acc, acc0, F, part, sc, x32, xhi, xlo, dvec, P, pulses, state, normref;
+  size_t total;
+  int nbf;
+  int sk_max, sj_max;
+};
+
+Layout make_layout(int o, int v, int nq, int R, int prec) {
+  Layout L{};
+  const size_t ov = (size_t)o * v;
+  const size_t ns = 2 * (size_t)R;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = off;
+    off += up(bytes > 0 ? bytes : 1);
+    return at;
+  };
+  L.nbf = field_blocks_a(v) * field_blocks_i(o);
+  L.sj_max = nq > 0 ? std::min(SJ_MAX, nq) : 0;
+  L.sk_max = nq > 0 ? std::min(SK_MAX, nq) : 0;
+  L.D = take(ov * 8);
+  L.moo = take((size_t)R * o * o * 8);
+  L.mov = take((size_t)R * ov * 8);
+  L.mvv = take((size_t)R * v * v * 8);
+  L.xs64 = take(ns * ov * 8);
+  L.xs0 = take(ns * 8);
+  L.acc = take(ns * ov * 8);
+  L.acc0 = take(ns * 8);
+  L.F = take(ns * ov * 8);
+  L.part = take((size_t)R * L.nbf * PART_STRIDE * 8);
+  L.sc = take((size_t)R * SC_STRIDE * 8);
+  L.x32 = take(ns * ov * 4);  // FP32 stage copy (Coulomb input; exchange input in FP32 mode)
+  L.xhi = take(prec == RTTDA_PREC_MIXED_BF16 ? ns * ov * 2 : 0);
+  L.xlo = take(prec == RTTDA_PREC_MIXED_BF16 ? ns * ov * 2 : 0);
+  L.dvec = take((size_t)std::max(nq, 1) * ns * 4);
+  L.P = take((size_t)(L.sj_max + L.sk_max) * ns * ov * 4);
+  L.pulses = take((size_t)R * sizeof(DevPulse));
+  L.state = take(sizeof(DevState));
+  L.normref = take((size_t)R * 8);
+  L.total = off;
+  return L;
+}
+
+struct Profiler {
+  static constexpr int CLASSES = 4;
+  static constexpr size_t CAP = 2048;  // event pairs kept per class before folding
+  bool on = false;
+  std::vector<hipEvent_t> start[CLASSES], stop[CLASSES];
+  size_t used[CLASSES] = {0, 0, 0, 0};
+  int64_t launches[CLASSES] = {0, 0, 0, 0};
+  double ms[CLASSES] = {0, 0, 0, 0};
+
+  hipError_t fold(int k) {
+    if (used[k] == 0) return hipSuccess;
+    hipError_t e = hipEventSynchronize(stop[k][used[k] - 1]);
+    if (e != hipSuccess) return e;
+    for (size_t i = 0; i < used[k]; ++i) {
+      float t = 0.f;
+      e = hipEventElapsedTime(&t, start[k][i], stop[k][i]);
+      if (e != hipSuccess) return e;
+      ms[k] += t;
+    }
+    used[k] = 0;
+    return hipSuccess;
+  }
+  hipError_t begin(int k, hipStream_t s) {
+    if (used[k] == CAP) {
+      hipError_t e = fold(k);
+      if (e != hipSuccess) return e;
+    }
+    if (start[k].size() <= used[k]) {
+      hipEvent_t a, b;
+      hipError_t e = hipEventCreate(&a);
+      if (e == hipSuccess) e = hipEventCreate(&b);
+      if (e != hipSuccess) return e;
+      start[k].push_back(a);
+      stop[k].push_back(b);
+    }
+    return hipEventRecord(start[k][used[k]], s);
+  }
+  hipError_t end(int k, hipStream_t s) {
+    hipError_t e = hipEventRecord(stop[k][used[k]], s);
+    ++used[k];
+    ++launches[k];
+    return e;
+  }
+  void reset() {
+    for (int k = 0; k < CLASSES; ++k) {
+      used[k] = 0;
+      launches[k] = 0;
+      ms[k] = 0;
+    }
+  }
+  void destroy() {
+    for (int k = 0; k < CLASSES; ++k) {
+      for (auto e : start[k]) (void)hipEventDestroy(e);
+      for (auto e : stop[k]) (void)hipEventDestroy(e);
+      start[k].clear();
+      stop[k].clear();
+    }
+  }
+};
+
+enum { PC_EXCHANGE = 0, PC_COULOMB = 1, PC_FIELD = 2, PC_EPILOGUE = 3 };
+
+struct GraphEntry {
+  bool valid = false;
+  // key
+  int nrhs = 0, steps = 0, mode = 0;
+  double dt = 0;
+  const void *c0 = nullptr, *c = nullptr;
+  bool trace = false, norms = false;
+  hipGraphExec_t exec = nullptr;
+};
+
+const ExchangeVariant *variant_of(int prec, int k) {
+  if (prec == RTTDA_PREC_FP32) return (k >= 0 && k < exchange_f32_variant_count()) ? exchange_f32_variant(k) : nullptr;
+  return (k >= 0 && k < exchange_bf16_variant_count()) ? exchange_bf16_variant(k) : nullptr;
+}
+int variant_count(int prec) {
+  return prec == RTTDA_PREC_FP32 ? exchange_f32_variant_count() : exchange_bf16_variant_count();
+}
+
+}  // namespace
+
+struct rttda_ctx {
+  rttda_desc d{};
+  hipStream_t stream = nullptr;
+  int o = 0, v = 0, nq = 0, R = 0, prec = 0;
+  size_t ov = 0;
+  Layout L{};
+  char *ws = nullptr;
+  // launch configuration
+  int xvar = -1;  // 0-based exchange variant
+  int sk = 0, sj = 0;
+  int use_graph = 1, steps_per_graph = 8;
+  // host staging for pulses (pinned)
+  DevPulse *h_pulses = nullptr;
+  hipEvent_t upload_ev = nullptr;
+  GraphEntry graph;
+  Profiler prof;
+
+  template <typename T>
+  T *at(size_t off) const {
+    return reinterpret_cast<T *>(ws + off);
+  }
+  double *D() const { return at<double>(L.D); }
+  double *moo() const { return at<double>(L.moo); }
+  double *mov() const { return at<double>(L.mov); }
+  double *mvv() const { return at<double>(L.mvv); }
+  double *xs64() const { return at<double>(L.xs64); }
+  double *xs0() const { return at<double>(L.xs0); }
+  double *acc() const { return at<double>(L.acc); }
+  double *acc0() const { return at<double>(L.acc0); }
+  double *F() const { return at<double>(L.F); }
+  double *part() const { return at<double>(L.part); }
+  double *sc() const { return at<double>(L.sc); }
+  float *x32() const { return at<float>(L.x32); }
+  __hip_bfloat16 *xhi() const { return at<__hip_bfloat16>(L.xhi); }
+  __hip_bfloat16 *xlo() const { return at<__hip_bfloat16>(L.xlo); }
+  float *dvec() const { return at<float>(L.dvec); }
+  float *P() const { return at<float>(L.P); }
+  DevPulse *pulses() const { return at<DevPulse>(L.pulses); }
+  DevState *state() const { return at<DevState>(L.state); }
+  double *normref() const { return at<double>(L.normref); }
+};
+
+namespace {
+
+rttda_status validate_desc(const rttda_desc *d, bool need_ptrs) {
+  if (!d) return fail(RTTDA_E_INVAL, "desc is NULL");
+  if (d->n_occ < 1 || d->n_virt < 1 || d->n_aux < 0)
+    return fail(RTTDA_E_INVAL, "bad sizes o=%d v=%d n_aux=%d (need o,v >= 1, n_aux >= 0)", d->n_occ, d->n_virt,
+                d->n_aux);
+  if ((long long)d->n_occ * d->n_virt > (1LL << 31) / 8)
+    return fail(RTTDA_E_UNSUPPORTED, "o*v=%lld too large", (long long)d->n_occ * d->n_virt);
+  if (d->max_rhs < 1 || d->max_rhs > MAX_RHS)
+    return fail(RTTDA_E_INVAL, "max_rhs=%d outside 1..%d", d->max_rhs, MAX_RHS);
+  if (d->precision == RTTDA_PREC_FP32) {
+    if (d->b_dtype != RTTDA_F32) return fail(RTTDA_E_INVAL, "PREC_FP32 needs b_dtype RTTDA_F32");
+  } else if (d->precision == RTTDA_PREC_MIXED_BF16) {
+    if (d->b_dtype != RTTDA_BF16) return fail(RTTDA_E_INVAL, "PREC_MIXED_BF16 needs b_dtype RTTDA_BF16");
+  } else {
+    return fail(RTTDA_E_INVAL, "unknown precision %d", d->precision);
+  }
+  if (!std::isfinite(d->cx)) return fail(RTTDA_E_INVAL, "cx not finite");
+  if (need_ptrs) {
+    const void *ptrs[] = {d->e_occ, d->e_virt, d->mu, d->workspace};
+    const char *names[] = {"e_occ", "e_virt", "mu", "workspace"};
+    for (int k = 0; k < 4; ++k) {
+      if (!ptrs[k]) return fail(RTTDA_E_INVAL, "%s is NULL", names[k]);
+      if (!aligned16(ptrs[k])) return fail(RTTDA_E_INVAL, "%s not 16-byte aligned", names[k]);
+    }
+    if ((reinterpret_cast<uintptr_t>(d->workspace) & (ALIGN - 1)) != 0)
+      return fail(RTTDA_E_INVAL, "workspace not 256-byte aligned");
+    if (d->n_aux > 0) {
+      const void *bp[] = {d->b_ov, d->b_oo, d->b_vv};
+      const char *bn[] = {"b_ov", "b_oo", "b_vv"};
+      for (int k = 0; k < 3; ++k) {
+        if (!bp[k]) return fail(RTTDA_E_INVAL, "%s is NULL", bn[k]);
+        if (!aligned16(bp[k])) return fail(RTTDA_E_INVAL, "%s not 16-byte aligned", bn[k]);
+      }
+    }
+  }
+  return RTTDA_OK;
+}
+
+int auto_variant(int prec, int o, int ns, int v) {
+  // smallest padded occupied size that holds o; among those prefer the variant whose tile
+  // wastes the least of the (slices x columns) space, then the larger tile.
+  int best = -1;
+  double best_score = 1e300;
+  const int n = variant_count(prec);
+  int o16_best = 1 << 30;
+  for (int k = 0; k < n; ++k) {
+    const ExchangeVariant *x = variant_of(prec, k);
+    if (x->o16 >= o && x->o16 < o16_best) o16_best = x->o16;
+  }
+  for (int k = 0; k < n; ++k) {
+    const ExchangeVariant *x = variant_of(prec, k);
+    if (x->o16 != o16_best) continue;
+    const double rows = (double)((ns + x->ks - 1) / x->ks) * x->ks;
+    const double cols = (double)((v + x->nt - 1) / x->nt) * x->nt;
+    const double waste = rows * cols / ((double)ns * v);
+    const double score = waste * (1.0 + 8.0 / (x->ks * x->nt));  // mild preference for big tiles
+    if (score < best_score) {
+      best_score = score;
+      best = k;
+    }
+  }
+  return best;
+}
+
+int auto_splits(const ExchangeVariant *x, int ns, int v, int nq, int cap) {
+  const int tiles = ((ns + x->ks - 1) / x->ks) * ((v + x->nt - 1) / x->nt);
+  const int cus = 256;
+  // aim at about two workgroups per CU, at least 4 Q per split
+  int s = (2 * cus + tiles - 1) / tiles;
+  s = std::min(s, std::max(1, nq / 4));
+  s = std::max(1, std::min(s, cap));
+  return s;
+}
+
+rttda_status upload_pulses(rttda_ctx *ctx, const DevPulse *src, int nrhs) {
+  HIP_TRY(hipEventSynchronize(ctx->upload_ev));  // previous upload has left the staging buffer
+  memcpy(ctx->h_pulses, src, sizeof(DevPulse) * nrhs);
+  HIP_TRY(hipMemcpyAsync(ctx->pulses(), ctx->h_pulses, sizeof(DevPulse) * nrhs, hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(hipEventRecord(ctx->upload_ev, ctx->stream));
+  return RTTDA_OK;
+}
+
+rttda_status check_dirs(const double *dir, int nrhs) {
+  for (int r = 0; r < nrhs; ++r) {
+    const double *d = dir + 3 * r;
+    if (!std::isfinite(d[0]) || !std::isfinite(d[1]) || !std::isfinite(d[2]))
+      return fail(RTTDA_E_INVAL, "direction %d not finite", r);
+    const double n2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    if (std::fabs(n2 - 1.0) > 1e-12) return fail(RTTDA_E_INVAL, "direction %d is not a unit vector", r);
+  }
+  return RTTDA_OK;
+}
+
+// Coulomb + exchange partials for the current stage input (x32 or xhi/xlo).
+rttda_status enqueue_two_electron(rttda_ctx *ctx, int nrhs) {
+  if (ctx->nq == 0) return RTTDA_OK;
+  const int ns = 2 * nrhs;
+  const int ov = (int)ctx->ov;
+  hipStream_t s = ctx->stream;
+  const bool pr = ctx->prof.on;
+  if (pr) HIP_TRY(ctx->prof.begin(PC_COULOMB, s));
+  HIP_TRY(launch_gemv1(s, ctx->d.b_dtype, ctx->d.b_ov, ctx->x32(), ctx->nq, ov, ns, ctx->dvec()));
+  HIP_TRY(launch_gemv2(s, ctx->d.b_dtype, ctx->d.b_ov, ctx->dvec(), ctx->nq, ov, ns, ctx->sj, ctx->P()));
+  if (pr) HIP_TRY(ctx->prof.end(PC_COULOMB, s));
+  const ExchangeVariant *x = variant_of(ctx->prec, ctx->xvar);
+  float *Pk = ctx->P() + (size_t)ctx->sj * ns * ctx->ov;
+  const void *X = ctx->prec == RTTDA_PREC_FP32 ? (const void *)ctx->x32() : (const void *)ctx->xhi();
+  const void *Xlo = ctx->prec == RTTDA_PREC_FP32 ? nullptr : (const void *)ctx->xlo();
+  if (pr) HIP_TRY(ctx->prof.begin(PC_EXCHANGE, s));
+  HIP_TRY(x->launch(s, ctx->d.b_oo, ctx->d.b_vv, X, Xlo, ctx->o, ctx->v, ctx->nq, ns, ctx->sk, (float)(-ctx->d.cx),
+                    Pk));
+  if (pr) HIP_TRY(ctx->prof.end(PC_EXCHANGE, s));
+  return RTTDA_OK;
+}
+
+int nslab(const rttda_ctx *ctx) { return ctx->nq > 0 ? ctx->sj + ctx->sk : 0; }
+
+// One RK4 step (4 stages) on the context's stream.
+rttda_status enqueue_step(rttda_ctx *ctx, int nrhs, double dt, bool has_field, double *c0, double *c) {
+  hipStream_t s = ctx->stream;
+  const int o = ctx->o, v = ctx->v;
+  for (int stage = 0; stage < 4; ++stage) {
+    double *Xin = stage == 0 ? c : ctx->xs64();
+    double *X0 = stage == 0 ? c0 : ctx->xs0();
+    rttda_status st = enqueue_two_electron(ctx, nrhs);
+    if (st != RTTDA_OK) return st;
+    const bool need_field = stage == 0 || has_field;
+    const bool pr = ctx->prof.on;
+    if (need_field) {
+      if (pr) HIP_TRY(ctx->prof.begin(PC_FIELD, s));
+      HIP_TRY(launch_field(s, Xin, X0, ctx->moo(), ctx->mov(), ctx->mvv(), o, v, nrhs, ctx->F(), ctx->part()));
+      if (pr) HIP_TRY(ctx->prof.end(PC_FIELD, s));
+    }
+    if (pr) HIP_TRY(ctx->prof.begin(PC_EPILOGUE, s));
+    int mode = 0;
+    if (stage == 0) mode |= SM_TRACE;
+    if (has_field) mode |= SM_C0 | SM_EFIELD;
+    if (stage == 3) mode |= SM_INC;
+    HIP_TRY(launch_scalar(s, nrhs, ctx->L.nbf, stage, mode, dt, ctx->pulses(), ctx->state(), ctx->part(), ctx->sc(),
+                          c0, ctx->acc0(), ctx->xs0(), nullptr, ctx->normref(), nullptr));
+    HIP_TRY(launch_epilogue(s, ctx->prec, nrhs, o, v, nslab(ctx), stage, EP_RK4, has_field ? 1 : 0, dt, ctx->D(),
+                            ctx->P(), ctx->F(), ctx->sc(), Xin, c, ctx->acc(), ctx->xs64(), ctx->x32(), ctx->xhi(),
+                            ctx->xlo(), nullptr));
+    if (pr) HIP_TRY(ctx->prof.end(PC_EPILOGUE, s));
+  }
+  return RTTDA_OK;
+}
+
+rttda_status to_stage_copy(rttda_ctx *ctx, const double *c, int nrhs) {
+  const long long n = 2LL * nrhs * (long long)ctx->ov;
+  if (ctx->prec == RTTDA_PREC_FP32)
+    HIP_TRY(launch_to_f32(ctx->stream, c, n, ctx->x32()));
+  else
+    HIP_TRY(launch_to_bf16x2(ctx->stream, c, n, ctx->x32(), ctx->xhi(), ctx->xlo()));
+  return RTTDA_OK;
+}
+
+void drop_graph(rttda_ctx *ctx) {
+  if (ctx->graph.valid && ctx->graph.exec) (void)hipGraphExecDestroy(ctx->graph.exec);
+  ctx->graph = GraphEntry{};
+}
+
+rttda_status check_nrhs(const rttda_ctx *ctx, int nrhs) {
+  if (nrhs < 1 || nrhs > ctx->R) return fail(RTTDA_E_INVAL, "nrhs=%d outside 1..max_rhs=%d", nrhs, ctx->R);
+  return RTTDA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *rttda_last_error(void) { return g_last_error.c_str(); }
+const char *rttda_version(void) { return "rttda-gfx950 0.1"; }
+
+int32_t rttda_exchange_variants(int32_t precision) {
+  if (precision != RTTDA_PREC_FP32 && precision != RTTDA_PREC_MIXED_BF16) return 0;
+  return variant_count(precision);
+}
+
+const char *rttda_exchange_variant_name(int32_t precision, int32_t k) {
+  if (precision != RTTDA_PREC_FP32 && precision != RTTDA_PREC_MIXED_BF16) return "";
+  const ExchangeVariant *x = variant_of(precision, k - 1);
+  return x ? x->name : "";
+}
+
+rttda_status rttda_workspace_bytes(const rttda_desc *desc, size_t *bytes) {
+  rttda_status st = validate_desc(desc, false);
+  if (st != RTTDA_OK) return st;
+  if (!bytes) return fail(RTTDA_E_INVAL, "bytes is NULL");
+  *bytes = make_layout(desc->n_occ, desc->n_virt, desc->n_aux, desc->max_rhs, desc->precision).total;
+  return RTTDA_OK;
+}
+
+rttda_status rttda_create(const rttda_desc *desc, rttda_ctx **out) {
+  if (!out) return fail(RTTDA_E_INVAL, "out is NULL");
+  *out = nullptr;
+  rttda_status st = validate_desc(desc, true);
+  if (st != RTTDA_OK) return st;
+  Layout L = make_layout(desc->n_occ, desc->n_virt, desc->n_aux, desc->max_rhs, desc->precision);
+  if (desc->workspace_bytes < L.total)
+    return fail(RTTDA_E_NOMEM, "workspace has %zu bytes, needs %zu", desc->workspace_bytes, L.total);
+  const int ns_max = 2 * desc->max_rhs;
+  int xv = -1;
+  if (desc->n_aux > 0) {
+    xv = auto_variant(desc->precision, desc->n_occ, ns_max, desc->n_virt);
+    if (xv < 0)
+      return fail(RTTDA_E_UNSUPPORTED, "no exchange kernel for o=%d in precision %d", desc->n_occ, desc->precision);
+  }
+  if (xv >= 0) HIP_TRY(variant_of(desc->precision, xv)->prepare());
+  rttda_ctx *ctx = new rttda_ctx();
+  ctx->d = *desc;
+  ctx->stream = static_cast<hipStream_t>(desc->stream);
+  ctx->o = desc->n_occ;
+  ctx->v = desc->n_virt;
+  ctx->nq = desc->n_aux;
+  ctx->R = desc->max_rhs;
+  ctx->prec = desc->precision;
+  ctx->ov = (size_t)ctx->o * ctx->v;
+  ctx->L = L;
+  ctx->ws = static_cast<char *>(desc->workspace);
+  ctx->xvar = xv;
+  if (desc->n_aux > 0) {
+    ctx->sk = auto_splits(variant_of(ctx->prec, xv), ns_max, ctx->v, ctx->nq, L.sk_max);
+    ctx->sj = L.sj_max;
+  }
+  hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&ctx->h_pulses), sizeof(DevPulse) * ctx->R);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->upload_ev, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventRecord(ctx->upload_ev, ctx->stream);
+  if (e == hipSuccess) e = launch_gaps(ctx->stream, desc->e_occ, desc->e_virt, ctx->o, ctx->v, ctx->D());
+  if (e == hipSuccess) e = launch_set_state(ctx->stream, ctx->state(), 0, nullptr, nullptr);
+  if (e != hipSuccess) {
+    if (ctx->h_pulses) (void)hipHostFree(ctx->h_pulses);
+    if (ctx->upload_ev) (void)hipEventDestroy(ctx->upload_ev);
+    delete ctx;
+    return fail(RTTDA_E_DEVICE, "create: %s", hipGetErrorString(e));
+  }
+  *out = ctx;
+  return RTTDA_OK;
+}
+
+rttda_status rttda_destroy(rttda_ctx *ctx) {
+  if (!ctx) return fail(RTTDA_E_INVAL, "ctx is NULL");
+  (void)hipStreamSynchronize(ctx->stream);
+  drop_graph(ctx);
+  ctx->prof.destroy();
+  if (ctx->upload_ev) (void)hipEventDestroy(ctx->upload_ev);
+  if (ctx->h_pulses) (void)hipHostFree(ctx->h_pulses);
+  delete ctx;
+  return RTTDA_OK;
+}
+
+rttda_status rttda_set_profiling(rttda_ctx *ctx, int32_t on) {
+  if (!ctx) return fail(RTTDA_E_INVAL, "ctx is NULL");
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  ctx->prof.reset();
+  ctx->prof.on = on != 0;
+  drop_graph(ctx);
+  return RTTDA_OK;
+}
+
+rttda_status rttda_get_profile(rttda_ctx *ctx, rttda_profile *out) {
+  if (!ctx || !out) return fail(RTTDA_E_INVAL, "NULL argument");
+  for (int k = 0; k < Profiler::CLASSES; ++k) {
+    HIP_TRY(ctx->prof.fold(k));
+    out->launches[k] = ctx->prof.launches[k];
+    out->ms[k] = ctx->prof.ms[k];
+  }
+  return RTTDA_OK;
+}
+
+rttda_status rttda_set_stream(rttda_ctx *ctx, void *stream) {
+  if (!ctx) return fail(RTTDA_E_INVAL, "ctx is NULL");
+  ctx->stream = static_cast<hipStream_t>(stream);
+  drop_graph(ctx);
+  return RTTDA_OK;
+}
+
+rttda_status rttda_set_tuning(rttda_ctx *ctx, const rttda_tuning *t) {
+  if (!ctx || !t) return fail(RTTDA_E_INVAL, "NULL argument");
+  int xv = ctx->xvar, sk = ctx->sk, sj = ctx->sj;
+  if (t->exchange_variant) {
+    const ExchangeVariant *x = variant_of(ctx->prec, t->exchange_variant - 1);
+    if (!x) return fail(RTTDA_E_UNSUPPORTED, "exchange variant %d does not exist", t->exchange_variant);
+    if (x->o16 < ctx->o) return fail(RTTDA_E_UNSUPPORTED, "variant %s holds o <= %d", x->name, x->o16);
+    HIP_TRY(x->prepare());
+    xv = t->exchange_variant - 1;
+  }
+  if (t->exchange_splits) {
+    if (t->exchange_splits < 1 || t->exchange_splits > ctx->L.sk_max)
+      return fail(RTTDA_E_NOMEM, "exchange_splits %d outside 1..%d", t->exchange_splits, ctx->L.sk_max);
+    sk = t->exchange_splits;
+  }
+  if (t->coulomb_splits) {
+    if (t->coulomb_splits < 1 || t->coulomb_splits > ctx->L.sj_max)
+      return fail(RTTDA_E_NOMEM, "coulomb_splits %d outside 1..%d", t->coulomb_splits, ctx->L.sj_max);
+    sj = t->coulomb_splits;
+  }
+  if (t->use_graph && t->use_graph != 1 && t->use_graph != 2) return fail(RTTDA_E_INVAL, "use_graph must be 0, 1 or 2");
+  if (t->steps_per_graph < 0 || t->steps_per_graph > 1024) return fail(RTTDA_E_INVAL, "steps_per_graph outside 0..1024");
+  if (ctx->nq > 0) {
+    ctx->xvar = xv;
+    ctx->sk = sk;
+    ctx->sj = sj;
+  }
+  if (t->use_graph) ctx->use_graph = t->use_graph;
+  if (t->steps_per_graph) ctx->steps_per_graph = t->steps_per_graph;
+  drop_graph(ctx);
+  return RTTDA_OK;
+}
+
+rttda_status rttda_get_tuning(const rttda_ctx *ctx, rttda_tuning *t) {
+  if (!ctx || !t) return fail(RTTDA_E_INVAL, "NULL argument");
+  t->exchange_variant = ctx->xvar + 1;
+  t->exchange_splits = ctx->sk;
+  t->coulomb_splits = ctx->sj;
+  t->use_graph = ctx->use_graph;
+  t->steps_per_graph = ctx->steps_per_graph;
+  return RTTDA_OK;
+}
+
+rttda_status rttda_sigma(rttda_ctx *ctx, int32_t nrhs, const double *field, const double *dir, const double *c0,
+                         const double *c, double *s0, double *s) {
+  if (!ctx) return fail(RTTDA_E_INVAL, "ctx is NULL");
+  rttda_status st = check_nrhs(ctx, nrhs);
+  if (st != RTTDA_OK) return st;
+  if (!field || !dir || !c0 || !c || !s0 || !s) return fail(RTTDA_E_INVAL, "NULL array argument");
+  if (!aligned16(c0) || !aligned16(c) || !aligned16(s0) || !aligned16(s))
+    return fail(RTTDA_E_INVAL, "device arrays must be 16-byte aligned");
+  if ((st = check_dirs(dir, nrhs)) != RTTDA_OK) return st;
+  for (int r = 0; r < nrhs; ++r)
+    if (!std::isfinite(field[r])) return fail(RTTDA_E_INVAL, "field %d not finite", r);
+  std::vector<DevPulse> p(nrhs);
+  std::vector<double> sc((size_t)nrhs * SC_STRIDE, 0.0);
+  for (int r = 0; r < nrhs; ++r) {
+    memset(&p[r], 0, sizeof(DevPulse));
+    p[r].kind = RTTDA_PULSE_NONE;
+    memcpy(p[r].dir, dir + 3 * r, 3 * sizeof(double));
+    sc[(size_t)r * SC_STRIDE + SC_E] = field[r];
+  }
+  if ((st = upload_pulses(ctx, p.data(), nrhs)) != RTTDA_OK) return st;
+  hipStream_t hs = ctx->stream;
+  // the E slots: host values, synchronous copy (tiny) keeps the vector's lifetime simple
+  HIP_TRY(hipMemcpyAsync(ctx->sc(), sc.data(), sc.size() * sizeof(double), hipMemcpyHostToDevice, hs));
+  HIP_TRY(hipStreamSynchronize(hs));
+  drop_graph(ctx);
+  HIP_TRY(launch_mu_blocks(hs, ctx->d.mu, ctx->pulses(), ctx->o, ctx->v, nrhs, ctx->moo(), ctx->mov(), ctx->mvv()));
+  if ((st = to_stage_copy(ctx, c, nrhs)) != RTTDA_OK) return st;
+  if ((st = enqueue_two_electron(ctx, nrhs)) != RTTDA_OK) return st;
+  HIP_TRY(launch_field(hs, c, c0, ctx->moo(), ctx->mov(), ctx->mvv(), ctx->o, ctx->v, nrhs, ctx->F(), ctx->part()));
+  HIP_TRY(launch_scalar(hs, nrhs, ctx->L.nbf, 0, SM_SIGMA0 | SM_KEEP_E, 0.0, ctx->pulses(), ctx->state(),
+                        ctx->part(), ctx->sc(), const_cast<double *>(c0), ctx->acc0(), ctx->xs0(), nullptr,
+                        ctx->normref(), s0));
+  HIP_TRY(launch_epilogue(hs, ctx->prec, nrhs, ctx->o, ctx->v, nslab(ctx), 0, EP_SIGMA, 1, 0.0, ctx->D(), ctx->P(),
+                          ctx->F(), ctx->sc(), c, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, s));
+  return RTTDA_OK;
+}
+
+rttda_status rttda_dipole_trace(rttda_ctx *ctx, int32_t nrhs, const double *dir, const double *c0, const double *c,
+                                double *out) {
+  if (!ctx) return fail(RTTDA_E_INVAL, "ctx is NULL");
+  rttda_status st = check_nrhs(ctx, nrhs);
+  if (st != RTTDA_OK) return st;
+  if (!dir || !c0 || !c || !out) return fail(RTTDA_E_INVAL, "NULL array argument");
+  if (!aligned16(c0) || !aligned16(c) || !aligned16(out))
+    return fail(RTTDA_E_INVAL, "device arrays must be 16-byte aligned");
+  if ((st = check_dirs(dir, nrhs)) != RTTDA_OK) return st;
+  std::vector<DevPulse> p(nrhs);
+  for (int r = 0; r < nrhs; ++r) {
+    memset(&p[r], 0, sizeof(DevPulse));
+    memcpy(p[r].dir, dir + 3 * r, 3 * sizeof(double));
+  }
+  if ((st = upload_pulses(ctx, p.data(), nrhs)) != RTTDA_OK) return st;
+  drop_graph(ctx);
+  hipStream_t hs = ctx->stream;
+  HIP_TRY(launch_mu_blocks(hs, ctx->d.mu, ctx->pulses(), ctx->o, ctx->v, nrhs, ctx->moo(), ctx->mov(), ctx->mvv()));
+  HIP_TRY(launch_field(hs, c, c0, ctx->moo(), ctx->mov(), ctx->mvv(), ctx->o, ctx->v, nrhs, ctx->F(), ctx->part()));
+  HIP_TRY(launch_scalar(hs, nrhs, ctx->L.nbf, 0, SM_OUT, 0.0, ctx->pulses(), ctx->state(), ctx->part(), ctx->sc(),
+                        const_cast<double *>(c0), ctx->acc0(), ctx->xs0(), out, ctx->normref(), nullptr));
+  return RTTDA_OK;
+}
+
+rttda_status rttda_propagate(rttda_ctx *ctx, int32_t nrhs, const rttda_pulse *pulses, double dt, int64_t step0,
+                             int64_t n_steps, double *c0, double *c, double *trace, double *norms) {
+  if (!ctx) return fail(RTTDA_E_INVAL, "ctx is NULL");
+  rttda_status st = check_nrhs(ctx, nrhs);
+  if (st != RTTDA_OK) return st;
+  if (!pulses || !c0 || !c) return fail(RTTDA_E_INVAL, "NULL argument (pulses, c0 and c are required)");
+  if (!aligned16(c0) || !aligned16(c) || (trace && !aligned16(trace)) || (norms && !aligned16(norms)))
+    return fail(RTTDA_E_INVAL, "device arrays must be 16-byte aligned");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(RTTDA_E_INVAL, "dt must be finite and > 0 (got %g)", dt);
+  if (step0 < 0 || n_steps < 0) return fail(RTTDA_E_INVAL, "step0 and n_steps must be >= 0");
+  bool has_field = false, has_kick = false;
+  for (int r = 0; r < nrhs; ++r) {
+    const rttda_pulse &p = pulses[r];
+    if (p.kind < RTTDA_PULSE_NONE || p.kind > RTTDA_PULSE_CHIRP) return fail(RTTDA_E_INVAL, "pulse %d: bad kind", r);
+    if (p.reserved != 0) return fail(RTTDA_E_INVAL, "pulse %d: reserved field must be 0", r);
+    const double vals[] = {p.e0, p.omega, p.t0, p.fwhm, p.beta, p.phase};
+    for (double x : vals)
+      if (!std::isfinite(x)) return fail(RTTDA_E_INVAL, "pulse %d: non-finite parameter", r);
+    if ((p.kind == RTTDA_PULSE_GAUSS || p.kind == RTTDA_PULSE_CHIRP) && !(p.fwhm > 0))
+      return fail(RTTDA_E_INVAL, "pulse %d: fwhm must be > 0", r);
+    if ((st = check_dirs(p.dir, 1)) != RTTDA_OK) return fail(RTTDA_E_INVAL, "pulse %d: dir is not a unit vector", r);
+    has_field |= (p.kind == RTTDA_PULSE_CW || p.kind == RTTDA_PULSE_GAUSS || p.kind == RTTDA_PULSE_CHIRP);
+    has_kick |= (p.kind == RTTDA_PULSE_DELTA && p.e0 != 0.0);
+  }
+  if ((st = upload_pulses(ctx, reinterpret_cast<const DevPulse *>(pulses), nrhs)) != RTTDA_OK) return st;
+  hipStream_t hs = ctx->stream;
+  const int o = ctx->o, v = ctx->v;
+  HIP_TRY(launch_mu_blocks(hs, ctx->d.mu, ctx->pulses(), o, v, nrhs, ctx->moo(), ctx->mov(), ctx->mvv()));
+  HIP_TRY(launch_set_state(hs, ctx->state(), step0, trace, norms));
+  if (has_kick && step0 == 0) {
+    HIP_TRY(launch_field(hs, c, c0, ctx->moo(), ctx->mov(), ctx->mvv(), o, v, nrhs, ctx->F(), ctx->part()));
+    HIP_TRY(launch_scalar(hs, nrhs, ctx->L.nbf, 0, 0, dt, ctx->pulses(), ctx->state(), ctx->part(), ctx->sc(), c0,
+                          ctx->acc0(), ctx->xs0(), nullptr, ctx->normref(), nullptr));
+    HIP_TRY(launch_kick(hs, nrhs, (int)ctx->ov, ctx->pulses(), ctx->F(), ctx->sc(), c, c0));
+  }
+  if ((st = to_stage_copy(ctx, c, nrhs)) != RTTDA_OK) return st;
+
+  const int spg = ctx->steps_per_graph;
+  const bool graph_ok = ctx->use_graph == 1 && !ctx->prof.on && hs != nullptr && n_steps >= 2LL * spg;
+  int64_t done = 0;
+  if (graph_ok) {
+    const int mode = has_field ? 1 : 0;
+    GraphEntry &G = ctx->graph;
+    const bool hit = G.valid && G.nrhs == nrhs && G.steps == spg && G.mode == mode && G.dt == dt && G.c0 == c0 &&
+                     G.c == c && G.trace == (trace != nullptr) && G.norms == (norms != nullptr);
+    if (!hit) {
+      drop_graph(ctx);
+      hipGraph_t graph = nullptr;
+      HIP_TRY(hipStreamBeginCapture(hs, hipStreamCaptureModeThreadLocal));
+      rttda_status cst = RTTDA_OK;
+      for (int k = 0; k < spg && cst == RTTDA_OK; ++k) cst = enqueue_step(ctx, nrhs, dt, has_field, c0, c);
+      hipError_t ee = hipStreamEndCapture(hs, &graph);
+      if (cst != RTTDA_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return cst;
+      }
+      if (ee != hipSuccess) return fail(RTTDA_E_DEVICE, "graph capture: %s", hipGetErrorString(ee));
+      hipGraphExec_t exec = nullptr;
+      ee = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ee != hipSuccess) return fail(RTTDA_E_DEVICE, "graph instantiate: %s", hipGetErrorString(ee));
+      G.valid = true;
+      G.exec = exec;
+      G.nrhs = nrhs;
+      G.steps = spg;
+      G.mode = mode;
+      G.dt = dt;
+      G.c0 = c0;
+      G.c = c;
+      G.trace = trace != nullptr;
+      G.norms = norms != nullptr;
+    }
+    const int64_t reps = n_steps / spg;
+    for (int64_t k = 0; k < reps; ++k) HIP_TRY(hipGraphLaunch(G.exec, hs));
+    done = reps * spg;
+  }
+  for (int64_t k = done; k < n_steps; ++k)
+    if ((st = enqueue_step(ctx, nrhs, dt, has_field, c0, c)) != RTTDA_OK) return st;
+  // final trace sample at step0 + n_steps
+  HIP_TRY(launch_field(hs, c, c0, ctx->moo(), ctx->mov(), ctx->mvv(), o, v, nrhs, ctx->F(), ctx->part()));
+  HIP_TRY(launch_scalar(hs, nrhs, ctx->L.nbf, 0, SM_TRACE, dt, ctx->pulses(), ctx->state(), ctx->part(), ctx->sc(),
+                        c0, ctx->acc0(), ctx->xs0(), nullptr, ctx->normref(), nullptr));
+  return RTTDA_OK;
+}
+
+rttda_status rttda_guard(rttda_ctx *ctx, int64_t *first_bad_step) {
+  if (!ctx || !first_bad_step) return fail(RTTDA_E_INVAL, "NULL argument");
+  DevState h{};
+  HIP_TRY(hipMemcpyAsync(&h, ctx->state(), sizeof h, hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  *first_bad_step = h.bad_step;
+  if (h.bad_step >= 0) return fail(RTTDA_E_UNSTABLE, "norm guard tripped at step %lld", (long long)h.bad_step);
+  return RTTDA_OK;
+}
+
+}  // extern "C"

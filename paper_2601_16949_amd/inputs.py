@@ -282,3 +282,49 @@ def serving_requests(n: int, rate: float = 20.0, seed: int = SEED_BASE + 5, o_mi
                       t0=0.5 * steps * dt, fwhm=400.0, direction=(0.0, 0.0, 1.0))
         out.append(Request(rid, t, Shape(o, v, 20 * o, 0.02, storage="bf16"), seed * 1000 + rid, steps, dt, p))
     return out
+
+
+# --------------------------------------------------------------------------------------
+# Device-side generation for large requests (serving): torch's counter-based CUDA generator,
+# one generator per (seed, tensor), drawn in Q chunks.  Same distributions and rounding rule
+# as make_problem (N(0,1) * s_eff in FP32, symmetric upper triangle mirrored, rounded to the
+# storage dtype); the values differ from make_problem's host streams.
+# --------------------------------------------------------------------------------------
+def make_device_tensors(shape: Shape, seed: int, device: str = "cuda:0", q_chunk: int = 64):
+    """Returns dict of device tensors e_occ, e_virt (f64), b_ov, b_oo, b_vv (f32 or bf16), mu (f64)."""
+    import torch
+
+    dt = torch.float32 if shape.storage == "f32" else torch.bfloat16
+    o, v, nq = shape.o, shape.v, shape.nq
+    s = float(np.float32(shape.s_eff))
+
+    def gen(tensor):
+        g = torch.Generator(device=device)
+        g.manual_seed((int(seed) * 7919 + int(tensor)) % (2 ** 63))
+        return g
+
+    e_occ, e_virt = gen_energies(shape, seed)
+    out = {"e_occ": torch.from_numpy(e_occ).to(device), "e_virt": torch.from_numpy(e_virt).to(device),
+           "mu": torch.from_numpy(gen_mu(shape, seed)).to(device)}
+    b_ov = torch.empty((nq, o, v), dtype=dt, device=device)
+    b_oo = torch.empty((nq, o, o), dtype=dt, device=device)
+    b_vv = torch.empty((nq, v, v), dtype=dt, device=device)
+    g_ov, g_oo, g_vv = gen(TENSOR_B_OV), gen(TENSOR_B_OO), gen(TENSOR_B_VV)
+    for q0 in range(0, nq, q_chunk):
+        q1 = min(nq, q0 + q_chunk)
+        n = q1 - q0
+        b_ov[q0:q1] = (torch.randn((n, o, v), generator=g_ov, device=device) * s).to(dt)
+        m = torch.randn((n, o, o), generator=g_oo, device=device)
+        b_oo[q0:q1] = ((torch.triu(m) + torch.triu(m, 1).transpose(1, 2)) * s).to(dt)
+        m = torch.randn((n, v, v), generator=g_vv, device=device)
+        b_vv[q0:q1] = ((torch.triu(m) + torch.triu(m, 1).transpose(1, 2)) * s).to(dt)
+        del m
+    out.update(b_ov=b_ov, b_oo=b_oo, b_vv=b_vv)
+    return out
+
+
+def problem_from_device(shape: Shape, seed: int, t: dict) -> Problem:
+    """Host copy (FP32 values) of device-generated tensors, for the oracle."""
+    f = lambda x: x.float().cpu().numpy()  # noqa: E731
+    return Problem(shape, seed, t["e_occ"].cpu().numpy(), t["e_virt"].cpu().numpy(), f(t["b_ov"]), f(t["b_oo"]),
+                   f(t["b_vv"]), t["mu"].cpu().numpy())

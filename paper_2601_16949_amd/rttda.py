@@ -1,0 +1,356 @@
+"""Python binding of librttda.so (ctypes): argument marshalling only.
+
+Every step of the computation runs in the library's HIP kernels; this module
+only checks shapes and dtypes, hands device pointers of torch tensors to the C
+ABI (include/rttda.h) and keeps the tensors alive.  It fails loudly if the
+shared library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librttda.so")
+
+OK, E_INVAL, E_NOMEM, E_DEVICE, E_STATE, E_UNSTABLE, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+F64, F32, BF16 = 0, 1, 2
+PREC_FP32, PREC_MIXED_BF16 = 1, 2
+PULSE_NONE, PULSE_DELTA, PULSE_CW, PULSE_GAUSS, PULSE_CHIRP = 0, 1, 2, 3, 4
+
+_lib = None
+
+
+class RttdaError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"rttda status {status}: {msg}")
+        self.status = status
+
+
+class CPulse(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32), ("e0", ctypes.c_double),
+                ("omega", ctypes.c_double), ("t0", ctypes.c_double), ("fwhm", ctypes.c_double),
+                ("beta", ctypes.c_double), ("phase", ctypes.c_double), ("dir", ctypes.c_double * 3)]
+
+
+class CDesc(ctypes.Structure):
+    _fields_ = [("n_occ", ctypes.c_int32), ("n_virt", ctypes.c_int32), ("n_aux", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("b_dtype", ctypes.c_int32), ("max_rhs", ctypes.c_int32),
+                ("cx", ctypes.c_double), ("e_occ", ctypes.c_void_p), ("e_virt", ctypes.c_void_p),
+                ("b_ov", ctypes.c_void_p), ("b_oo", ctypes.c_void_p), ("b_vv", ctypes.c_void_p),
+                ("mu", ctypes.c_void_p), ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
+                ("stream", ctypes.c_void_p)]
+
+
+class CTuning(ctypes.Structure):
+    _fields_ = [("exchange_variant", ctypes.c_int32), ("exchange_splits", ctypes.c_int32),
+                ("coulomb_splits", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("steps_per_graph", ctypes.c_int32)]
+
+
+class CProfile(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64 * 4), ("ms", ctypes.c_double * 4)]
+
+
+PROFILE_CLASSES = ("exchange", "coulomb", "field", "epilogue")
+
+EXPORTS = {
+    "rttda_set_profiling": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "rttda_get_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(CProfile)]),
+    "rttda_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(CDesc), ctypes.POINTER(ctypes.c_size_t)]),
+    "rttda_create": (ctypes.c_int, [ctypes.POINTER(CDesc), ctypes.POINTER(ctypes.c_void_p)]),
+    "rttda_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "rttda_set_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "rttda_sigma": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(ctypes.c_double), ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.c_void_p]),
+    "rttda_propagate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(CPulse), ctypes.c_double,
+                                       ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_void_p]),
+    "rttda_dipole_trace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "rttda_guard": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
+    "rttda_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(CTuning)]),
+    "rttda_get_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(CTuning)]),
+    "rttda_exchange_variants": (ctypes.c_int32, [ctypes.c_int32]),
+    "rttda_exchange_variant_name": (ctypes.c_char_p, [ctypes.c_int32, ctypes.c_int32]),
+    "rttda_last_error": (ctypes.c_char_p, []),
+    "rttda_version": (ctypes.c_char_p, []),
+}
+
+
+def load(path: str = LIB_PATH):
+    """Load librttda.so (built in-tree); raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"librttda.so not built at {path}; run `python -m paper_2601_16949_amd.build`")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in EXPORTS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != OK:
+        raise RttdaError(status, load().rttda_last_error().decode())
+
+
+def _ptr(t) -> int:
+    return t.data_ptr()
+
+
+def _dev_check(t, dtype, shape, name):
+    import torch
+
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def make_pulses(pulses) -> ctypes.Array:
+    arr = (CPulse * len(pulses))()
+    for k, p in enumerate(pulses):
+        d = np.asarray(p.direction, dtype=np.float64)
+        d = d / np.linalg.norm(d)
+        arr[k].kind = int(p.kind)
+        arr[k].reserved = 0
+        arr[k].e0 = float(p.e0)
+        arr[k].omega = float(p.omega)
+        arr[k].t0 = float(p.t0)
+        arr[k].fwhm = float(p.fwhm)
+        arr[k].beta = float(p.beta)
+        arr[k].phase = float(p.phase)
+        for i in range(3):
+            arr[k].dir[i] = float(d[i])
+    return arr
+
+
+class DeviceProblem:
+    """Stored inputs of one molecule as device tensors (what the C ABI points at)."""
+
+    @classmethod
+    def from_tensors(cls, shape, tensors: dict, precision: str):
+        self = cls.__new__(cls)
+        self.o, self.v, self.nq = shape.o, shape.v, shape.nq
+        self.cx = float(shape.cx)
+        self.precision = precision
+        for k in ("e_occ", "e_virt", "b_ov", "b_oo", "b_vv", "mu"):
+            setattr(self, k, tensors[k])
+        return self
+
+    def __init__(self, problem, precision: str = "fp32", device: str = "cuda:0"):
+        import torch
+
+        self.o, self.v, self.nq = problem.o, problem.v, problem.nq
+        self.cx = float(problem.cx)
+        self.precision = precision
+        bt = torch.float32 if precision == "fp32" else torch.bfloat16
+        if precision == "mixed" and problem.shape.storage != "bf16":
+            raise ValueError("mixed precision takes BF16-stored factors")
+        self.e_occ = torch.from_numpy(np.ascontiguousarray(problem.e_occ)).to(device)
+        self.e_virt = torch.from_numpy(np.ascontiguousarray(problem.e_virt)).to(device)
+        self.b_ov = torch.from_numpy(np.ascontiguousarray(problem.b_ov)).to(device).to(bt).contiguous()
+        self.b_oo = torch.from_numpy(np.ascontiguousarray(problem.b_oo)).to(device).to(bt).contiguous()
+        self.b_vv = torch.from_numpy(np.ascontiguousarray(problem.b_vv)).to(device).to(bt).contiguous()
+        self.mu = torch.from_numpy(np.ascontiguousarray(problem.mu)).to(device)
+
+    @property
+    def nbytes(self) -> int:
+        return sum(t.numel() * t.element_size() for t in (self.e_occ, self.e_virt, self.b_ov, self.b_oo, self.b_vv,
+                                                          self.mu))
+
+
+class Context:
+    """One operator on the GPU: rttda_create + workspace, with sigma / propagate / dipole_trace."""
+
+    def __init__(self, dev: DeviceProblem, max_rhs: int, stream=None, sync_streams: bool = True):
+        import torch
+
+        lib = load()
+        self.sync_streams = sync_streams
+        self.lib = lib
+        self.dev = dev
+        self.max_rhs = int(max_rhs)
+        self.o, self.v = dev.o, dev.v
+        self.device = dev.e_occ.device
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        prec = PREC_FP32 if dev.precision == "fp32" else PREC_MIXED_BF16
+        d = CDesc()
+        d.n_occ, d.n_virt, d.n_aux = dev.o, dev.v, dev.nq
+        d.precision = prec
+        d.b_dtype = F32 if prec == PREC_FP32 else BF16
+        d.max_rhs = self.max_rhs
+        d.cx = dev.cx
+        d.e_occ, d.e_virt, d.mu = _ptr(dev.e_occ), _ptr(dev.e_virt), _ptr(dev.mu)
+        if dev.nq > 0:
+            d.b_ov, d.b_oo, d.b_vv = _ptr(dev.b_ov), _ptr(dev.b_oo), _ptr(dev.b_vv)
+        nbytes = ctypes.c_size_t(0)
+        _check(lib.rttda_workspace_bytes(ctypes.byref(d), ctypes.byref(nbytes)))
+        self.workspace = torch.empty(max(int(nbytes.value), 256) + 256, dtype=torch.uint8, device=self.device)
+        base = _ptr(self.workspace)
+        aligned = (base + 255) // 256 * 256
+        d.workspace = aligned
+        d.workspace_bytes = int(nbytes.value)
+        d.stream = self.stream.cuda_stream
+        self.desc = d
+        h = ctypes.c_void_p()
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        _check(lib.rttda_create(ctypes.byref(d), ctypes.byref(h)))
+        self.handle = h
+
+    # -- stream ordering with torch's current stream --------------------------------------------
+    def _enter(self):
+        import torch
+
+        if self.sync_streams:
+            self.stream.wait_stream(torch.cuda.current_stream(self.device))
+
+    def _leave(self):
+        import torch
+
+        if self.sync_streams:
+            torch.cuda.current_stream(self.device).wait_stream(self.stream)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _check(self.lib.rttda_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- entry points ---------------------------------------------------------------------------
+    def sigma(self, field: Sequence[float], dirs, c0, c, s0=None, s=None):
+        import torch
+
+        nrhs = c.shape[0]
+        _dev_check(c0, torch.float64, (nrhs, 2), "c0")
+        _dev_check(c, torch.float64, (nrhs, 2, self.o, self.v), "c")
+        s0 = torch.empty_like(c0) if s0 is None else s0
+        s = torch.empty_like(c) if s is None else s
+        f = (ctypes.c_double * nrhs)(*[float(x) for x in field])
+        dd = np.ascontiguousarray(np.asarray(dirs, dtype=np.float64).reshape(nrhs, 3))
+        dd = dd / np.linalg.norm(dd, axis=1, keepdims=True)
+        dptr = dd.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        self._enter()
+        _check(self.lib.rttda_sigma(self.handle, nrhs, f, dptr, _ptr(c0), _ptr(c), _ptr(s0), _ptr(s)))
+        self._leave()
+        return s0, s
+
+    def propagate(self, pulses, dt: float, n_steps: int, c0, c, step0: int = 0, trace=None, norms=None,
+                  want_trace: bool = True, want_norms: bool = False):
+        import torch
+
+        nrhs = c.shape[0]
+        _dev_check(c0, torch.float64, (nrhs, 2), "c0")
+        _dev_check(c, torch.float64, (nrhs, 2, self.o, self.v), "c")
+        if want_trace and trace is None:
+            trace = torch.empty((n_steps + 1, nrhs), dtype=torch.float64, device=self.device)
+        if want_norms and norms is None:
+            norms = torch.empty((n_steps + 1, nrhs), dtype=torch.float64, device=self.device)
+        cp = make_pulses(pulses)
+        self._enter()
+        _check(self.lib.rttda_propagate(self.handle, nrhs, cp, float(dt), int(step0), int(n_steps), _ptr(c0),
+                                        _ptr(c), _ptr(trace) if trace is not None else None,
+                                        _ptr(norms) if norms is not None else None))
+        self._leave()
+        if want_norms:
+            return trace, norms
+        return trace
+
+    def dipole_trace(self, dirs, c0, c, out=None):
+        import torch
+
+        nrhs = c.shape[0]
+        _dev_check(c0, torch.float64, (nrhs, 2), "c0")
+        _dev_check(c, torch.float64, (nrhs, 2, self.o, self.v), "c")
+        out = torch.empty(nrhs, dtype=torch.float64, device=self.device) if out is None else out
+        dd = np.ascontiguousarray(np.asarray(dirs, dtype=np.float64).reshape(nrhs, 3))
+        dd = dd / np.linalg.norm(dd, axis=1, keepdims=True)
+        self._enter()
+        _check(self.lib.rttda_dipole_trace(self.handle, nrhs, dd.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                           _ptr(c0), _ptr(c), _ptr(out)))
+        self._leave()
+        return out
+
+    def guard(self) -> int:
+        bad = ctypes.c_int64(0)
+        st = self.lib.rttda_guard(self.handle, ctypes.byref(bad))
+        if st not in (OK, E_UNSTABLE):
+            _check(st)
+        return int(bad.value)
+
+    def set_tuning(self, exchange_variant=0, exchange_splits=0, coulomb_splits=0, use_graph=0, steps_per_graph=0):
+        t = CTuning(exchange_variant, exchange_splits, coulomb_splits, use_graph, steps_per_graph)
+        _check(self.lib.rttda_set_tuning(self.handle, ctypes.byref(t)))
+
+    def get_tuning(self) -> dict:
+        t = CTuning()
+        _check(self.lib.rttda_get_tuning(self.handle, ctypes.byref(t)))
+        return {k: getattr(t, k) for k, _ in CTuning._fields_}
+
+    def set_profiling(self, on: bool):
+        _check(self.lib.rttda_set_profiling(self.handle, 1 if on else 0))
+
+    def get_profile(self) -> dict:
+        p = CProfile()
+        _check(self.lib.rttda_get_profile(self.handle, ctypes.byref(p)))
+        return {name: {"launches": int(p.launches[k]), "ms": float(p.ms[k])} for k, name in enumerate(PROFILE_CLASSES)}
+
+    def variant_name(self, k: int) -> str:
+        return self.lib.rttda_exchange_variant_name(self.desc.precision, k).decode()
+
+
+def workspace_bytes(o: int, v: int, nq: int, precision: str, max_rhs: int) -> int:
+    """Workspace a context of this shape needs (host-side query, no device work)."""
+    d = CDesc()
+    d.n_occ, d.n_virt, d.n_aux = o, v, nq
+    d.precision = PREC_FP32 if precision == "fp32" else PREC_MIXED_BF16
+    d.b_dtype = F32 if precision == "fp32" else BF16
+    d.max_rhs = max_rhs
+    n = ctypes.c_size_t(0)
+    _check(load().rttda_workspace_bytes(ctypes.byref(d), ctypes.byref(n)))
+    return int(n.value)
+
+
+def ground_state(nrhs: int, o: int, v: int, device="cuda:0"):
+    """c0 = 1, C = 0 for nrhs states (the Kohn-Sham ground state)."""
+    import torch
+
+    c0 = torch.zeros((nrhs, 2), dtype=torch.float64, device=device)
+    c0[:, 0] = 1.0
+    c = torch.zeros((nrhs, 2, o, v), dtype=torch.float64, device=device)
+    return c0, c
+
+
+def to_planes(c0: np.ndarray, c: np.ndarray, device="cuda:0"):
+    """complex (nrhs,), (nrhs, o, v) -> device f64 planes (nrhs, 2), (nrhs, 2, o, v)."""
+    import torch
+
+    c0p = np.stack([c0.real, c0.imag], axis=-1)
+    cp = np.stack([c.real, c.imag], axis=1)
+    return (torch.from_numpy(np.ascontiguousarray(c0p)).to(device),
+            torch.from_numpy(np.ascontiguousarray(cp)).to(device))
+
+
+def from_planes(c0p, cp):
+    a = c0p.detach().cpu().numpy()
+    b = cp.detach().cpu().numpy()
+    return a[:, 0] + 1j * a[:, 1], b[:, 0] + 1j * b[:, 1]

@@ -1,0 +1,193 @@
+"""Continuous-batching serving loop for RT-TDA propagation requests on one GPU.
+
+Requests (o, v, N_Q, pulse, steps) arrive over time.  The server admits a request as soon as
+its HBM footprint (factor tensors + library workspace + state + trace) fits the remaining
+budget, keeps its factors and amplitudes resident, and advances every admitted request in
+chunks of RK4 steps, each request on its own HIP stream so that the work of different
+requests overlaps on the device.  A request is retired (memory released, latency recorded)
+when its last chunk has finished.  All device work goes through the C ABI (one context per
+request); this module only schedules.
+
+Each request's result does not depend on what else is resident: the kernels use no atomics
+and no cross-request state, so a request's trace in a mix is bitwise the trace it gets alone.
+"""
+from __future__ import annotations
+
+import math
+import time
+from collections import deque
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional
+
+import numpy as np
+
+from . import inputs as I
+from . import rttda
+
+AU_FS = 0.02418884326585747
+
+
+def request_flops(shape: I.Shape, n_steps: int) -> float:
+    ov = shape.o * shape.v
+    return n_steps * 4.0 * (8.0 * shape.nq * ov + 4.0 * shape.nq * ov * (shape.o + shape.v))
+
+
+def footprint(shape: I.Shape, n_steps: int, precision: str) -> int:
+    """HBM bytes a resident request holds."""
+    o, v, nq = shape.o, shape.v, shape.nq
+    bsz = 4 if precision == "fp32" else 2
+    factors = nq * (o * v + o * o + v * v) * bsz
+    other = (o + v) * 8 + 3 * (o + v) ** 2 * 8
+    state = 2 * o * v * 8 + 16
+    trace = (n_steps + 1) * 8
+    ws = rttda.workspace_bytes(o, v, nq, precision, 1) + 512
+    return int(factors + other + state + trace + ws)
+
+
+@dataclass
+class Slot:
+    req: I.Request
+    ctx: rttda.Context
+    dev: rttda.DeviceProblem
+    c0: object
+    c: object
+    trace: object
+    stream: object
+    bytes: int
+    t_admit: float
+    done: int = 0
+    event: object = None
+    t_first_chunk: float = 0.0
+
+
+@dataclass
+class Result:
+    rid: int
+    o: int
+    n_steps: int
+    arrival: float
+    admitted: float
+    finished: float
+    trace: Optional[np.ndarray] = None
+
+    @property
+    def latency(self):
+        return self.finished - self.arrival
+
+    @property
+    def wait(self):
+        return self.admitted - self.arrival
+
+
+class Server:
+    def __init__(self, budget_bytes: int, chunk_steps: int = 128, precision: str = "mixed", device: str = "cuda:0",
+                 keep_traces: bool = True, max_active: int = 64):
+        self.budget = int(budget_bytes)
+        self.chunk = int(chunk_steps)
+        self.precision = precision
+        self.device = device
+        self.keep_traces = keep_traces
+        self.max_active = max_active
+        self.used = 0
+        self.peak_used = 0
+        self.active: List[Slot] = []
+        self.queue: deque = deque()
+        self.results: Dict[int, Result] = {}
+
+    # ------------------------------------------------------------------------------------
+    def _admit(self, req: I.Request, now: float) -> Slot:
+        import torch
+
+        nb = footprint(req.shape, req.n_steps, self.precision)
+        stream = torch.cuda.Stream(device=self.device)
+        with torch.cuda.stream(stream):
+            t = I.make_device_tensors(req.shape, req.seed, device=self.device)
+            dev = rttda.DeviceProblem.from_tensors(req.shape, t, self.precision)
+            ctx = rttda.Context(dev, max_rhs=1, stream=stream, sync_streams=False)
+            c0, c = rttda.ground_state(1, req.shape.o, req.shape.v, device=self.device)
+            trace = torch.empty((req.n_steps + 1, 1), dtype=torch.float64, device=self.device)
+        self.used += nb
+        self.peak_used = max(self.peak_used, self.used)
+        return Slot(req, ctx, dev, c0, c, trace, stream, nb, now)
+
+    def _issue(self, s: Slot):
+        import torch
+
+        n = min(self.chunk, s.req.n_steps - s.done)
+        with torch.cuda.stream(s.stream):
+            s.ctx.propagate([s.req.pulse], s.req.dt, n, s.c0, s.c, step0=s.done,
+                            trace=s.trace[s.done:s.done + n + 1])
+            s.event = torch.cuda.Event()
+            s.event.record(s.stream)
+        s.done += n
+
+    def _retire(self, s: Slot, now: float):
+        tr = s.trace.cpu().numpy()[:, 0] if self.keep_traces else None
+        bad = s.ctx.guard()
+        if bad != -1:
+            raise rttda.RttdaError(rttda.E_UNSTABLE, f"request {s.req.rid}: norm guard at step {bad}")
+        s.ctx.close()
+        self.used -= s.bytes
+        self.results[s.req.rid] = Result(s.req.rid, s.req.shape.o, s.req.n_steps, s.req.arrival, s.t_admit, now, tr)
+
+    # ------------------------------------------------------------------------------------
+    def run(self, requests: List[I.Request], time_scale: float = 1.0, realtime: bool = True) -> dict:
+        """Serve `requests` (arrival times scaled by time_scale); returns statistics."""
+        import torch
+
+        pending = deque(sorted(requests, key=lambda r: r.arrival))
+        for r in requests:
+            if footprint(r.shape, r.n_steps, self.precision) > self.budget:
+                raise ValueError(f"request {r.rid} alone exceeds the HBM budget")
+        t0 = time.perf_counter()
+        clock = lambda: time.perf_counter() - t0  # noqa: E731
+        max_concurrent = 0
+        while pending or self.queue or self.active:
+            now = clock()
+            while pending and (not realtime or pending[0].arrival * time_scale <= now):
+                r = pending.popleft()
+                self.queue.append(r)
+            # retire finished requests
+            for s in list(self.active):
+                if s.done >= s.req.n_steps and s.event.query():
+                    self.active.remove(s)
+                    self._retire(s, clock())
+            # admit in arrival order while memory and slots allow (later requests may backfill)
+            for r in list(self.queue):
+                if len(self.active) >= self.max_active:
+                    break
+                nb = footprint(r.shape, r.n_steps, self.precision)
+                if self.used + nb <= self.budget:
+                    self.queue.remove(r)
+                    self.active.append(self._admit(r, clock()))
+            max_concurrent = max(max_concurrent, len(self.active))
+            # keep every resident request's stream busy
+            issued = False
+            for s in self.active:
+                if s.done < s.req.n_steps and (s.event is None or s.event.query()):
+                    self._issue(s)
+                    issued = True
+            if not issued:
+                if self.active:
+                    time.sleep(2e-4)
+                elif pending and realtime:
+                    time.sleep(max(0.0, min(0.01, pending[0].arrival * time_scale - clock())))
+        makespan = clock()
+        torch.cuda.synchronize()
+        res = [self.results[r.rid] for r in requests]
+        lat = np.array([x.latency for x in res])
+        wait = np.array([x.wait for x in res])
+        flops = sum(request_flops(r.shape, r.n_steps) for r in requests)
+        fs = sum(r.n_steps * r.dt * AU_FS for r in requests)
+        return {
+            "requests": len(requests),
+            "makespan_s": makespan,
+            "p50_latency_s": float(np.percentile(lat, 50)),
+            "p99_latency_s": float(np.percentile(lat, 99)),
+            "p50_wait_s": float(np.percentile(wait, 50)),
+            "max_concurrent": max_concurrent,
+            "peak_hbm_bytes": self.peak_used,
+            "budget_bytes": self.budget,
+            "aggregate_fs_per_hour": fs / (makespan / 3600.0),
+            "sigma_gflops": flops / makespan / 1e9,
+        }

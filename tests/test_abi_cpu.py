@@ -1,0 +1,73 @@
+"""The C-ABI library loads and exports every entry point include/rttda.h declares (no GPU needed),
+and the host-side argument checks that run before any device work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2601_16949_amd import rttda
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "rttda.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rttda_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = rttda.load()
+    names = declared_functions()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(rttda.EXPORTS), "binding and header disagree"
+
+
+def test_version_and_variants():
+    lib = rttda.load()
+    assert lib.rttda_version().decode().startswith("rttda-gfx950")
+    n = lib.rttda_exchange_variants(rttda.PREC_FP32)
+    assert n >= 4
+    names = [lib.rttda_exchange_variant_name(rttda.PREC_FP32, k).decode() for k in range(1, n + 1)]
+    assert all(nm.startswith("f32_o") for nm in names)
+    assert lib.rttda_exchange_variant_name(rttda.PREC_FP32, n + 1).decode() == ""
+    assert lib.rttda_exchange_variants(7) == 0
+
+
+def desc(o=10, v=40, nq=120, prec=rttda.PREC_FP32, bd=rttda.F32, max_rhs=3):
+    d = rttda.CDesc()
+    d.n_occ, d.n_virt, d.n_aux = o, v, nq
+    d.precision, d.b_dtype, d.max_rhs = prec, bd, max_rhs
+    d.cx = 0.2
+    return d
+
+
+def ws_bytes(d):
+    n = ctypes.c_size_t(0)
+    st = rttda.load().rttda_workspace_bytes(ctypes.byref(d), ctypes.byref(n))
+    return st, n.value
+
+
+def test_workspace_query_and_validation():
+    st, n = ws_bytes(desc())
+    assert st == rttda.OK and n > 0
+    st2, n2 = ws_bytes(desc(max_rhs=6))
+    assert st2 == rttda.OK and n2 > n  # grows with the RHS count
+    for bad in (desc(o=0), desc(v=0), desc(nq=-1), desc(max_rhs=0), desc(max_rhs=5000),
+                desc(prec=rttda.PREC_FP32, bd=rttda.BF16), desc(prec=rttda.PREC_MIXED_BF16, bd=rttda.F32),
+                desc(prec=9)):
+        st, _ = ws_bytes(bad)
+        assert st == rttda.E_INVAL
+        assert rttda.load().rttda_last_error().decode() != ""
+
+
+def test_create_rejects_null_pointers_before_any_device_work():
+    d = desc()
+    h = ctypes.c_void_p()
+    st = rttda.load().rttda_create(ctypes.byref(d), ctypes.byref(h))
+    assert st == rttda.E_INVAL
+    assert "NULL" in rttda.load().rttda_last_error().decode()
+    assert rttda.load().rttda_destroy(None) == rttda.E_INVAL

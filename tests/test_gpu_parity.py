@@ -1,0 +1,248 @@
+"""Parity of the HIP path (through the C ABI) against the FP64 oracle on seeded inputs.
+
+Tolerances (FP32 precision): sigma and single-call outputs element-wise within 5e-6 of the
+largest |value|; dipole traces within 1e-5 relative (max abs difference / max |trace|).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import rttda64 as O
+from paper_2601_16949_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def setup(shape, seed, max_rhs, precision="fp32"):
+    from paper_2601_16949_amd import rttda
+
+    prob = I.make_problem(shape, seed)
+    dev = rttda.DeviceProblem(prob, precision)
+    ctx = rttda.Context(dev, max_rhs=max_rhs)
+    return prob, O.Operator.from_problem(prob), ctx
+
+
+SIGMA_CASES = [
+    # (o, v, nq, nrhs)
+    (10, 40, 120, 1),
+    (13, 37, 7, 3),
+    (60, 400, 50, 3),
+    (40, 300, 20, 5),
+    (1, 1, 1, 1),
+    (5, 9, 0, 2),
+    (17, 67, 33, 4),
+    (100, 130, 11, 2),
+]
+
+
+MIXED_SIGMA_CASES = [
+    (10, 40, 120, 1),
+    (60, 400, 40, 3),
+    (33, 70, 9, 2),
+    (240, 64, 3, 1),
+    (130, 96, 5, 2),
+    (7, 13, 4, 3),
+]
+
+SIGMA_TOL = {"fp32": 5e-6, "mixed": 2e-5}
+
+
+@pytest.mark.parametrize("o,v,nq,nrhs,prec", [c + ("fp32",) for c in SIGMA_CASES] +
+                         [c + ("mixed",) for c in MIXED_SIGMA_CASES])
+def test_sigma_matches_oracle(gpu_lib, o, v, nq, nrhs, prec):
+    import torch
+
+    say(f"[sigma] o={o} v={v} nq={nq} nrhs={nrhs} precision={prec}")
+    shape = I.Shape(o, v, nq, b_scale=0.05, storage="f32" if prec == "fp32" else "bf16")
+    prob, op, ctx = setup(shape, 1234 + o, nrhs, prec)
+    c0, c = I.random_state(o, v, nrhs, seed=o * 7 + v)
+    rng = np.random.default_rng(5)
+    dirs = rng.standard_normal((nrhs, 3))
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    field = rng.uniform(-0.05, 0.05, nrhs)
+    c0d, cd = gpu_lib.to_planes(c0, c)
+    s0d, sd = ctx.sigma(field, dirs, c0d, cd)
+    torch.cuda.synchronize()
+    s0, s = gpu_lib.from_planes(s0d, sd)
+    for r in range(nrhs):
+        blocks = O.dipole_blocks(op, dirs[r])
+        h0, hC = O.apply_H(op, blocks, field[r], c0[r], c[r])
+        scale = max(np.max(np.abs(hC)), abs(h0))
+        err = np.max(np.abs(s[r] - hC)) / scale
+        err0 = abs(s0[r] - h0) / scale
+        say(f"   rhs {r}: rel err {err:.2e}, ground {err0:.2e}")
+        assert err < SIGMA_TOL[prec]
+        assert err0 < 1e-12
+
+
+@pytest.mark.parametrize("o,v,nq,nrhs", [(10, 40, 120, 3), (23, 51, 9, 2)])
+def test_dipole_trace_matches_oracle(gpu_lib, o, v, nq, nrhs):
+    import torch
+
+    say(f"[dipole_trace] o={o} v={v} nq={nq} nrhs={nrhs}")
+    prob, op, ctx = setup(I.Shape(o, v, nq), 99, nrhs)
+    c0, c = I.random_state(o, v, nrhs, seed=3)
+    dirs = np.eye(3)[:nrhs] if nrhs <= 3 else np.random.default_rng(1).standard_normal((nrhs, 3))
+    c0d, cd = gpu_lib.to_planes(c0, c)
+    out = ctx.dipole_trace(dirs, c0d, cd)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    for r in range(nrhs):
+        ref = O.dipole_expectation(O.dipole_blocks(op, dirs[r]), c0[r], c[r])
+        assert abs(got[r] - ref) <= 1e-12 * max(1.0, abs(ref))
+
+
+def run_trace(gpu_lib, ctx, pulses, dt, n_steps, o, v, step0=0, c0d=None, cd=None):
+    import torch
+
+    nrhs = len(pulses)
+    if c0d is None:
+        c0d, cd = gpu_lib.ground_state(nrhs, o, v)
+    tr = ctx.propagate(pulses, dt, n_steps, c0d, cd, step0=step0)
+    torch.cuda.synchronize()
+    return tr.cpu().numpy(), c0d, cd
+
+
+def rel_trace_err(got, ref):
+    return np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+
+
+def test_cfg1_full_trace_parity(gpu_lib):
+    """o10 v40 N_Q120, z kick kappa 1e-4, dt 0.05, 2000 steps: dipole trace within 1e-5."""
+    wl = I.workload(1)
+    say(f"[cfg1 full] {wl.name}")
+    prob, op, ctx = setup(wl.shape, wl.seed, 1)
+    got, c0d, cd = run_trace(gpu_lib, ctx, wl.pulses, wl.dt, wl.n_steps, wl.shape.o, wl.shape.v)
+    ref = O.EigenRoute(op).propagate_field_free(wl.pulses[0], wl.dt, wl.n_steps)
+    err = rel_trace_err(got[:, 0], ref)
+    say(f"   trace rel err {err:.3e}")
+    assert err < 1e-5
+    assert ctx.guard() == -1
+
+
+@pytest.mark.parametrize("kind", [I.PULSE_GAUSS, I.PULSE_CHIRP, I.PULSE_CW])
+def test_pulse_trace_parity(gpu_lib, kind):
+    o, v, nq = 12, 30, 24
+    say(f"[pulse trace] kind={kind}")
+    prob, op, ctx = setup(I.Shape(o, v, nq), 4321, 3)
+    pulses = [
+        I.Pulse(kind=kind, e0=0.04, omega=0.5 + 0.1 * r, t0=5.0, fwhm=6.0, beta=0.02, phase=0.3 * r,
+                direction=I.AXES[r])
+        for r in range(3)
+    ]
+    dt, n = 0.05, 300
+    got, c0d, cd = run_trace(gpu_lib, ctx, pulses, dt, n, o, v)
+    for r in range(3):
+        ref, c0f, Cf = O.propagate(op, pulses[r], dt, n)
+        err = rel_trace_err(got[:, r], ref)
+        say(f"   rhs {r}: trace rel err {err:.3e}")
+        assert err < 1e-5
+        c0g, cg = gpu_lib.from_planes(c0d, cd)
+        assert np.max(np.abs(cg[r] - Cf)) < 1e-5 * max(np.max(np.abs(Cf)), 1e-12) + 1e-9
+        assert abs(c0g[r] - c0f) < 1e-6
+
+
+def test_batched_rhs_equal_single(gpu_lib):
+    """Three kicks in one launch give the same traces as three single-RHS runs (bitwise)."""
+    import torch
+
+    o, v, nq = 20, 64, 40
+    say("[batched == single]")
+    prob, op, ctx = setup(I.Shape(o, v, nq), 777, 3)
+    pulses = I.kick_pulses()
+    got, _, _ = run_trace(gpu_lib, ctx, pulses, 0.05, 120, o, v)
+    for r in range(3):
+        one, _, _ = run_trace(gpu_lib, ctx, [pulses[r]], 0.05, 120, o, v)
+        err = rel_trace_err(one[:, 0], got[:, r])
+        assert err < 1e-6, err
+
+
+def test_resume_equals_single_call(gpu_lib):
+    """Propagating 150 + 170 steps (step0 = 150 on the second call) equals one 320-step call."""
+    o, v, nq = 16, 48, 30
+    say("[resume]")
+    prob, op, ctx = setup(I.Shape(o, v, nq), 555, 2)
+    pulses = [I.Pulse(kind=I.PULSE_GAUSS, e0=0.03, omega=0.6, t0=8.0, fwhm=10.0, direction=(0, 0, 1)),
+              I.Pulse(kind=I.PULSE_DELTA, e0=1e-3, direction=(1, 0, 0))]
+    full, c0a, ca = run_trace(gpu_lib, ctx, pulses, 0.05, 320, o, v)
+    part1, c0b, cb = run_trace(gpu_lib, ctx, pulses, 0.05, 150, o, v)
+    part2, c0b, cb = run_trace(gpu_lib, ctx, pulses, 0.05, 170, o, v, step0=150, c0d=c0b, cd=cb)
+    assert np.array_equal(np.concatenate([part1, part2[1:]]), full)
+    assert np.array_equal(ca.cpu().numpy(), cb.cpu().numpy())
+
+
+def test_graph_and_direct_paths_agree(gpu_lib):
+    o, v, nq = 10, 40, 120
+    say("[graph vs direct]")
+    prob, op, ctx = setup(I.Shape(o, v, nq), 16950, 1)
+    pulses = [I.Pulse(kind=I.PULSE_DELTA, e0=1e-4, direction=(0, 0, 1))]
+    ctx.set_tuning(use_graph=1, steps_per_graph=8)
+    g, _, _ = run_trace(gpu_lib, ctx, pulses, 0.05, 100, o, v)
+    ctx.set_tuning(use_graph=2)
+    d, _, _ = run_trace(gpu_lib, ctx, pulses, 0.05, 100, o, v)
+    assert np.array_equal(g, d)
+
+
+def test_zero_steps_returns_initial_sample(gpu_lib):
+    o, v, nq = 8, 20, 10
+    prob, op, ctx = setup(I.Shape(o, v, nq), 31, 1)
+    p = [I.Pulse(kind=I.PULSE_DELTA, e0=1e-3, direction=(0, 1, 0))]
+    got, c0d, cd = run_trace(gpu_lib, ctx, p, 0.05, 0, o, v)
+    ref, _, _ = O.propagate(op, p[0], 0.05, 0)
+    assert got.shape == (1, 1)
+    assert abs(got[0, 0] - ref[0]) < 1e-15
+
+
+def test_norm_guard_trips_on_unstable_step(gpu_lib):
+    """dt * rho(A) far above the RK4 stability limit 2.83: the guard reports a step."""
+    o, v, nq = 6, 10, 4
+    say("[guard]")
+    prob, op, ctx = setup(I.Shape(o, v, nq), 8, 1)
+    p = [I.Pulse(kind=I.PULSE_DELTA, e0=1e-2, direction=(0, 0, 1))]
+    run_trace(gpu_lib, ctx, p, 5.0, 60, o, v)
+    bad = ctx.guard()
+    assert bad > 0
+    run_trace(gpu_lib, ctx, p, 0.05, 60, o, v)
+    assert ctx.guard() == -1
+
+
+def test_invalid_arguments_rejected(gpu_lib):
+    import torch
+
+    o, v, nq = 4, 6, 2
+    prob, op, ctx = setup(I.Shape(o, v, nq), 3, 2)
+    c0d, cd = gpu_lib.ground_state(2, o, v)
+    p = [I.Pulse(kind=I.PULSE_DELTA, e0=1e-3, direction=(0, 0, 1))] * 2
+    with pytest.raises(gpu_lib.RttdaError) as e:
+        ctx.propagate(p, -0.1, 5, c0d, cd)
+    assert e.value.status == gpu_lib.E_INVAL
+    c0x, cx_ = gpu_lib.ground_state(3, o, v)
+    with pytest.raises(gpu_lib.RttdaError) as e:
+        ctx.propagate(p + p[:1], 0.05, 5, c0x, cx_)
+    assert e.value.status == gpu_lib.E_INVAL
+    with pytest.raises(gpu_lib.RttdaError):
+        ctx.dipole_trace([[0, 0, 1]] * 2, c0d, cd, out=torch.empty(3, dtype=torch.float64, device="cuda")[1:])
+
+
+def test_mixed_trace_parity_small(gpu_lib):
+    """Mixed precision (BF16 factors, split exchange): x/y/z kick traces within 1e-4 of the oracle."""
+    o, v, nq = 24, 96, 64
+    say("[mixed trace]")
+    shape = I.Shape(o, v, nq, b_scale=0.05, storage="bf16")
+    prob, op, ctx = setup(shape, 2024, 3, "mixed")
+    pulses = I.kick_pulses()
+    dt, n = 0.05, 400
+    got, _, _ = run_trace(gpu_lib, ctx, pulses, dt, n, o, v)
+    route = O.EigenRoute(op)
+    for r in range(3):
+        ref = route.propagate_field_free(pulses[r], dt, n)
+        err = rel_trace_err(got[:, r], ref)
+        say(f"   rhs {r}: trace rel err {err:.3e}")
+        assert err < 1e-4

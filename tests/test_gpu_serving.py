@@ -1,0 +1,68 @@
+"""Serving loop on the GPU: each request's trace is the same alone and in a mix (bitwise, the
+kernels use no atomics), admission respects the HBM budget, and a probe request matches the
+FP64 oracle (mixed-precision tolerance 1e-4)."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import rttda64 as O
+from paper_2601_16949_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def small_requests(n, seed=11, o_max=24):
+    reqs = I.serving_requests(n, rate=200.0, seed=seed, o_min=4, o_max=o_max)
+    for r in reqs:
+        r.n_steps = 60 + (r.rid * 37) % 90
+        if r.pulse.kind == I.PULSE_GAUSS:
+            r.pulse.t0 = 0.5 * r.n_steps * r.dt
+            r.pulse.fwhm = 2.0
+    return reqs
+
+
+def test_alone_equals_mix_and_budget(gpu_lib):
+    from paper_2601_16949_amd import serve
+
+    reqs = small_requests(8)
+    say("[serving] mix of 8")
+    srv = serve.Server(budget_bytes=2 << 30, chunk_steps=32, precision="mixed")
+    stats = srv.run(reqs, realtime=False)
+    say(f"   {stats}")
+    assert stats["max_concurrent"] >= 2
+    mix = {r.rid: srv.results[r.rid].trace for r in reqs}
+    for r in reqs[:3]:
+        alone = serve.Server(budget_bytes=2 << 30, chunk_steps=32, precision="mixed")
+        alone.run([r], realtime=False)
+        assert np.array_equal(alone.results[r.rid].trace, mix[r.rid]), r.rid
+    # a budget that fits only the largest request alone forces one-at-a-time service
+    big = max(serve.footprint(r.shape, r.n_steps, "mixed") for r in reqs)
+    tight = serve.Server(budget_bytes=big, chunk_steps=32, precision="mixed")
+    st2 = tight.run(reqs, realtime=False)
+    assert tight.peak_used <= big
+    for r in reqs:
+        assert np.array_equal(tight.results[r.rid].trace, mix[r.rid])
+    say(f"   tight budget: max_concurrent {st2['max_concurrent']}")
+
+
+def test_probe_request_matches_oracle(gpu_lib):
+    import torch
+    from paper_2601_16949_amd import serve
+
+    r = small_requests(3, seed=5, o_max=12)[0]
+    r.pulse = I.Pulse(kind=I.PULSE_GAUSS, e0=0.02, omega=0.5, t0=3.0, fwhm=2.0, direction=(0, 0, 1))
+    say(f"[serving probe] o={r.shape.o} v={r.shape.v} nq={r.shape.nq} steps={r.n_steps}")
+    srv = serve.Server(budget_bytes=1 << 30, chunk_steps=40, precision="mixed")
+    srv.run([r], realtime=False)
+    got = srv.results[r.rid].trace
+    t = I.make_device_tensors(r.shape, r.seed)
+    prob = I.problem_from_device(r.shape, r.seed, t)
+    ref, _, _ = O.propagate(O.Operator.from_problem(prob), r.pulse, r.dt, r.n_steps)
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    say(f"   trace rel err {err:.2e}")
+    assert err < 1e-4
