@@ -29,6 +29,14 @@ sys.path.insert(0, ROOT)
 from paper_2601_16949_amd import inputs as I  # noqa: E402
 
 AU_FS = 0.02418884326585747
+
+# HBM bytes per exchange launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs (KiB per dispatch,
+# scaled by the counters' readings for a plain 1 GiB copy: factors 2.0 and 1.0), keyed by
+# (variant, workload, splits); valid only while the kernel source hashes to `src`.
+TRAFFIC = {
+    ("f32_o64_ws1_wc2_kc16", "o60_v400_nq1500_kick_xyz", 119):
+        {"src": "13c2ccdc9a206c1c", "fetch_bytes": 516335.5 * 1024 * 2.0, "write_bytes": 69345.8 * 1024 * 1.0},
+}
 PEAK = {"fp32": 157.3, "mixed": 2516.6}  # dense MFMA TFLOP/s: FP32, BF16
 HBM_PEAK_GBS = 8000.0
 
@@ -51,6 +59,19 @@ def make_workload(name: str):
         wl.pulses = I.gauss_cos_scan(0.39, 0.05)
         return wl
     raise SystemExit(f"unknown workload {name}")
+
+
+def traffic_for(variant: str, workload: str, splits: int, precision: str):
+    import hashlib
+
+    e = TRAFFIC.get((variant, workload, splits))
+    if not e:
+        return None
+    src = os.path.join(ROOT, "paper_2601_16949_amd", "csrc",
+                       "exchange_f32.hip" if precision == "fp32" else "exchange_bf16.hip")
+    if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != e["src"]:
+        return None  # kernel changed since the counters were taken
+    return e["fetch_bytes"] + e["write_bytes"]
 
 
 def cpu_baseline(wl, prob, budget_s: float):
@@ -98,6 +119,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--variant", type=int, default=0)
     ap.add_argument("--splits", type=int, default=0)
+    ap.add_argument("--precision", default=None, help="override the workload's precision (fp32 | mixed)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is a design "
@@ -107,16 +131,32 @@ def main():
     import torch
     from paper_2601_16949_amd import rttda
 
+    if args.copy_probe:
+        n = args.copy_probe * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4, "dispatches": 5}))
+        return
     rttda.load()
     if not torch.cuda.is_available():
         raise SystemExit("no GPU visible")
     wl = make_workload(args.workload)
+    if args.precision and args.precision != wl.precision:
+        wl.precision = args.precision
+        wl.shape = I.Shape(wl.shape.o, wl.shape.v, wl.shape.nq, wl.shape.b_scale,
+                           storage="f32" if args.precision == "fp32" else "bf16")
     prob = I.make_problem(wl.shape, wl.seed)
     dev = rttda.DeviceProblem(prob, wl.precision)
     R = len(wl.pulses)
     ctx = rttda.Context(dev, max_rhs=R)
+    tuned = False
     if args.variant or args.splits:
         ctx.set_tuning(exchange_variant=args.variant, exchange_splits=args.splits)
+    else:
+        tuned = ctx.use_tuned(R)
     tun = ctx.get_tuning()
     c0, c = rttda.ground_state(R, prob.o, prob.v)
     ctx.propagate(wl.pulses, wl.dt, args.warmup, c0, c)
@@ -164,11 +204,14 @@ def main():
         "config": {"workload": wl.name, "o": o, "v": v, "n_aux": nq, "nrhs": R, "dt": wl.dt,
                    "precision": wl.precision, "exchange_variant": ctx.variant_name(tun["exchange_variant"]),
                    "exchange_splits": tun["exchange_splits"], "coulomb_splits": tun["coulomb_splits"],
+                   "autotuned": tuned,
                    "parallelism": "single GPU, RHS batched"},
         "fs_per_hour": round(fs_h, 3),
         "mfma_frac_step": round(value / 1e3 / peak, 4),
         "roofline": {"bound": "mfma", "kernel": "exchange", "achieved": round(achieved, 3), "peak": peak,
-                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                     "traffic": traffic_for(ctx.variant_name(tun["exchange_variant"]), wl.name,
+                                            tun["exchange_splits"], wl.precision),
                      "avg_launch_us": round(ex_avg_ms * 1e3, 2), "algorithmic_flops_per_launch": ex_flops},
         "kernels": breakdown,
         "guard_bad_step": bad,

@@ -379,7 +379,7 @@ def sigma_element(op: Operator, C_real: np.ndarray, i: int, a: int, d: np.ndarra
         d = np.einsum("qjb,jb->q", op.b_ov, C_real)
     diag = (op.e_virt[a] - op.e_occ[i]) * C_real[i, a]
     J = 2.0 * float(np.dot(op.b_ov[:, i, a], d))
-    # K_ia = sum_Q sum_j B_oo[Q,i,j] sum_b C[j,b] B_vv[Q,b,a]
-    t = np.einsum("qj,jb,qb->q", op.b_oo[:, i, :], C_real, op.b_vv[:, :, a])
-    K = float(t.sum())
+    # K_ia = sum_Q sum_b (sum_j B_oo[Q,i,j] C[j,b]) B_vv[Q,b,a]
+    t = op.b_oo[:, i, :] @ C_real  # (N_Q, v)
+    K = float(np.sum(t * op.b_vv[:, :, a]))
     return diag + J - op.cx * K

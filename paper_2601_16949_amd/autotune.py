@@ -37,6 +37,29 @@ def save_cache(cache: Dict[str, dict], path: str = DEFAULT_CACHE):
     os.replace(tmp, path)
 
 
+def variant_index(ctx, name: str) -> int:
+    """1-based index of the exchange variant called `name` in this build (0 if absent)."""
+    n = ctx.lib.rttda_exchange_variants(ctx.desc.precision)
+    for k in range(1, n + 1):
+        if ctx.variant_name(k) == name:
+            return k
+    return 0
+
+
+def apply(ctx, entry: dict) -> bool:
+    """Apply a cached (variant name, splits) choice; False if this build lacks the variant."""
+    k = variant_index(ctx, entry["name"])
+    if not k:
+        return False
+    splits = min(int(entry["splits"]), ctx.max_splits())
+    ctx.set_tuning(exchange_variant=k, exchange_splits=splits)
+    return True
+
+
+def lookup(ctx, nrhs: int, cache_path: str = DEFAULT_CACHE) -> Optional[dict]:
+    return load_cache(cache_path).get(_key(ctx, nrhs))
+
+
 def candidates(ctx, max_per_variant: int = 4) -> List[tuple]:
     """(variant, splits) pairs: every variant holding o, with splits around the library's default."""
     lib = ctx.lib
@@ -78,7 +101,7 @@ def tune(ctx, pulses, dt: float, nrhs: Optional[int] = None, steps: int = 3, cac
     cache = load_cache(cache_path) if use_cache else {}
     if key in cache:
         best = cache[key]
-        ctx.set_tuning(exchange_variant=best["variant"], exchange_splits=best["splits"])
+        apply(ctx, best)
         return best
     c0, c = rttda.ground_state(nrhs, ctx.o, ctx.v, device=ctx.device)
     results = []

@@ -44,7 +44,7 @@ rttda_status fail(rttda_status st, const char *fmt, ...) {
 
 constexpr int MAX_RHS = 4096;
 constexpr int SJ_MAX = 8;    // Coulomb second-product Q splits
-constexpr int SK_MAX = 96;   // exchange Q splits
+constexpr int SK_MAX = 192;  // exchange Q splits
 constexpr size_t ALIGN = 256;
 
 inline size_t up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
@@ -286,8 +286,8 @@ int auto_variant(int prec, int o, int ns, int v) {
 int auto_splits(const ExchangeVariant *x, int ns, int v, int nq, int cap) {
   const int tiles = ((ns + x->ks - 1) / x->ks) * ((v + x->nt - 1) / x->nt);
   const int cus = 256;
-  // aim at about two workgroups per CU, at least 4 Q per split
-  int s = (2 * cus + tiles - 1) / tiles;
+  // aim at about six rounds of one workgroup per CU (tail below ~15 %), at least 4 Q per split
+  int s = (6 * cus + tiles - 1) / tiles;
   s = std::min(s, std::max(1, nq / 4));
   s = std::max(1, std::min(s, cap));
   return s;

@@ -306,6 +306,17 @@ class Context:
         _check(self.lib.rttda_get_tuning(self.handle, ctypes.byref(t)))
         return {k: getattr(t, k) for k, _ in CTuning._fields_}
 
+    def max_splits(self) -> int:
+        """Largest exchange split count the workspace holds (min(192, N_Q))."""
+        return max(1, min(192, self.dev.nq))
+
+    def use_tuned(self, nrhs: int) -> bool:
+        """Apply the packaged autotune choice for (shape, nrhs) if there is one."""
+        from . import autotune
+
+        e = autotune.lookup(self, nrhs)
+        return bool(e) and autotune.apply(self, e)
+
     def set_profiling(self, on: bool):
         _check(self.lib.rttda_set_profiling(self.handle, 1 if on else 0))
 

@@ -46,7 +46,7 @@ MIXED_SIGMA_CASES = [
     (10, 40, 120, 1),
     (60, 400, 40, 3),
     (33, 70, 9, 2),
-    (240, 64, 3, 1),
+    (160, 64, 3, 1),
     (130, 96, 5, 2),
     (7, 13, 4, 3),
 ]
@@ -246,3 +246,146 @@ def test_mixed_trace_parity_small(gpu_lib):
         err = rel_trace_err(got[:, r], ref)
         say(f"   rhs {r}: trace rel err {err:.3e}")
         assert err < 1e-4
+
+
+def _golden_peaks(name):
+    import os
+
+    path = os.path.join(os.path.dirname(__file__), "golden", f"{name}_kick_peaks.txt")
+    rows = [ln.split() for ln in open(path) if ln.strip() and not ln.startswith("#")]
+    out = {}
+    for r, w, h in rows:
+        out.setdefault(int(r), []).append((float(w), float(h)))
+    return out
+
+
+def test_cfg1_spectrum_peaks_match_oracle(gpu_lib):
+    """Kick spectrum of the full cfg1 trace: every peak of the oracle's trace (FP64 eigen route,
+    full trace including its O(kappa^2) part) is found in the GPU spectrum within 1e-5 Ha (same
+    post-processing on both traces)."""
+    from oracle import spectrum as S
+
+    wl = I.workload(1)
+    say("[cfg1 spectrum]")
+    prob, op, ctx = setup(wl.shape, wl.seed, 1)
+    got, _, _ = run_trace(gpu_lib, ctx, wl.pulses, wl.dt, wl.n_steps, wl.shape.o, wl.shape.v)
+    pk = S.peaks(got[:, 0], wl.dt, wl.pulses[0].e0, rel_height=0.05, omega_max=8.0)
+    ref = O.EigenRoute(op).propagate_field_free(wl.pulses[0], wl.dt, wl.n_steps)
+    gold = S.peaks(ref, wl.dt, wl.pulses[0].e0, rel_height=0.05, omega_max=8.0)
+    worst = max(min(abs(p - w) for p, _ in pk) for w, _ in gold)
+    say(f"   {len(gold)} oracle peaks, {len(pk)} GPU peaks, worst position error {worst:.2e} Ha")
+    assert worst < 1e-5
+
+
+def test_isolated_kick_peaks_at_eigenvalues(gpu_lib):
+    """Tiny instance, long run: GPU kick-spectrum peaks sit at the RK4-modified eigenvalues of A
+    (oracle eigh) within 1e-5 Ha."""
+    from oracle import spectrum as S
+
+    o, v, nq = 2, 3, 2
+    say("[isolated peaks]")
+    shape = I.Shape(o, v, nq, b_scale=0.2, rescale=False)
+    prob, op, ctx = setup(shape, 7, 1)
+    kappa, dt, n = 1e-4, 0.2, 100000
+    p = [I.Pulse(kind=I.PULSE_DELTA, e0=kappa, direction=(0, 0, 1))]
+    got, _, _ = run_trace(gpu_lib, ctx, p, dt, n, o, v)
+    route = O.EigenRoute(op)
+    wI = route.w[1:]
+    strength = wI * route.dipole_eig((0, 0, 1))[0, 1:] ** 2
+    wt = -np.angle(O.rk4_amplification(-1j * wI * dt)) / dt
+    pk = S.peaks(got[:, 0], dt, kappa, rel_height=0.05, refine=True)
+    for w, s in zip(wt, strength):
+        if s >= 0.1 * strength.max():
+            d = min(abs(q - w) for q, _ in pk)
+            say(f"   eig {w:.8f}: nearest GPU peak {d:.2e} Ha away")
+            assert d < 1e-5
+
+
+def test_bench_shape_sigma_sampled(gpu_lib):
+    """Full bench shape (o60 v400 N_Q1500, 3 RHS, bench launch configuration): sigma on a kicked
+    and briefly propagated state, checked element by element against the oracle at 96 sampled
+    (i, a) per RHS and plane; then 2 RK4 steps of the trace against the oracle's direct route."""
+    import torch
+
+    wl = I.workload(2)
+    say(f"[bench shape sampled] {wl.name}")
+    prob, op, ctx = setup(wl.shape, wl.seed, 3)
+    c0d, cd = gpu_lib.ground_state(3, wl.shape.o, wl.shape.v)
+    tr = ctx.propagate(wl.pulses, wl.dt, 2, c0d, cd)
+    torch.cuda.synchronize()
+    c0, c = gpu_lib.from_planes(c0d, cd)
+    # trace of the first 2 steps against the oracle (kick + 2 RK4 steps per RHS)
+    for r in range(3):
+        ref, _, _ = O.propagate(op, wl.pulses[r], wl.dt, 2)
+        err = rel_trace_err(tr.cpu().numpy()[:, r], ref)
+        say(f"   rhs {r}: 2-step trace rel err {err:.2e}")
+        assert err < 1e-5
+    s0d, sd = ctx.sigma([0.0, 0.0, 0.0], np.eye(3), c0d, cd)
+    torch.cuda.synchronize()
+    _, s = gpu_lib.from_planes(s0d, sd)
+    rng = np.random.default_rng(17)
+    for r in range(3):
+        for part, C in (("re", c[r].real.copy()), ("im", c[r].imag.copy())):
+            S_ = s[r].real if part == "re" else s[r].imag
+            d = np.einsum("qjb,jb->q", op.b_ov, C)
+            idx = list(zip(rng.integers(0, wl.shape.o, 96), rng.integers(0, wl.shape.v, 96)))
+            ref = np.array([O.sigma_element(op, C, i, a, d) for i, a in idx])
+            got = np.array([S_[i, a] for i, a in idx])
+            err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+            say(f"   rhs {r} {part}: sampled sigma rel err {err:.2e}")
+            assert err < 5e-6
+
+
+def test_pulse_scan_batch_64_rhs(gpu_lib):
+    """cfg4 shape (o40 v300 N_Q1000), 64 Gaussian-cos carriers in one launch: the first 10 steps of
+    8 RHS spread over the batch match the oracle (trace 1e-5, populations |c0|^2 and sum |c_ia|^2
+    within 1e-5 absolute)."""
+    import torch
+
+    wl = I.workload(4)
+    say(f"[cfg4 64 RHS] {wl.name}")
+    pulses = I.gauss_cos_scan(0.39, 0.05)
+    for p in pulses:  # centre the envelope near t = 0 so the field is strong in the first steps
+        p.t0 = 0.3
+    prob, op, ctx = setup(wl.shape, wl.seed, 64)
+    c0d, cd = gpu_lib.ground_state(64, wl.shape.o, wl.shape.v)
+    n = 10
+    tr = ctx.propagate(pulses, wl.dt, n, c0d, cd)
+    torch.cuda.synchronize()
+    got = tr.cpu().numpy()
+    c0g, cg = gpu_lib.from_planes(c0d, cd)
+    for r in range(0, 64, 9):
+        ref, c0f, Cf = O.propagate(op, pulses[r], wl.dt, n)
+        err = rel_trace_err(got[:, r], ref)
+        p0 = abs(abs(c0g[r]) ** 2 - abs(c0f) ** 2)
+        pe = abs(np.sum(np.abs(cg[r]) ** 2) - np.sum(np.abs(Cf) ** 2))
+        say(f"   rhs {r}: trace {err:.2e}, |c0|^2 {p0:.1e}, sum|c|^2 {pe:.1e}")
+        assert err < 1e-5 and p0 < 1e-5 and pe < 1e-5
+
+
+def test_cfg2_full_run_spectrum_peaks(gpu_lib):
+    """Full cfg2 run (o60 v400 N_Q1500, x/y/z kicks as 3 RHS, 20000 steps of dt 0.05): every oracle
+    peak (golden file written by tests/golden/make_kick_spectrum.py from the FP64 eigen route) is
+    found in the GPU spectrum of the same direction within 1e-5 Ha."""
+    import torch
+    from oracle import spectrum as S
+
+    wl = I.workload(2)
+    say(f"[cfg2 full spectrum] {wl.name}")
+    prob, op, ctx = setup(wl.shape, wl.seed, 3)
+    c0d, cd = gpu_lib.ground_state(3, wl.shape.o, wl.shape.v)
+    trace = torch.empty((wl.n_steps + 1, 3), dtype=torch.float64, device="cuda")
+    chunk = 2000
+    for k0 in range(0, wl.n_steps, chunk):
+        n = min(chunk, wl.n_steps - k0)
+        ctx.propagate(wl.pulses, wl.dt, n, c0d, cd, step0=k0, trace=trace[k0:k0 + n + 1])
+        torch.cuda.synchronize()
+        say(f"   steps {k0 + n}/{wl.n_steps}")
+    assert ctx.guard() == -1
+    got = trace.cpu().numpy()
+    gold = _golden_peaks("cfg2")
+    for r in range(3):
+        pk = S.peaks(got[:, r], wl.dt, wl.pulses[r].e0, rel_height=0.05, omega_max=8.0)
+        worst = max(min(abs(p - w) for p, _ in pk) for w, _ in gold[r])
+        say(f"   direction {r}: {len(gold[r])} oracle peaks, {len(pk)} GPU peaks, worst {worst:.2e} Ha")
+        assert worst < 1e-5
