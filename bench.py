@@ -109,6 +109,32 @@ def cpu_baseline(wl, prob, budget_s: float):
             "sample": f"{steps} RK4 steps x {R} RHS of {wl.name} ({el:.1f} s)", "fs_per_hour": round(fs_h, 4)}
 
 
+def short_leg(wl, precision: str, pulses, steps: int, warmup: int = 5):
+    """Aggregate fs/hour and sigma GFLOP/s of a short timed run (comparison legs)."""
+    import torch
+    from paper_2601_16949_amd import rttda
+
+    shape = I.Shape(wl.shape.o, wl.shape.v, wl.shape.nq, wl.shape.b_scale,
+                    storage="f32" if precision == "fp32" else "bf16")
+    prob = I.make_problem(shape, wl.seed)
+    R = len(pulses)
+    ctx = rttda.Context(rttda.DeviceProblem(prob, precision), max_rhs=R)
+    tuned = ctx.use_tuned(R)
+    c0, c = rttda.ground_state(R, prob.o, prob.v)
+    ctx.propagate(pulses, wl.dt, warmup, c0, c, want_trace=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.propagate(pulses, wl.dt, steps, c0, c, step0=warmup)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    fc, fx = flops_per_sigma(prob.o, prob.v, prob.nq)
+    tun = ctx.get_tuning()
+    return {"precision": precision, "nrhs": R, "steps": steps, "ms_per_step": round(1e3 * el / steps, 4),
+            "fs_per_hour": round(steps * wl.dt * AU_FS * R / (el / 3600.0), 3),
+            "sigma_gflops": round(steps * 4 * R * (fc + fx) / el / 1e9, 2),
+            "exchange_variant": ctx.variant_name(tun["exchange_variant"]), "autotuned": tuned}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,6 +142,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="cfg2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true", help="skip the mixed vs FP32 single-solve legs")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--variant", type=int, default=0)
     ap.add_argument("--splits", type=int, default=0)
@@ -217,6 +244,16 @@ def main():
         "guard_bad_step": bad,
         "trace_finite": bool(torch.isfinite(trace).all().item()),
     }
+    if not args.no_compare and args.workload == "cfg2":
+        # batched mixed precision (3 RHS, BF16 factors, split exchange) against the plain FP32
+        # single solve (1 RHS) on the same shape; the accuracy of the mixed path against the FP64
+        # oracle (trace <= 1e-4) is checked by the parity tests
+        del ctx, dev
+        torch.cuda.empty_cache()
+        single = short_leg(wl, "fp32", wl.pulses[:1], 100)
+        mixed = short_leg(wl, "mixed", wl.pulses, 200)
+        out["mixed_vs_fp32_single"] = {"fp32_single": single, "mixed_batched": mixed,
+                                       "ratio_fs_per_hour": round(mixed["fs_per_hour"] / single["fs_per_hour"], 3)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, prob, args.cpu_budget)
     print(json.dumps(out), flush=True)

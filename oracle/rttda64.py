@@ -376,10 +376,23 @@ class EigenRoute:
 def sigma_element(op: Operator, C_real: np.ndarray, i: int, a: int, d: np.ndarray = None) -> float:
     """(A C)_ia for one (i, a) of a real C, by direct sums over Q, j, b."""
     if d is None:
-        d = np.einsum("qjb,jb->q", op.b_ov, C_real)
-    diag = (op.e_virt[a] - op.e_occ[i]) * C_real[i, a]
-    J = 2.0 * float(np.dot(op.b_ov[:, i, a], d))
-    # K_ia = sum_Q sum_b (sum_j B_oo[Q,i,j] C[j,b]) B_vv[Q,b,a]
-    t = op.b_oo[:, i, :] @ C_real  # (N_Q, v)
-    K = float(np.sum(t * op.b_vv[:, :, a]))
-    return diag + J - op.cx * K
+        d = coulomb_contraction(op.b_ov, C_real)
+    return sigma_element_from_slices(op.e_occ[i], op.e_virt[a], C_real, i, a, op.b_ov[:, i, a], d,
+                                     op.b_oo[:, i, :], op.b_vv[:, :, a], op.cx)
+
+
+def coulomb_contraction(b_ov: np.ndarray, C_real: np.ndarray) -> np.ndarray:
+    """d_Q = sum_jb B^Q_jb C_jb."""
+    return np.einsum("qjb,jb->q", np.asarray(b_ov, dtype=np.float64), C_real)
+
+
+def sigma_element_from_slices(e_i, e_a, C_real, i, a, b_ov_ia, d, b_oo_i, b_vv_a, cx) -> float:
+    """(A C)_ia from the slices of the factors it needs: B^Q_ia (N_Q,), d_Q (N_Q,),
+    B^Q_i. (N_Q, o) and B^Q_.a (N_Q, v).  K_ia = sum_Q sum_b (sum_j B_oo[Q,i,j] C[j,b]) B_vv[Q,b,a]."""
+    b_oo_i = np.asarray(b_oo_i, dtype=np.float64)
+    b_vv_a = np.asarray(b_vv_a, dtype=np.float64)
+    diag = (e_a - e_i) * C_real[i, a]
+    J = 2.0 * float(np.dot(np.asarray(b_ov_ia, dtype=np.float64), d))
+    t = b_oo_i @ C_real  # (N_Q, v)
+    K = float(np.sum(t * b_vv_a))
+    return diag + J - cx * K

@@ -91,6 +91,10 @@ struct ExchangeVariant {
                        int v, int nq, int ns, int nsplit, float scale, float *P);
   size_t lds_bytes;
   hipError_t (*prepare)();  // one-time kernel attributes (dynamic LDS size); call outside graph capture
+  int v_min = 1;            // applicability: v >= v_min, v % v_mod == 0, o % o_mod == 0
+  int v_mod = 1;
+  int o_mod = 1;
+  bool applies(int o, int v) const { return o <= o16 && v >= v_min && v % v_mod == 0 && o % o_mod == 0; }
 };
 
 }  // namespace rttda

@@ -1,0 +1,318 @@
+// Exchange contraction, split BF16 precision, with direct global->LDS loads (gfx950
+// global_load_lds): same arithmetic as exchange_bf16.hip (X = X_hi + X_lo, W = X B_vv^Q in FP32
+// accumulators of v_mfma_f32_32x32x16_bf16, W split into hi/lo for K += B_oo^Q W), same data
+// path as exchange_f32_dl.hip:
+//  * the X_hi, X_lo and B_vv tiles of a 32-wide K chunk go from global memory straight into one
+//    of three LDS buffers (16 bytes per lane); chunk c+2 is in flight while chunk c is multiplied;
+//  * the B_oo^Q tile goes into LDS with the 4-byte form (rows of o bf16 need only o even);
+//  * every lane of every load instruction is active (out-of-range lanes read a zero page) so the
+//    explicit vmcnt waits count exactly; the workgroup barrier waits only for LDS reads;
+//  * 16-byte chunks of the 64-byte LDS rows are XOR-swizzled with row bits so that the operand
+//    reads (rows m = 0..31 at one logical chunk) spread over the banks.
+#include <type_traits>
+
+#include "common.h"
+
+namespace rttda {
+namespace {
+
+typedef float f16v __attribute__((ext_vector_type(16)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) void lds_void;
+
+__device__ __attribute__((aligned(256))) unsigned int g_zero_page_b[64];  // 256 zero bytes
+
+constexpr int KC = 32;  // bf16 per chunk row: 64 bytes = four 16-byte chunks
+
+__device__ __forceinline__ int swz(int r) { return (r >> 1) & 3; }
+__device__ __forceinline__ int swz_o(int i) { return i & 3; }
+
+__device__ __forceinline__ void dma16(const void *src, void *lds_base) {
+  __builtin_amdgcn_global_load_lds(src, (lds_void *)lds_base, 16, 0, 0);
+}
+__device__ __forceinline__ void dma4(const void *src, void *lds_base) {
+  __builtin_amdgcn_global_load_lds(src, (lds_void *)lds_base, 4, 0, 0);
+}
+
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
+
+// LDS reads of this wave are done; loads of later chunks stay in flight (see exchange_f32_dl.hip)
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_s_waitcnt(0xF | (7 << 4) | (0 << 8) | (3 << 14));
+  asm volatile("s_barrier" ::: "memory");
+}
+
+__device__ __forceinline__ f16v zero16() {
+  f16v z;
+#pragma unroll
+  for (int t = 0; t < 16; ++t) z[t] = 0.f;
+  return z;
+}
+
+template <int O32, int WS, int WC>
+struct CfgBD {
+  static constexpr int KS = 2 * WS, NT = 64 * WC, JB = O32 / 32;
+  static constexpr int XROWS = KS * O32;
+  static constexpr int NXW = XROWS / 64;  // per plane: 16-byte load instructions per wave
+  static constexpr int NBW = NT / 64;
+  static constexpr int ODW = O32 * O32 / 2;            // dwords of the B_oo tile
+  static constexpr int NOW = (ODW + 255) / 256;        // 4-byte load instructions per wave
+  static constexpr int XS = XROWS * KC, BS = NT * KC;  // bf16 per buffer and plane
+  static constexpr int OS = NOW * 256 * 2;             // bf16 (padded to whole instructions)
+  static constexpr size_t LDS = (size_t)(3 * (2 * XS + BS) + OS) * 2;
+  static_assert(XROWS % 64 == 0 && NT % 64 == 0, "tile must split into whole load instructions");
+};
+
+template <int O32, int WS, int WC>
+__global__ __launch_bounds__(256, 2) void k_exchange_bf16_dl(const __bf16 *__restrict__ Boo,
+                                                             const __bf16 *__restrict__ Bvv,
+                                                             const __bf16 *__restrict__ Xh,
+                                                             const __bf16 *__restrict__ Xl, int o, int v, int nq,
+                                                             int ns, int n_sg, int n_ct, int nsplit, float scale,
+                                                             float *__restrict__ P) {
+  using C = CfgBD<O32, WS, WC>;
+  constexpr int JB = C::JB, NXW = C::NXW, NBW = C::NBW, NOW = C::NOW, NXB = 2 * NXW + NBW;
+  extern __shared__ __attribute__((aligned(16))) __bf16 ldsbd[];
+  __bf16 *Xh0 = ldsbd;               // [3][XROWS][32]
+  __bf16 *Xl0 = Xh0 + 3 * C::XS;     // [3][XROWS][32]
+  __bf16 *Bs0 = Xl0 + 3 * C::XS;     // [3][NT][32]
+  __bf16 *Os = Bs0 + 3 * C::BS;      // [O32][O32] (+ padding)
+
+  const int total = n_sg * n_ct * nsplit;
+  const int per_xcd = (int)gridDim.x / 8;
+  const int lb = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
+  if (lb >= total) return;
+  const int sg = lb % n_sg;
+  const int ct = (lb / n_sg) % n_ct;
+  const int sp = lb / (n_sg * n_ct);
+  const int qa = (int)((long long)sp * nq / nsplit), qb = (int)((long long)(sp + 1) * nq / nsplit);
+  const int s_base = sg * C::KS, c_base = ct * C::NT;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int h = lane >> 5, m = lane & 31;
+  const int ws = wave >> 1, wc = wave & 1;
+  const int nkc = (v + KC - 1) / KC;
+  const int NC = (qb - qa) * nkc;
+  int nvalid = 0;
+#pragma unroll
+  for (int cb = 0; cb < WC; ++cb) nvalid += (c_base + (wc * WC + cb) * 32 < v) ? 1 : 0;
+  const int lrow = lane >> 2;
+
+  auto issue = [&](int c) {
+    const int q = qa + c / nkc, kc = c % nkc, a0 = kc * KC;
+    const int buf = c % 3;
+#pragma unroll
+    for (int k = 0; k < NXW; ++k) {
+      const int r0 = (wave * NXW + k) * 16, r = r0 + lrow;
+      const int a = a0 + 8 * ((lane & 3) ^ swz(r));
+      const int sl = s_base + r / O32, j = r % O32;
+      const bool ok = sl < ns && j < o && a < v;
+      const size_t off = ((size_t)sl * o + j) * v + a;
+      dma16(ok ? (const void *)(Xh + off) : (const void *)g_zero_page_b, Xh0 + buf * C::XS + r0 * KC);
+      dma16(ok ? (const void *)(Xl + off) : (const void *)g_zero_page_b, Xl0 + buf * C::XS + r0 * KC);
+    }
+    const __bf16 *Vq = Bvv + (size_t)q * v * v;
+#pragma unroll
+    for (int k = 0; k < NBW; ++k) {
+      const int r0 = (wave * NBW + k) * 16, r = r0 + lrow;
+      const int a = a0 + 8 * ((lane & 3) ^ swz(r));
+      const int cc = c_base + r;
+      const bool ok = cc < v && a < v;
+      dma16(ok ? (const void *)(Vq + (size_t)cc * v + a) : (const void *)g_zero_page_b,
+              Bs0 + buf * C::BS + r0 * KC);
+    }
+  };
+  auto issue_os = [&](int q) {
+    const __bf16 *Oq = Boo + (size_t)q * o * o;
+#pragma unroll
+    for (int k = 0; k < NOW; ++k) {
+      const int d0 = (wave * NOW + k) * 64, d = d0 + lane;  // dword index in the tile
+      const int i = d / (O32 / 2), w = d % (O32 / 2);
+      const int jl = 2 * (4 * ((w >> 2) ^ swz_o(i)) + (w & 3));  // logical column (bf16)
+      const bool ok = d < C::ODW && i < o && jl < o;
+      dma4(ok ? (const void *)(Oq + (size_t)i * o + jl) : (const void *)g_zero_page_b, Os + 2 * d0);
+    }
+  };
+
+  f16v Kacc[WS][JB][WC], Wacc[WS][JB][WC];
+#pragma unroll
+  for (int a = 0; a < WS; ++a)
+#pragma unroll
+    for (int b = 0; b < JB; ++b)
+#pragma unroll
+      for (int c = 0; c < WC; ++c) {
+        Kacc[a][b][c] = zero16();
+        Wacc[a][b][c] = zero16();
+      }
+
+  // B_oo row i, logical columns j .. j+3 (one 8-byte half of a swizzled 16-byte chunk)
+  auto os4 = [&](int i, int j) -> bf4 {
+    const int ch = (j >> 3) ^ swz_o(i);
+    return *reinterpret_cast<const bf4 *>(&Os[i * O32 + 8 * ch + (j & 7)]);
+  };
+
+  auto compute_n = [&](auto ncb_tag, int c) {
+    constexpr int NCB = decltype(ncb_tag)::value;
+    const int kc = c % nkc, buf = c % 3;
+    const __bf16 *Xhs = Xh0 + buf * C::XS;
+    const __bf16 *Xls = Xl0 + buf * C::XS;
+    const __bf16 *Bs = Bs0 + buf * C::BS;
+    const int klim = v - kc * KC;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {  // two MFMA K steps of 16 per chunk
+      if (16 * u < klim) {
+        bf8 bf[WC];
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+          const int r = (wc * WC + cb) * 32 + m;
+          bf[cb] = *reinterpret_cast<const bf8 *>(&Bs[r * KC + 8 * ((2 * u + h) ^ swz(r))]);
+        }
+#pragma unroll
+        for (int si = 0; si < WS; ++si)
+#pragma unroll
+          for (int jb = 0; jb < JB; ++jb) {
+            const int r = (ws * WS + si) * O32 + jb * 32 + m;
+            const int co = r * KC + 8 * ((2 * u + h) ^ swz(r));
+            const bf8 ah = *reinterpret_cast<const bf8 *>(&Xhs[co]);
+            const bf8 al = *reinterpret_cast<const bf8 *>(&Xls[co]);
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) {
+              Wacc[si][jb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bf[cb], Wacc[si][jb][cb], 0, 0, 0);
+              Wacc[si][jb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bf[cb], Wacc[si][jb][cb], 0, 0, 0);
+            }
+          }
+      }
+    }
+    if (kc == nkc - 1) {
+#pragma unroll
+      for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          bf8 wh[WS][WC], wl[WS][WC];
+#pragma unroll
+          for (int si = 0; si < WS; ++si)
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+              for (int e = 0; e < 8; ++e) {
+                const float w = Wacc[si][jb][cb][8 * u + e];
+                const __bf16 hi = (__bf16)w;
+                wh[si][cb][e] = hi;
+                wl[si][cb][e] = (__bf16)(w - (float)hi);
+              }
+          const int j0 = jb * 32 + 16 * u + 4 * h;
+#pragma unroll
+          for (int ib = 0; ib < JB; ++ib) {
+            const int i = ib * 32 + m;
+            const bf4 lo4 = os4(i, j0), hi4 = os4(i, j0 + 8);
+            const bf8 ar = bf8{lo4[0], lo4[1], lo4[2], lo4[3], hi4[0], hi4[1], hi4[2], hi4[3]};
+#pragma unroll
+            for (int si = 0; si < WS; ++si)
+#pragma unroll
+              for (int cb = 0; cb < NCB; ++cb) {
+                Kacc[si][ib][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar, wh[si][cb], Kacc[si][ib][cb], 0, 0, 0);
+                Kacc[si][ib][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar, wl[si][cb], Kacc[si][ib][cb], 0, 0, 0);
+              }
+          }
+        }
+#pragma unroll
+      for (int a = 0; a < WS; ++a)
+#pragma unroll
+        for (int b = 0; b < JB; ++b)
+#pragma unroll
+          for (int cc = 0; cc < WC; ++cc) Wacc[a][b][cc] = zero16();
+    }
+  };
+  auto compute = [&](int c) {
+    if (nvalid == WC)
+      compute_n(std::integral_constant<int, WC>{}, c);
+    else if (WC > 1 && nvalid == 1)
+      compute_n(std::integral_constant<int, 1>{}, c);
+  };
+
+  if (NC > 0) {
+    issue_os(qa);
+    issue(0);
+    if (NC > 1) {
+      issue(1);
+      wait_vm<NXB>();
+    } else {
+      wait_vm<0>();
+    }
+    lds_barrier();
+  }
+  for (int c = 0; c < NC; ++c) {
+    const bool os_now = (c > 0) && (c % nkc == 0);
+    const bool more = c + 2 < NC;
+    if (os_now) issue_os(qa + c / nkc);
+    if (more) issue(c + 2);
+    compute(c);
+    if (os_now) {
+      if (more) wait_vm<NOW + NXB>(); else wait_vm<NOW>();
+    } else {
+      if (more) wait_vm<NXB>(); else wait_vm<0>();
+    }
+    lds_barrier();
+  }
+
+  float *Pp = P + (size_t)sp * ns * o * v;
+#pragma unroll
+  for (int si = 0; si < WS; ++si) {
+    const int sl = s_base + ws * WS + si;
+    if (sl >= ns) continue;
+#pragma unroll
+    for (int ib = 0; ib < JB; ++ib)
+#pragma unroll
+      for (int cb = 0; cb < WC; ++cb) {
+        const int c = c_base + (wc * WC + cb) * 32 + m;
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+          const int i = ib * 32 + 8 * (t / 4) + 4 * h + (t % 4);
+          if (i < o && c < v) Pp[((size_t)sl * o + i) * v + c] = scale * Kacc[si][ib][cb][t];
+        }
+      }
+  }
+}
+
+template <int O32, int WS, int WC>
+hipError_t launch_xbf16dl(hipStream_t s, const void *Boo, const void *Bvv, const void *X, const void *Xlo, int o,
+                          int v, int nq, int ns, int nsplit, float scale, float *P) {
+  using C = CfgBD<O32, WS, WC>;
+  if (o > O32 || (v & 7) != 0 || (o & 1) != 0 || v < 3 * KC) return hipErrorInvalidValue;
+  const int n_sg = (ns + C::KS - 1) / C::KS, n_ct = (v + C::NT - 1) / C::NT;
+  const int total = n_sg * n_ct * nsplit;
+  dim3 grid((total + 7) / 8 * 8);
+  hipLaunchKernelGGL((k_exchange_bf16_dl<O32, WS, WC>), grid, dim3(256), C::LDS, s, static_cast<const __bf16 *>(Boo),
+                     static_cast<const __bf16 *>(Bvv), static_cast<const __bf16 *>(X),
+                     static_cast<const __bf16 *>(Xlo), o, v, nq, ns, n_sg, n_ct, nsplit, scale, P);
+  return hipGetLastError();
+}
+
+template <int O32, int WS, int WC>
+hipError_t prepare_xbf16dl() {
+  return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_exchange_bf16_dl<O32, WS, WC>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)CfgBD<O32, WS, WC>::LDS);
+}
+
+#define XBD(O32, WS, WC)                                                                                    \
+  ExchangeVariant {                                                                                         \
+    RTTDA_PREC_MIXED_BF16, O32, CfgBD<O32, WS, WC>::KS, CfgBD<O32, WS, WC>::NT,                             \
+        "bf16x2dl_o" #O32 "_ws" #WS "_wc" #WC, &launch_xbf16dl<O32, WS, WC>, CfgBD<O32, WS, WC>::LDS,      \
+        &prepare_xbf16dl<O32, WS, WC>, 3 * KC, 8, 2                                                         \
+  }
+
+const ExchangeVariant kBf16DlVariants[] = {
+    XBD(32, 1, 1), XBD(32, 2, 1), XBD(64, 1, 1), XBD(64, 1, 2), XBD(64, 2, 1),
+};
+
+}  // namespace
+
+int exchange_bf16dl_variant_count() { return (int)(sizeof(kBf16DlVariants) / sizeof(kBf16DlVariants[0])); }
+const ExchangeVariant *exchange_bf16dl_variant(int k) { return &kBf16DlVariants[k]; }
+
+}  // namespace rttda

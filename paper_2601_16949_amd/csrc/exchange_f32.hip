@@ -71,6 +71,10 @@ __global__ __launch_bounds__(256, 1) void k_exchange_f32(const float *__restrict
   const bool vec = (v & 3) == 0;
   const int nkc = (v + KC - 1) / KC;
   const int NC = (qb - qa) * nkc;
+  // column blocks entirely beyond v (last column tile) skip their MFMAs (wave-uniform)
+  bool cvalid[WC];
+#pragma unroll
+  for (int cb = 0; cb < WC; ++cb) cvalid[cb] = c_base + (wc * WC + cb) * 16 < v;
 
   struct Regs {
     f4 x[C::XR], b[C::BR];
@@ -202,8 +206,9 @@ __global__ __launch_bounds__(256, 1) void k_exchange_f32(const float *__restrict
             for (int jb = 0; jb < JB; ++jb)
 #pragma unroll
               for (int cb = 0; cb < WC; ++cb)
-                Wacc[si][jb][cb] =
-                    __builtin_amdgcn_mfma_f32_16x16x4f32(af[si][jb][t], bf[cb][t], Wacc[si][jb][cb], 0, 0, 0);
+                if (cvalid[cb])
+                  Wacc[si][jb][cb] =
+                      __builtin_amdgcn_mfma_f32_16x16x4f32(af[si][jb][t], bf[cb][t], Wacc[si][jb][cb], 0, 0, 0);
       }
     }
     if (kc == nkc - 1) {
@@ -240,8 +245,9 @@ __global__ __launch_bounds__(256, 1) void k_exchange_f32(const float *__restrict
             for (int si = 0; si < WS; ++si)
 #pragma unroll
               for (int cb = 0; cb < WC; ++cb)
-                Kacc[si][ib][cb] =
-                    __builtin_amdgcn_mfma_f32_16x16x4f32(ar[ib][t], Wacc[si][jb][cb][t], Kacc[si][ib][cb], 0, 0, 0);
+                if (cvalid[cb])
+                  Kacc[si][ib][cb] =
+                      __builtin_amdgcn_mfma_f32_16x16x4f32(ar[ib][t], Wacc[si][jb][cb][t], Kacc[si][ib][cb], 0, 0, 0);
       }
 #pragma unroll
       for (int a = 0; a < WS; ++a)

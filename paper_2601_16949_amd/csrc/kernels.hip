@@ -390,8 +390,23 @@ __global__ __launch_bounds__(256) void k_epilogue(int R, int o, int v, int nslab
     const size_t i0 = r * 2 * ov + ia, i1 = i0 + ov;
     const double x0 = Xin[i0], x1 = Xin[i1];
     const double d = D[ia];
+    // partial slabs: eight independent loads in flight per plane, summed in a fixed order
     double p0 = 0.0, p1 = 0.0;
-    for (int sl = 0; sl < nslab; ++sl) {
+    int sl = 0;
+    for (; sl + 8 <= nslab; sl += 8) {
+      float a[8], b[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        a[u] = P[(sl + u) * slab + i0];
+        b[u] = P[(sl + u) * slab + i1];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        p0 += (double)a[u];
+        p1 += (double)b[u];
+      }
+    }
+    for (; sl < nslab; ++sl) {
       p0 += (double)P[sl * slab + i0];
       p1 += (double)P[sl * slab + i1];
     }

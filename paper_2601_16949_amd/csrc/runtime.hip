@@ -14,6 +14,10 @@ int exchange_f32_variant_count();
 const ExchangeVariant *exchange_f32_variant(int k);
 int exchange_bf16_variant_count();
 const ExchangeVariant *exchange_bf16_variant(int k);
+int exchange_f32dl_variant_count();
+const ExchangeVariant *exchange_f32dl_variant(int k);
+int exchange_bf16dl_variant_count();
+const ExchangeVariant *exchange_bf16dl_variant(int k);
 }  // namespace rttda
 
 using namespace rttda;
@@ -165,12 +169,23 @@ struct GraphEntry {
   hipGraphExec_t exec = nullptr;
 };
 
+// Variant tables: register-staged variants first, then direct-to-LDS variants
 const ExchangeVariant *variant_of(int prec, int k) {
-  if (prec == RTTDA_PREC_FP32) return (k >= 0 && k < exchange_f32_variant_count()) ? exchange_f32_variant(k) : nullptr;
-  return (k >= 0 && k < exchange_bf16_variant_count()) ? exchange_bf16_variant(k) : nullptr;
+  if (k < 0) return nullptr;
+  if (prec == RTTDA_PREC_FP32) {
+    const int n1 = exchange_f32_variant_count();
+    if (k < n1) return exchange_f32_variant(k);
+    k -= n1;
+    return k < exchange_f32dl_variant_count() ? exchange_f32dl_variant(k) : nullptr;
+  }
+  const int n2 = exchange_bf16_variant_count();
+  if (k < n2) return exchange_bf16_variant(k);
+  k -= n2;
+  return k < exchange_bf16dl_variant_count() ? exchange_bf16dl_variant(k) : nullptr;
 }
 int variant_count(int prec) {
-  return prec == RTTDA_PREC_FP32 ? exchange_f32_variant_count() : exchange_bf16_variant_count();
+  return prec == RTTDA_PREC_FP32 ? exchange_f32_variant_count() + exchange_f32dl_variant_count()
+                                 : exchange_bf16_variant_count() + exchange_bf16dl_variant_count();
 }
 
 }  // namespace
@@ -266,11 +281,11 @@ int auto_variant(int prec, int o, int ns, int v) {
   int o16_best = 1 << 30;
   for (int k = 0; k < n; ++k) {
     const ExchangeVariant *x = variant_of(prec, k);
-    if (x->o16 >= o && x->o16 < o16_best) o16_best = x->o16;
+    if (x->applies(o, v) && x->o16 < o16_best) o16_best = x->o16;
   }
   for (int k = 0; k < n; ++k) {
     const ExchangeVariant *x = variant_of(prec, k);
-    if (x->o16 != o16_best) continue;
+    if (x->o16 != o16_best || !x->applies(o, v)) continue;
     const double rows = (double)((ns + x->ks - 1) / x->ks) * x->ks;
     const double cols = (double)((v + x->nt - 1) / x->nt) * x->nt;
     const double waste = rows * cols / ((double)ns * v);
@@ -502,7 +517,8 @@ rttda_status rttda_set_tuning(rttda_ctx *ctx, const rttda_tuning *t) {
   if (t->exchange_variant) {
     const ExchangeVariant *x = variant_of(ctx->prec, t->exchange_variant - 1);
     if (!x) return fail(RTTDA_E_UNSUPPORTED, "exchange variant %d does not exist", t->exchange_variant);
-    if (x->o16 < ctx->o) return fail(RTTDA_E_UNSUPPORTED, "variant %s holds o <= %d", x->name, x->o16);
+    if (!x->applies(ctx->o, ctx->v))
+      return fail(RTTDA_E_UNSUPPORTED, "variant %s does not apply to o=%d v=%d", x->name, ctx->o, ctx->v);
     HIP_TRY(x->prepare());
     xv = t->exchange_variant - 1;
   }

@@ -32,7 +32,7 @@ def test_version_and_variants():
     n = lib.rttda_exchange_variants(rttda.PREC_FP32)
     assert n >= 4
     names = [lib.rttda_exchange_variant_name(rttda.PREC_FP32, k).decode() for k in range(1, n + 1)]
-    assert all(nm.startswith("f32_o") for nm in names)
+    assert all(nm.startswith("f32") for nm in names) and len(set(names)) == len(names)
     assert lib.rttda_exchange_variant_name(rttda.PREC_FP32, n + 1).decode() == ""
     assert lib.rttda_exchange_variants(7) == 0
 

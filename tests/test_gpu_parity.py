@@ -46,7 +46,9 @@ MIXED_SIGMA_CASES = [
     (10, 40, 120, 1),
     (60, 400, 40, 3),
     (33, 70, 9, 2),
+    (240, 64, 3, 1),
     (160, 64, 3, 1),
+    (100, 130, 4, 2),
     (130, 96, 5, 2),
     (7, 13, 4, 3),
 ]
@@ -389,3 +391,103 @@ def test_cfg2_full_run_spectrum_peaks(gpu_lib):
         worst = max(min(abs(p - w) for p, _ in pk) for w, _ in gold[r])
         say(f"   direction {r}: {len(gold[r])} oracle peaks, {len(pk)} GPU peaks, worst {worst:.2e} Ha")
         assert worst < 1e-5
+
+
+def _cfg3_device():
+    wl = I.workload(3)
+    t = I.make_device_tensors(wl.shape, wl.seed)
+    return wl, t
+
+
+def test_cfg3_shape_sigma_sampled(gpu_lib):
+    """Full cfg3 shape (o240 v1800 N_Q5000, BF16 factors, split-BF16 exchange): sigma of a random
+    state at 24 sampled (i, a) per plane against the oracle's element formula (FP64 over the
+    stored BF16 factors), within 2e-5 of max |sigma|."""
+    import torch
+    from paper_2601_16949_amd import rttda
+
+    say("[cfg3 sampled sigma] generating inputs on the device")
+    wl, t = _cfg3_device()
+    o, v, nq = wl.shape.o, wl.shape.v, wl.shape.nq
+    ctx = rttda.Context(rttda.DeviceProblem.from_tensors(wl.shape, t, "mixed"), max_rhs=1)
+    say(f"   variant {ctx.variant_name(ctx.get_tuning()['exchange_variant'])}")
+    c0, c = I.random_state(o, v, 1, seed=33, c_scale=1e-2)
+    c0d, cd = gpu_lib.to_planes(c0, c)
+    s0d, sd = ctx.sigma([0.0], [[0.0, 0.0, 1.0]], c0d, cd)
+    torch.cuda.synchronize()
+    _, s = gpu_lib.from_planes(s0d, sd)
+    say("   sigma done; oracle elements")
+    e_occ, e_virt = t["e_occ"].cpu().numpy(), t["e_virt"].cpu().numpy()
+    rng = np.random.default_rng(4)
+    idx = list(zip(rng.integers(0, o, 24), rng.integers(0, v, 24)))
+    for part in ("re", "im"):
+        C = (c[0].real if part == "re" else c[0].imag).copy()
+        d = np.zeros(nq)
+        for q0 in range(0, nq, 250):
+            d[q0:q0 + 250] = O.coulomb_contraction(t["b_ov"][q0:q0 + 250].float().cpu().numpy(), C)
+        got = (s[0].real if part == "re" else s[0].imag)
+        ref = []
+        for i, a in idx:
+            ref.append(O.sigma_element_from_slices(
+                e_occ[i], e_virt[a], C, i, a, t["b_ov"][:, i, a].float().cpu().numpy(), d,
+                t["b_oo"][:, i, :].float().cpu().numpy(), t["b_vv"][:, :, a].float().cpu().numpy(), wl.shape.cx))
+        ref = np.array(ref)
+        scale = np.max(np.abs(got))
+        err = np.max(np.abs(np.array([got[i, a] for i, a in idx]) - ref)) / scale
+        say(f"   {part}: sampled rel err {err:.2e}")
+        assert err < 2e-5
+
+
+def test_cfg3_batched_equals_single_few_steps(gpu_lib):
+    """cfg3 shape, x/y/z kicks as 3 RHS for 4 RK4 steps: each RHS's trace equals its single-RHS run
+    (bitwise: the kernels have no cross-RHS reductions or atomics) and stays finite."""
+    import torch
+    from paper_2601_16949_amd import rttda
+
+    say("[cfg3 batched == single]")
+    wl, t = _cfg3_device()
+    o, v = wl.shape.o, wl.shape.v
+    ctx = rttda.Context(rttda.DeviceProblem.from_tensors(wl.shape, t, "mixed"), max_rhs=3)
+    c0d, cd = gpu_lib.ground_state(3, o, v)
+    tr = ctx.propagate(wl.pulses, wl.dt, 4, c0d, cd)
+    torch.cuda.synchronize()
+    got = tr.cpu().numpy()
+    assert np.isfinite(got).all() and ctx.guard() == -1
+    one_c0, one_c = gpu_lib.ground_state(1, o, v)
+    one = ctx.propagate(wl.pulses[2:], wl.dt, 4, one_c0, one_c).cpu().numpy()
+    say(f"   traces z: batched {got[-1, 2]:.6e} single {one[-1, 0]:.6e}")
+    assert np.array_equal(one[:, 0], got[:, 2])
+
+
+@pytest.mark.parametrize("o,v,nq,nrhs,prec", [(60, 400, 23, 3, "fp32"), (40, 300, 9, 5, "fp32"), (32, 96, 7, 2, "fp32"),
+                                              (60, 400, 11, 3, "mixed"), (96, 200, 5, 1, "mixed"),
+                                              (240, 136, 3, 1, "mixed")])
+def test_every_exchange_variant_matches_oracle(gpu_lib, o, v, nq, nrhs, prec):
+    """Each exchange tile variant that applies to the shape (and a range of Q splits) gives sigma
+    within the precision's tolerance of the oracle."""
+    import torch
+
+    shape = I.Shape(o, v, nq, b_scale=0.05, storage="f32" if prec == "fp32" else "bf16")
+    prob, op, ctx = setup(shape, 4242 + o, nrhs, prec)
+    c0, c = I.random_state(o, v, nrhs, seed=11)
+    dirs = np.tile([[0.0, 0.0, 1.0]], (nrhs, 1))
+    field = np.full(nrhs, 0.01)
+    ref = [O.apply_H(op, O.dipole_blocks(op, dirs[r]), field[r], c0[r], c[r])[1] for r in range(nrhs)]
+    c0d, cd = gpu_lib.to_planes(c0, c)
+    n = ctx.lib.rttda_exchange_variants(ctx.desc.precision)
+    tried = 0
+    for k in range(1, n + 1):
+        for splits in (1, 3):
+            try:
+                ctx.set_tuning(exchange_variant=k, exchange_splits=min(splits, nq))
+            except gpu_lib.RttdaError:
+                continue
+            say(f"[variant] {ctx.variant_name(k)} splits {splits} o={o} v={v} {prec}")
+            _, sd = ctx.sigma(field, dirs, c0d, cd)
+            torch.cuda.synchronize()
+            _, s = gpu_lib.from_planes(torch.zeros_like(c0d), sd)
+            for r in range(nrhs):
+                err = np.max(np.abs(s[r] - ref[r])) / np.max(np.abs(ref[r]))
+                assert err < SIGMA_TOL[prec], (ctx.variant_name(k), splits, r, err)
+            tried += 1
+    assert tried >= 2
