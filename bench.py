@@ -52,6 +52,8 @@ def make_workload(name: str):
         return I.workload(1)
     if name == "cfg2":
         return I.workload(2)
+    if name == "cfg3":
+        return I.workload(3)
     if name == "cfg4":
         wl = I.workload(4)
         # carriers span 0.5x..1.2x the lowest excitation; the bench uses a fixed nominal
@@ -143,6 +145,8 @@ def main():
     ap.add_argument("--workload", default="cfg2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the mixed vs FP32 single-solve legs")
+    ap.add_argument("--graph-compare", action="store_true",
+                    help="also time the same number of steps replayed from the captured HIP graph (no events)")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--variant", type=int, default=0)
     ap.add_argument("--splits", type=int, default=0)
@@ -175,8 +179,15 @@ def main():
         wl.precision = args.precision
         wl.shape = I.Shape(wl.shape.o, wl.shape.v, wl.shape.nq, wl.shape.b_scale,
                            storage="f32" if args.precision == "fp32" else "bf16")
-    prob = I.make_problem(wl.shape, wl.seed)
-    dev = rttda.DeviceProblem(prob, wl.precision)
+    if args.workload == "cfg3":
+        # 37 GB of factors: drawn on the device (same distributions, torch's generator)
+        t = I.make_device_tensors(wl.shape, wl.seed)
+        dev = rttda.DeviceProblem.from_tensors(wl.shape, t, wl.precision)
+        prob = None
+        args.no_cpu_baseline = True
+    else:
+        prob = I.make_problem(wl.shape, wl.seed)
+        dev = rttda.DeviceProblem(prob, wl.precision)
     R = len(wl.pulses)
     ctx = rttda.Context(dev, max_rhs=R)
     tuned = False
@@ -185,7 +196,7 @@ def main():
     else:
         tuned = ctx.use_tuned(R)
     tun = ctx.get_tuning()
-    c0, c = rttda.ground_state(R, prob.o, prob.v)
+    c0, c = rttda.ground_state(R, dev.o, dev.v)
     ctx.propagate(wl.pulses, wl.dt, args.warmup, c0, c)
     torch.cuda.synchronize()
     print(f"# warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
@@ -203,7 +214,7 @@ def main():
     elapsed = t1 - t0
     print(f"# timed {args.steps} steps in {elapsed:.3f} s", file=sys.stderr, flush=True)
 
-    o, v, nq = prob.o, prob.v, prob.nq
+    o, v, nq = dev.o, dev.v, dev.nq
     fc, fx = flops_per_sigma(o, v, nq)
     sigma_flops = args.steps * 4 * R * (fc + fx)
     value = sigma_flops / elapsed / 1e9
@@ -244,6 +255,20 @@ def main():
         "guard_bad_step": bad,
         "trace_finite": bool(torch.isfinite(trace).all().item()),
     }
+    if args.graph_compare:
+        # the same K steps with the step captured once in a HIP graph and replayed, against
+        # direct launches (no profiling events in either)
+        times = {}
+        for mode, tag in ((1, "graph"), (2, "direct")):
+            ctx.set_tuning(use_graph=mode)
+            ctx.propagate(wl.pulses, wl.dt, 16, c0, c, step0=args.warmup + args.steps, want_trace=False)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.propagate(wl.pulses, wl.dt, args.steps, c0, c, step0=args.warmup + args.steps + 16, want_trace=False)
+            torch.cuda.synchronize()
+            times[tag] = round(1e3 * (time.perf_counter() - t0) / args.steps, 4)
+        ctx.set_tuning(use_graph=1)
+        out["ms_per_step_graph_vs_direct"] = times
     if not args.no_compare and args.workload == "cfg2":
         # batched mixed precision (3 RHS, BF16 factors, split exchange) against the plain FP32
         # single solve (1 RHS) on the same shape; the accuracy of the mixed path against the FP64

@@ -212,12 +212,22 @@ __global__ __launch_bounds__(256, 2) void k_exchange_f32_dl(const float *__restr
           for (int cc = 0; cc < WC; ++cc) Wacc[a][b][cc] = f4{0.f, 0.f, 0.f, 0.f};
     }
   };
+  // nvalid == 0: this wave's columns lie beyond v; it only takes part in loads and barriers
   auto compute = [&](int c) {
-    if (nvalid == WC)
+    static_assert(WC >= 1 && WC <= 4, "column blocks per wave");
+    if (nvalid == WC) {
       compute_n(std::integral_constant<int, WC>{}, c);
-    else if (WC > 1 && nvalid == 1)
-      compute_n(std::integral_constant<int, 1>{}, c);
-    // nvalid == 0: this wave's columns lie beyond v; it only takes part in loads and barriers
+    } else {
+      if constexpr (WC >= 4) {
+        if (nvalid == 3) compute_n(std::integral_constant<int, 3>{}, c);
+      }
+      if constexpr (WC >= 3) {
+        if (nvalid == 2) compute_n(std::integral_constant<int, 2>{}, c);
+      }
+      if constexpr (WC >= 2) {
+        if (nvalid == 1) compute_n(std::integral_constant<int, 1>{}, c);
+      }
+    }
   };
 
   if (NC > 0) {

@@ -191,3 +191,50 @@ class Server:
             "aggregate_fs_per_hour": fs / (makespan / 3600.0),
             "sigma_gflops": flops / makespan / 1e9,
         }
+
+
+def _scaled_requests(n: int, seed: int, o_max: int, steps_scale: float, rate: float):
+    reqs = I.serving_requests(n, rate=rate, seed=seed, o_min=10, o_max=o_max)
+    for r in reqs:
+        r.n_steps = max(20, int(round(r.n_steps * steps_scale)))
+        if r.pulse.kind == I.PULSE_GAUSS:
+            r.pulse.t0 = 0.5 * r.n_steps * r.dt
+            r.pulse.fwhm = min(400.0, 0.25 * r.n_steps * r.dt)
+    return reqs
+
+
+def main(argv=None):
+    """Capacity-scaled serving run: a burst (all arrivals at t = 0) measures the capacity of the
+    request mix; a Poisson stream at `load` x that capacity then gives steady-state latencies."""
+    import argparse
+    import json
+
+    import torch
+
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--requests", type=int, default=60)
+    ap.add_argument("--o-max", type=int, default=48)
+    ap.add_argument("--steps-scale", type=float, default=0.1, help="scale of the 500..8000 step counts")
+    ap.add_argument("--budget-gib", type=float, default=64.0)
+    ap.add_argument("--chunk", type=int, default=100)
+    ap.add_argument("--load", type=float, default=0.7)
+    ap.add_argument("--seed", type=int, default=I.SEED_BASE + 5)
+    a = ap.parse_args(argv)
+    budget = int(a.budget_gib * (1 << 30))
+    burst = _scaled_requests(a.requests, a.seed, a.o_max, a.steps_scale, rate=1e9)
+    srv = Server(budget, chunk_steps=a.chunk, precision="mixed", keep_traces=False)
+    b = srv.run(burst, realtime=False)
+    capacity = a.requests / b["makespan_s"]
+    rate = a.load * capacity
+    stream = _scaled_requests(a.requests, a.seed, a.o_max, a.steps_scale, rate=rate)
+    srv2 = Server(budget, chunk_steps=a.chunk, precision="mixed", keep_traces=False)
+    p = srv2.run(stream, realtime=True)
+    torch.cuda.synchronize()
+    print(json.dumps({"mix": {"requests": a.requests, "o": [10, a.o_max], "v": "7.5 o", "n_aux": "20 o",
+                              "steps": [int(500 * a.steps_scale), int(8000 * a.steps_scale)],
+                              "pulses": "50% delta kick, 50% Gaussian-sine", "precision": "mixed"},
+                      "burst": b, "capacity_req_per_s": capacity, "poisson_rate_req_per_s": rate, "poisson": p}))
+
+
+if __name__ == "__main__":
+    main()
