@@ -32,10 +32,17 @@ AU_FS = 0.02418884326585747
 
 # HBM bytes per exchange launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs (KiB per dispatch,
 # scaled by the counters' readings for a plain 1 GiB copy: factors 2.0 and 1.0), keyed by
-# (variant, workload, splits); valid only while the kernel source hashes to `src`.
+# (variant, workload, splits); valid only while the kernel's source file hashes to `src`.
 TRAFFIC = {
     ("f32_o64_ws1_wc2_kc16", "o60_v400_nq1500_kick_xyz", 119):
-        {"src": "13c2ccdc9a206c1c", "fetch_bytes": 516335.5 * 1024 * 2.0, "write_bytes": 69345.8 * 1024 * 1.0},
+        {"file": "exchange_f32.hip", "src": "13c2ccdc9a206c1c",
+         "fetch_bytes": 516335.5 * 1024 * 2.0, "write_bytes": 69345.8 * 1024 * 1.0},
+    ("f32dl_o64_ws1_wc2", "o60_v400_nq1500_kick_xyz", 119):
+        {"file": "exchange_f32_dl.hip", "src": "cbe66e8930b46a99",
+         "fetch_bytes": 770082.34375 * 1024 * 2.0, "write_bytes": 68752.4609375 * 1024 * 1.0},
+    ("bf16x2dl_o64_ws1_wc2", "o60_v400_nq1500_kick_xyz", 192):
+        {"file": "exchange_bf16_dl.hip", "src": "f255ad1eb16b4f05",
+         "fetch_bytes": 263676.1 * 1024 * 2.0, "write_bytes": 111747.0 * 1024 * 1.0},
 }
 PEAK = {"fp32": 157.3, "mixed": 2516.6}  # dense MFMA TFLOP/s: FP32, BF16
 HBM_PEAK_GBS = 8000.0
@@ -69,8 +76,7 @@ def traffic_for(variant: str, workload: str, splits: int, precision: str):
     e = TRAFFIC.get((variant, workload, splits))
     if not e:
         return None
-    src = os.path.join(ROOT, "paper_2601_16949_amd", "csrc",
-                       "exchange_f32.hip" if precision == "fp32" else "exchange_bf16.hip")
+    src = os.path.join(ROOT, "paper_2601_16949_amd", "csrc", e["file"])
     if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != e["src"]:
         return None  # kernel changed since the counters were taken
     return e["fetch_bytes"] + e["write_bytes"]
