@@ -166,6 +166,9 @@ typedef struct rttda_tuning {
   int32_t coulomb_splits;   /* number of Q ranges the second Coulomb product is split into */
   int32_t use_graph;        /* 1 = replay RK4 steps from a captured HIP graph, 2 = direct  */
   int32_t steps_per_graph;  /* RK4 steps captured in one graph                              */
+  int32_t exchange_chunk;   /* Q values per chunk of the large-o GEMM exchange path (its W
+                               scratch holds W hi/lo for one chunk, so at most what fits);
+                               -1 = as many as fit (the default)                           */
 } rttda_tuning;
 rttda_status rttda_set_tuning(rttda_ctx *ctx, const rttda_tuning *t);
 rttda_status rttda_get_tuning(const rttda_ctx *ctx, rttda_tuning *t);

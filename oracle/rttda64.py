@@ -295,6 +295,23 @@ def rk4_amplification(z):
     return 1.0 + z + z * z / 2.0 + z ** 3 / 6.0 + z ** 4 / 24.0
 
 
+def lowest_states(op: Operator, k: int):
+    """The k lowest TI-TDA states (eigenpairs of A, eq. casida_tda): energies w[k] and
+    eigenvectors U[(i,a), k], from the dense A and a LAPACK subset eigensolver."""
+    import scipy.linalg
+
+    A = dense_A_blas(op) if op.o * op.v > 600 else dense_A(op)
+    w, U = scipy.linalg.eigh(A, subset_by_index=[0, k - 1])
+    return w, U
+
+
+def state_populations(U: np.ndarray, c0, C) -> np.ndarray:
+    """Populations of the ground state and of the TI-TDA states in the columns of U by projection
+    of the amplitudes (eq. populations): [|c0|^2, |U_1^T c|^2, ...]."""
+    x = np.asarray(C, dtype=np.complex128).reshape(-1)
+    return np.concatenate([[abs(complex(c0)) ** 2], np.abs(U.T @ x) ** 2])
+
+
 class EigenRoute:
     """Extended-space eigen decomposition: w[0] = 0 (ground state), w[1:] = eig(A)."""
 

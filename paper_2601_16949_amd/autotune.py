@@ -47,12 +47,12 @@ def variant_index(ctx, name: str) -> int:
 
 
 def apply(ctx, entry: dict) -> bool:
-    """Apply a cached (variant name, splits) choice; False if this build lacks the variant."""
+    """Apply a cached (variant name, splits[, Q chunk]) choice; False if this build lacks the variant."""
     k = variant_index(ctx, entry["name"])
     if not k:
         return False
     splits = min(int(entry["splits"]), ctx.max_splits())
-    ctx.set_tuning(exchange_variant=k, exchange_splits=splits)
+    ctx.set_tuning(exchange_variant=k, exchange_splits=splits, exchange_chunk=int(entry.get("chunk", 0)) or -1)
     return True
 
 
@@ -60,8 +60,12 @@ def lookup(ctx, nrhs: int, cache_path: str = DEFAULT_CACHE) -> Optional[dict]:
     return load_cache(cache_path).get(_key(ctx, nrhs))
 
 
+GEMM_CHUNKS = (0, 6, 12)  # Q per chunk tried for the large-o GEMM path (0 = as many as fit)
+
+
 def candidates(ctx, max_per_variant: int = 4) -> List[tuple]:
-    """(variant, splits) pairs: every variant holding o, with splits around the library's default."""
+    """(variant, splits, Q chunk) triples: every variant holding o, with splits around the
+    library's default; the GEMM path also over a few chunk lengths (0 elsewhere)."""
     lib = ctx.lib
     prec = ctx.desc.precision
     n = lib.rttda_exchange_variants(prec)
@@ -73,8 +77,10 @@ def candidates(ctx, max_per_variant: int = 4) -> List[tuple]:
         except Exception:
             continue  # variant does not hold o
         s0 = ctx.get_tuning()["exchange_splits"]
+        chunks = GEMM_CHUNKS if ctx.variant_name(k).startswith("bf16x2gemm") else (0,)
         for s in sorted({max(1, s0 // 2), s0, s0 * 2, s0 * 3})[:max_per_variant]:
-            out.append((k, s))
+            for ch in chunks:
+                out.append((k, s, ch))
     ctx.set_tuning(exchange_variant=base["exchange_variant"], exchange_splits=base["exchange_splits"])
     return out
 
@@ -105,18 +111,19 @@ def tune(ctx, pulses, dt: float, nrhs: Optional[int] = None, steps: int = 3, cac
         return best
     c0, c = rttda.ground_state(nrhs, ctx.o, ctx.v, device=ctx.device)
     results = []
-    for k, s in candidates(ctx):
+    for k, s, ch in candidates(ctx):
         try:
-            ctx.set_tuning(exchange_variant=k, exchange_splits=s)
+            ctx.set_tuning(exchange_variant=k, exchange_splits=s, exchange_chunk=ch or -1)
         except rttda.RttdaError:
             continue
         measure(ctx, pulses, dt, c0, c, steps=1)  # warm
         ms = measure(ctx, pulses, dt, c0, c, steps=steps)
-        results.append({"variant": k, "name": ctx.variant_name(k), "splits": s, "ms": ms})
+        results.append({"variant": k, "name": ctx.variant_name(k), "splits": s, "chunk": ch, "ms": ms})
         if verbose:
-            print(f"  {ctx.variant_name(k):24s} splits {s:3d}: {ms * 1e3:9.1f} us", flush=True)
+            print(f"  {ctx.variant_name(k):34s} splits {s:3d} chunk {ch:3d}: {ms * 1e3:10.1f} us", flush=True)
     best = min(results, key=lambda r: r["ms"])
-    ctx.set_tuning(exchange_variant=best["variant"], exchange_splits=best["splits"])
+    ctx.set_tuning(exchange_variant=best["variant"], exchange_splits=best["splits"],
+                   exchange_chunk=best["chunk"] or -1)
     best = dict(best, candidates=len(results))
     if use_cache:
         cache[key] = best

@@ -63,8 +63,12 @@ hipError_t launch_gaps(hipStream_t s, const double *e_occ, const double *e_virt,
 hipError_t launch_to_f32(hipStream_t s, const double *c, long long n, float *x32);
 hipError_t launch_to_bf16x2(hipStream_t s, const double *c, long long n, float *x32, __hip_bfloat16 *hi,
                             __hip_bfloat16 *lo);
-hipError_t launch_gemv1(hipStream_t s, int b_dtype, const void *B, const float *X, int nq, int ov, int ns,
-                        float *dvec);
+// Coulomb first product in `nes` ia chunks (partials dpart[nes][nq][ns], summed into slot 0 when
+// nes > 1, which is d for the second product); gemv1_chunks picks nes (at most GEMV1_CHUNKS_MAX).
+constexpr int GEMV1_CHUNKS_MAX = 16;
+int gemv1_chunks(int nq, int ov);
+hipError_t launch_gemv1(hipStream_t s, int b_dtype, const void *B, const float *X, int nq, int ov, int ns, int nes,
+                        float *dpart);
 hipError_t launch_gemv2(hipStream_t s, int b_dtype, const void *B, const float *dvec, int nq, int ov, int ns,
                         int nsplit, float *P);
 hipError_t launch_field(hipStream_t s, const double *X, const double *X0, const double *moo, const double *mov,
@@ -81,6 +85,12 @@ hipError_t launch_kick(hipStream_t s, int R, int ov, const DevPulse *pulses, con
 hipError_t launch_set_state(hipStream_t s, DevState *st, long long step0, double *trace, double *norms);
 
 // Exchange: K partials P[split][slice][o][v] = scale * sum_{Q in split} B_oo^Q X_slice B_vv^Q.
+// Large-o split-BF16 path (two batched GEMMs per chunk of Q through a W scratch buffer): used
+// for o >= XGEMM_O_MIN with o % 8 == 0 and v % 8 == 0; the scratch holds W hi/lo for up to
+// XGEMM_SCRATCH_MAX bytes' worth of Q values.
+constexpr int XGEMM_O_MIN = 128;
+constexpr size_t XGEMM_SCRATCH_MAX = size_t(256) << 20;
+
 struct ExchangeVariant {
   int precision;  // RTTDA_PREC_*
   int o16;        // padded occupied count handled (o <= o16)
@@ -88,13 +98,18 @@ struct ExchangeVariant {
   int nt;         // virtual columns per workgroup
   const char *name;
   hipError_t (*launch)(hipStream_t s, const void *Boo, const void *Bvv, const void *X, const void *Xlo, int o,
-                       int v, int nq, int ns, int nsplit, float scale, float *P);
+                       int v, int nq, int ns, int nsplit, float scale, float *P, void *scratch,
+                       size_t scratch_bytes);
   size_t lds_bytes;
   hipError_t (*prepare)();  // one-time kernel attributes (dynamic LDS size); call outside graph capture
-  int v_min = 1;            // applicability: v >= v_min, v % v_mod == 0, o % o_mod == 0
+  int v_min = 1;            // applicability: v >= v_min, v % v_mod == 0, o % o_mod == 0, o >= o_min
   int v_mod = 1;
   int o_mod = 1;
-  bool applies(int o, int v) const { return o <= o16 && v >= v_min && v % v_mod == 0 && o % o_mod == 0; }
+  int o_min = 1;
+  bool scratch = false;  // needs the W scratch region of the workspace
+  bool applies(int o, int v) const {
+    return o <= o16 && o >= o_min && v >= v_min && v % v_mod == 0 && o % o_mod == 0;
+  }
 };
 
 }  // namespace rttda

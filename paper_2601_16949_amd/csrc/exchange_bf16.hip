@@ -343,7 +343,7 @@ __global__ __launch_bounds__(256, 1) void k_exchange_bf16(const __bf16 *__restri
 
 template <int O32, int WS, int WC, int KC>
 hipError_t launch_xbf16(hipStream_t s, const void *Boo, const void *Bvv, const void *X, const void *Xlo, int o, int v,
-                        int nq, int ns, int nsplit, float scale, float *P) {
+                        int nq, int ns, int nsplit, float scale, float *P, void *, size_t) {
   using C = CfgB<O32, WS, WC, KC>;
   if (o > O32) return hipErrorInvalidValue;
   const int n_sg = (ns + C::KS - 1) / C::KS, n_ct = (v + C::NT - 1) / C::NT;
@@ -594,7 +594,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_exchange_bf16w(const __bf16 *__r
 
 template <int O32, int NT, int NW, int KC>
 hipError_t launch_xbf16w(hipStream_t s, const void *Boo, const void *Bvv, const void *X, const void *Xlo, int o,
-                         int v, int nq, int ns, int nsplit, float scale, float *P) {
+                         int v, int nq, int ns, int nsplit, float scale, float *P, void *, size_t) {
   using C = CfgW<O32, NT, NW, KC>;
   if (o > O32) return hipErrorInvalidValue;
   const int n_sg = ns, n_ct = (v + NT - 1) / NT;

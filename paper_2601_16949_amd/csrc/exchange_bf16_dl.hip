@@ -292,7 +292,7 @@ __global__ __launch_bounds__(256, 2) void k_exchange_bf16_dl(const __bf16 *__res
 
 template <int O32, int WS, int WC>
 hipError_t launch_xbf16dl(hipStream_t s, const void *Boo, const void *Bvv, const void *X, const void *Xlo, int o,
-                          int v, int nq, int ns, int nsplit, float scale, float *P) {
+                          int v, int nq, int ns, int nsplit, float scale, float *P, void *, size_t) {
   using C = CfgBD<O32, WS, WC>;
   if (o > O32 || (v & 7) != 0 || (o & 1) != 0 || v < 3 * KC) return hipErrorInvalidValue;
   const int n_sg = (ns + C::KS - 1) / C::KS, n_ct = (v + C::NT - 1) / C::NT;

@@ -299,7 +299,7 @@ __global__ __launch_bounds__(256, 1) void k_exchange_f32(const float *__restrict
 
 template <int O16, int WS, int WC, int KC>
 hipError_t launch_xf32(hipStream_t s, const void *Boo, const void *Bvv, const void *X, const void * /*Xlo*/, int o,
-                       int v, int nq, int ns, int nsplit, float scale, float *P) {
+                       int v, int nq, int ns, int nsplit, float scale, float *P, void *, size_t) {
   using C = Cfg<O16, WS, WC, KC>;
   if (o > O16) return hipErrorInvalidValue;
   const int n_sg = (ns + C::KS - 1) / C::KS, n_ct = (v + C::NT - 1) / C::NT;

@@ -277,7 +277,7 @@ __global__ __launch_bounds__(256, 2) void k_exchange_f32_dl(const float *__restr
 
 template <int O16, int WS, int WC>
 hipError_t launch_xf32dl(hipStream_t s, const void *Boo, const void *Bvv, const void *X, const void *, int o, int v,
-                         int nq, int ns, int nsplit, float scale, float *P) {
+                         int nq, int ns, int nsplit, float scale, float *P, void *, size_t) {
   using C = CfgD<O16, WS, WC>;
   if (o > O16 || (v & 3) != 0 || (o & 3) != 0 || v < 3 * KC) return hipErrorInvalidValue;
   const int n_sg = (ns + C::KS - 1) / C::KS, n_ct = (v + C::NT - 1) / C::NT;

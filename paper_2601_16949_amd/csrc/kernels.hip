@@ -1,5 +1,7 @@
 // Bandwidth- and latency-bound kernels of the RT-TDA step on gfx950:
 // dipole blocks, Coulomb GEMV pair, FP64 field/trace, stage scalars, RK4 epilogue, kick.
+#include <algorithm>
+
 #include "common.h"
 
 namespace rttda {
@@ -87,42 +89,107 @@ __global__ void k_to_bf16x2(const double *__restrict__ c, long long n, float *__
 
 // ------------------------------------------------------------------------------------------------
 // Coulomb, first product: d[Q][s] = sum_ia B_ov[Q][ia] X[s][ia]   (B streamed once from HBM)
-// Block = QT rows of B x ST slices; 256 threads stride over ia, then a deterministic block sum.
+// Block = QT rows of B x ST slices x one ia chunk; the chunk partials dpart[chunk][Q][s] are summed
+// in a fixed order by the second product.  Vector path: 4 consecutive ia per lane and load (needs
+// ov % 4 == 0 so that every B row starts 16/8-byte aligned); scalar path otherwise.
 // ------------------------------------------------------------------------------------------------
-template <typename TB, int QT, int ST>
+__device__ __forceinline__ float4 load_b4(const float *p, size_t i) {
+  return *reinterpret_cast<const float4 *>(p + i);
+}
+__device__ __forceinline__ float4 load_b4(const __hip_bfloat16 *p, size_t i) {
+  const uint2 u = *reinterpret_cast<const uint2 *>(p + i);  // element 2k in the low half of word k
+  return make_float4(__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xffff0000u), __uint_as_float(u.y << 16),
+                     __uint_as_float(u.y & 0xffff0000u));
+}
+
+// Sum 64 per-lane values over the wave with 63 exchanges: at each halving step a lane keeps the
+// half of its values selected by its lane bit and adds the partner's copy of that half.  On exit
+// lane l holds the wave total of value l.
+template <int K>
+__device__ __forceinline__ void transpose_sum_step(float (&v)[64], int lane) {
+  const bool up = (lane & K) != 0;
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const float send = up ? v[j] : v[j + K];
+    const float keep = up ? v[j + K] : v[j];
+    v[j] = keep + __shfl_xor(send, K, 64);
+  }
+  if constexpr (K > 1) transpose_sum_step<K / 2>(v, lane);
+}
+
+__device__ __forceinline__ float wave_transpose_sum64(float (&v)[64], int lane) {
+  transpose_sum_step<32>(v, lane);
+  return v[0];
+}
+
+template <typename TB, int QT, int ST, bool VEC>
 __global__ __launch_bounds__(256) void k_gemv1(const TB *__restrict__ B, const float *__restrict__ X, int nq, int ov,
-                                               int ns, float *__restrict__ dvec) {
+                                               int ns, int echunk, float *__restrict__ dpart) {
+  static_assert(QT * ST <= 64, "one reduced value per lane");
   const int q0 = blockIdx.x * QT, s0 = blockIdx.y * ST;
+  const int e0 = blockIdx.z * echunk, e1 = min(ov, e0 + echunk);
+  const int nqv = min(QT, nq - q0), nsv = min(ST, ns - s0);
   float acc[QT][ST];
 #pragma unroll
   for (int a = 0; a < QT; ++a)
 #pragma unroll
     for (int b = 0; b < ST; ++b) acc[a][b] = 0.f;
-  for (int e = threadIdx.x; e < ov; e += 256) {
-    float bq[QT], xs[ST];
+  if constexpr (VEC) {
+    for (int e = e0 + 4 * (int)threadIdx.x; e < e1; e += 1024) {
+      float4 xs[ST];
 #pragma unroll
-    for (int a = 0; a < QT; ++a) bq[a] = (q0 + a < nq) ? load_b(B, (size_t)(q0 + a) * ov + e) : 0.f;
+      for (int b = 0; b < ST; ++b)
+        xs[b] = b < nsv ? *reinterpret_cast<const float4 *>(X + (size_t)(s0 + b) * ov + e) : make_float4(0, 0, 0, 0);
 #pragma unroll
-    for (int b = 0; b < ST; ++b) xs[b] = (s0 + b < ns) ? X[(size_t)(s0 + b) * ov + e] : 0.f;
+      for (int a = 0; a < QT; ++a) {
+        if (a < nqv) {
+          const float4 bq = load_b4(B, (size_t)(q0 + a) * ov + e);
 #pragma unroll
-    for (int a = 0; a < QT; ++a)
-#pragma unroll
-      for (int b = 0; b < ST; ++b) acc[a][b] += bq[a] * xs[b];
-  }
-  __shared__ float red[4][QT * ST];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-  for (int a = 0; a < QT; ++a)
-#pragma unroll
-    for (int b = 0; b < ST; ++b) {
-      const float t = wave_sum(acc[a][b]);
-      if (lane == 0) red[wave][a * ST + b] = t;
+          for (int b = 0; b < ST; ++b) {
+            float t = acc[a][b];
+            t = fmaf(bq.x, xs[b].x, t);
+            t = fmaf(bq.y, xs[b].y, t);
+            t = fmaf(bq.z, xs[b].z, t);
+            acc[a][b] = fmaf(bq.w, xs[b].w, t);
+          }
+        }
+      }
     }
+  } else {
+    for (int e = e0 + (int)threadIdx.x; e < e1; e += 256) {
+      float xs[ST];
+#pragma unroll
+      for (int b = 0; b < ST; ++b) xs[b] = b < nsv ? X[(size_t)(s0 + b) * ov + e] : 0.f;
+#pragma unroll
+      for (int a = 0; a < QT; ++a) {
+        if (a < nqv) {
+          const float bq = load_b(B, (size_t)(q0 + a) * ov + e);
+#pragma unroll
+          for (int b = 0; b < ST; ++b) acc[a][b] = fmaf(bq, xs[b], acc[a][b]);
+        }
+      }
+    }
+  }
+  float vals[64];
+#pragma unroll
+  for (int k = 0; k < 64; ++k) vals[k] = k < QT * ST ? acc[k / ST][k % ST] : 0.f;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __shared__ float red[4][64];
+  red[wave][lane] = wave_transpose_sum64(vals, lane);
   __syncthreads();
-  for (int k = threadIdx.x; k < QT * ST; k += 256) {
-    const int a = k / ST, b = k % ST;
-    if (q0 + a < nq && s0 + b < ns)
-      dvec[(size_t)(q0 + a) * ns + s0 + b] = (red[0][k] + red[1][k]) + (red[2][k] + red[3][k]);
+  if (threadIdx.x < QT * ST) {
+    const int k = threadIdx.x, a = k / ST, b = k % ST;
+    if (a < nqv && b < nsv)
+      dpart[((size_t)blockIdx.z * nq + q0 + a) * ns + s0 + b] = (red[0][k] + red[1][k]) + (red[2][k] + red[3][k]);
+  }
+}
+
+// Sum of the ia-chunk partials into chunk slot 0: dpart[0][q][s] = sum_k dpart[k][q][s] (fixed order).
+__global__ void k_dsum(float *__restrict__ dpart, int n, int nes) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+    float d = dpart[e];
+    for (int k = 1; k < nes; ++k) d += dpart[(size_t)k * n + e];
+    dpart[e] = d;
   }
 }
 
@@ -518,16 +585,45 @@ hipError_t launch_to_bf16x2(hipStream_t s, const double *c, long long n, float *
   return hipGetLastError();
 }
 
-hipError_t launch_gemv1(hipStream_t s, int b_dtype, const void *B, const float *X, int nq, int ov, int ns,
-                        float *dvec) {
-  constexpr int QT = 4, ST = 8;
-  dim3 grid((nq + QT - 1) / QT, (ns + ST - 1) / ST);
-  if (b_dtype == RTTDA_BF16)
-    hipLaunchKernelGGL((k_gemv1<__hip_bfloat16, QT, ST>), grid, dim3(256), 0, s,
-                       static_cast<const __hip_bfloat16 *>(B), X, nq, ov, ns, dvec);
+int gemv1_chunks(int nq, int ov) {
+  // independent of the slice count, so that a batch and a single RHS sum d identically
+  if (nq <= 0 || ov <= 0) return 1;
+  const int blocks = (nq + 7) / 8;
+  int es = std::max(1, std::min({(2048 + blocks - 1) / blocks, GEMV1_CHUNKS_MAX, ov / 2048}));
+  const int echunk = (((ov + es - 1) / es) + 1023) / 1024 * 1024;
+  return (ov + echunk - 1) / echunk;
+}
+
+template <typename TB, int ST>
+static void gemv1_go(hipStream_t s, const TB *B, const float *X, int nq, int ov, int ns, int nes, float *dpart) {
+  constexpr int QT = 8;
+  const bool vec = (ov % 4) == 0;
+  const int echunk = nes == 1 ? ov : (((ov + nes - 1) / nes) + 1023) / 1024 * 1024;
+  dim3 grid((nq + QT - 1) / QT, (ns + ST - 1) / ST, nes);
+  if (vec)
+    hipLaunchKernelGGL((k_gemv1<TB, QT, ST, true>), grid, dim3(256), 0, s, B, X, nq, ov, ns, echunk, dpart);
   else
-    hipLaunchKernelGGL((k_gemv1<float, QT, ST>), grid, dim3(256), 0, s, static_cast<const float *>(B), X, nq, ov,
-                       ns, dvec);
+    hipLaunchKernelGGL((k_gemv1<TB, QT, ST, false>), grid, dim3(256), 0, s, B, X, nq, ov, ns, echunk, dpart);
+  if (nes > 1) {
+    const int n = nq * ns;
+    hipLaunchKernelGGL(k_dsum, dim3(grid_for(n)), dim3(256), 0, s, dpart, n, nes);
+  }
+}
+
+template <typename TB>
+static void gemv1_st(hipStream_t s, const TB *B, const float *X, int nq, int ov, int ns, int nes, float *dpart) {
+  if (ns <= 2) gemv1_go<TB, 2>(s, B, X, nq, ov, ns, nes, dpart);
+  else if (ns <= 4) gemv1_go<TB, 4>(s, B, X, nq, ov, ns, nes, dpart);
+  else if (ns <= 6) gemv1_go<TB, 6>(s, B, X, nq, ov, ns, nes, dpart);
+  else gemv1_go<TB, 8>(s, B, X, nq, ov, ns, nes, dpart);
+}
+
+hipError_t launch_gemv1(hipStream_t s, int b_dtype, const void *B, const float *X, int nq, int ov, int ns, int nes,
+                        float *dpart) {
+  if (b_dtype == RTTDA_BF16)
+    gemv1_st(s, static_cast<const __hip_bfloat16 *>(B), X, nq, ov, ns, nes, dpart);
+  else
+    gemv1_st(s, static_cast<const float *>(B), X, nq, ov, ns, nes, dpart);
   return hipGetLastError();
 }
 

@@ -18,6 +18,8 @@ int exchange_f32dl_variant_count();
 const ExchangeVariant *exchange_f32dl_variant(int k);
 int exchange_bf16dl_variant_count();
 const ExchangeVariant *exchange_bf16dl_variant(int k);
+int exchange_gemm_variant_count();
+const ExchangeVariant *exchange_gemm_variant(int k);
 }  // namespace rttda
 
 using namespace rttda;
@@ -56,6 +58,7 @@ inline bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 
 
 struct Layout {
   size_t D, moo, mov, mvv, xs64, xs0, acc, acc0, F, part, sc, x32, xhi, xlo, dvec, P, pulses, state, normref;
+  size_t scratch, scratch_bytes;  // W hi/lo of the large-o exchange path (0 bytes when it does not apply)
   size_t total;
   int nbf;
   int sk_max, sj_max;
@@ -88,11 +91,17 @@ Layout make_layout(int o, int v, int nq, int R, int prec) {
   L.x32 = take(ns * ov * 4);  // FP32 stage copy (Coulomb input; exchange input in FP32 mode)
   L.xhi = take(prec == RTTDA_PREC_MIXED_BF16 ? ns * ov * 2 : 0);
   L.xlo = take(prec == RTTDA_PREC_MIXED_BF16 ? ns * ov * 2 : 0);
-  L.dvec = take((size_t)std::max(nq, 1) * ns * 4);
+  L.dvec = take((size_t)GEMV1_CHUNKS_MAX * std::max(nq, 1) * ns * 4);
   L.P = take((size_t)(L.sj_max + L.sk_max) * ns * ov * 4);
   L.pulses = take((size_t)R * sizeof(DevPulse));
   L.state = take(sizeof(DevState));
   L.normref = take((size_t)R * 8);
+  L.scratch_bytes = 0;
+  if (prec == RTTDA_PREC_MIXED_BF16 && nq > 0 && o >= XGEMM_O_MIN && o <= 256 && o % 8 == 0 && v % 8 == 0) {
+    const size_t per_q = (size_t)v * ns * o * 4;  // W hi + lo for one Q at the largest RHS count
+    L.scratch_bytes = std::min((size_t)nq * per_q, std::max(per_q, XGEMM_SCRATCH_MAX));
+  }
+  L.scratch = take(L.scratch_bytes);
   L.total = off;
   return L;
 }
@@ -181,11 +190,19 @@ const ExchangeVariant *variant_of(int prec, int k) {
   const int n2 = exchange_bf16_variant_count();
   if (k < n2) return exchange_bf16_variant(k);
   k -= n2;
-  return k < exchange_bf16dl_variant_count() ? exchange_bf16dl_variant(k) : nullptr;
+  const int n3 = exchange_bf16dl_variant_count();
+  if (k < n3) return exchange_bf16dl_variant(k);
+  k -= n3;
+  return k < exchange_gemm_variant_count() ? exchange_gemm_variant(k) : nullptr;
 }
 int variant_count(int prec) {
-  return prec == RTTDA_PREC_FP32 ? exchange_f32_variant_count() + exchange_f32dl_variant_count()
-                                 : exchange_bf16_variant_count() + exchange_bf16dl_variant_count();
+  return prec == RTTDA_PREC_FP32
+             ? exchange_f32_variant_count() + exchange_f32dl_variant_count()
+             : exchange_bf16_variant_count() + exchange_bf16dl_variant_count() + exchange_gemm_variant_count();
+}
+// a variant runs on a context when it holds the shape and, if it needs one, the workspace has scratch
+bool usable(const ExchangeVariant *x, int o, int v, const Layout &L) {
+  return x && x->applies(o, v) && (!x->scratch || L.scratch_bytes > 0);
 }
 
 }  // namespace
@@ -201,6 +218,7 @@ struct rttda_ctx {
   int xvar = -1;  // 0-based exchange variant
   int sk = 0, sj = 0;
   int use_graph = 1, steps_per_graph = 8;
+  int qchunk = 0;  // Q per chunk of the GEMM exchange path, 0 = as many as the scratch holds
   // host staging for pulses (pinned)
   DevPulse *h_pulses = nullptr;
   hipEvent_t upload_ev = nullptr;
@@ -227,6 +245,7 @@ struct rttda_ctx {
   __hip_bfloat16 *xlo() const { return at<__hip_bfloat16>(L.xlo); }
   float *dvec() const { return at<float>(L.dvec); }
   float *P() const { return at<float>(L.P); }
+  void *scratch() const { return L.scratch_bytes ? static_cast<void *>(ws + L.scratch) : nullptr; }
   DevPulse *pulses() const { return at<DevPulse>(L.pulses); }
   DevState *state() const { return at<DevState>(L.state); }
   double *normref() const { return at<double>(L.normref); }
@@ -272,20 +291,25 @@ rttda_status validate_desc(const rttda_desc *d, bool need_ptrs) {
   return RTTDA_OK;
 }
 
-int auto_variant(int prec, int o, int ns, int v) {
-  // smallest padded occupied size that holds o; among those prefer the variant whose tile
-  // wastes the least of the (slices x columns) space, then the larger tile.
+int auto_variant(int prec, int o, int ns, int v, const Layout &L) {
+  const int n = variant_count(prec);
+  // the large-o GEMM path first whenever the workspace carries its scratch
+  for (int k = 0; k < n; ++k) {
+    const ExchangeVariant *x = variant_of(prec, k);
+    if (x->scratch && usable(x, o, v, L)) return k;
+  }
+  // else the smallest padded occupied size that holds o; among those prefer the variant whose
+  // tile wastes the least of the (slices x columns) space, then the larger tile.
   int best = -1;
   double best_score = 1e300;
-  const int n = variant_count(prec);
   int o16_best = 1 << 30;
   for (int k = 0; k < n; ++k) {
     const ExchangeVariant *x = variant_of(prec, k);
-    if (x->applies(o, v) && x->o16 < o16_best) o16_best = x->o16;
+    if (!x->scratch && x->applies(o, v) && x->o16 < o16_best) o16_best = x->o16;
   }
   for (int k = 0; k < n; ++k) {
     const ExchangeVariant *x = variant_of(prec, k);
-    if (x->o16 != o16_best || !x->applies(o, v)) continue;
+    if (x->scratch || x->o16 != o16_best || !x->applies(o, v)) continue;
     const double rows = (double)((ns + x->ks - 1) / x->ks) * x->ks;
     const double cols = (double)((v + x->nt - 1) / x->nt) * x->nt;
     const double waste = rows * cols / ((double)ns * v);
@@ -298,7 +322,16 @@ int auto_variant(int prec, int o, int ns, int v) {
   return best;
 }
 
-int auto_splits(const ExchangeVariant *x, int ns, int v, int nq, int cap) {
+int auto_splits(const ExchangeVariant *x, int o, int ns, int v, int nq, int cap, const Layout &L) {
+  if (x->scratch) {
+    // GEMM path: splits of each chunk's Q range for the B_oo product (about two workgroups per
+    // CU), at most the chunk length
+    const size_t per_q = (size_t)v * ns * o * 4;
+    const int qc = (int)std::max<size_t>(1, std::min<size_t>((size_t)nq, L.scratch_bytes / per_q));
+    const int tiles_b = ns * ((v + 127) / 128);
+    int s = (512 + tiles_b - 1) / tiles_b;
+    return std::max(1, std::min({s, std::max(1, qc / 2), cap}));
+  }
   const int tiles = ((ns + x->ks - 1) / x->ks) * ((v + x->nt - 1) / x->nt);
   const int cus = 256;
   // aim at about six rounds of one workgroup per CU (tail below ~15 %), at least 4 Q per split
@@ -327,6 +360,17 @@ rttda_status check_dirs(const double *dir, int nrhs) {
   return RTTDA_OK;
 }
 
+// Scratch bytes handed to the exchange: the GEMM path sizes its Q chunk from them.  The chunk
+// length is fixed per context (what the scratch holds at the largest RHS count, or the tuned
+// chunk), so a batch and a single RHS sum their Q chunks identically.
+size_t scratch_for(const rttda_ctx *ctx, int ns) {
+  if (ctx->L.scratch_bytes == 0) return 0;
+  const size_t per_q_max = (size_t)ctx->v * (2 * (size_t)ctx->R) * ctx->o * 4;
+  size_t qc = std::max<size_t>(1, ctx->L.scratch_bytes / per_q_max);
+  if (ctx->qchunk > 0) qc = std::min(qc, (size_t)ctx->qchunk);
+  return qc * (size_t)ctx->v * ns * ctx->o * 4;
+}
+
 // Coulomb + exchange partials for the current stage input (x32 or xhi/xlo).
 rttda_status enqueue_two_electron(rttda_ctx *ctx, int nrhs) {
   if (ctx->nq == 0) return RTTDA_OK;
@@ -335,7 +379,8 @@ rttda_status enqueue_two_electron(rttda_ctx *ctx, int nrhs) {
   hipStream_t s = ctx->stream;
   const bool pr = ctx->prof.on;
   if (pr) HIP_TRY(ctx->prof.begin(PC_COULOMB, s));
-  HIP_TRY(launch_gemv1(s, ctx->d.b_dtype, ctx->d.b_ov, ctx->x32(), ctx->nq, ov, ns, ctx->dvec()));
+  const int nes = gemv1_chunks(ctx->nq, ov);
+  HIP_TRY(launch_gemv1(s, ctx->d.b_dtype, ctx->d.b_ov, ctx->x32(), ctx->nq, ov, ns, nes, ctx->dvec()));
   HIP_TRY(launch_gemv2(s, ctx->d.b_dtype, ctx->d.b_ov, ctx->dvec(), ctx->nq, ov, ns, ctx->sj, ctx->P()));
   if (pr) HIP_TRY(ctx->prof.end(PC_COULOMB, s));
   const ExchangeVariant *x = variant_of(ctx->prec, ctx->xvar);
@@ -344,7 +389,7 @@ rttda_status enqueue_two_electron(rttda_ctx *ctx, int nrhs) {
   const void *Xlo = ctx->prec == RTTDA_PREC_FP32 ? nullptr : (const void *)ctx->xlo();
   if (pr) HIP_TRY(ctx->prof.begin(PC_EXCHANGE, s));
   HIP_TRY(x->launch(s, ctx->d.b_oo, ctx->d.b_vv, X, Xlo, ctx->o, ctx->v, ctx->nq, ns, ctx->sk, (float)(-ctx->d.cx),
-                    Pk));
+                    Pk, ctx->scratch(), scratch_for(ctx, ns)));
   if (pr) HIP_TRY(ctx->prof.end(PC_EXCHANGE, s));
   return RTTDA_OK;
 }
@@ -438,7 +483,7 @@ rttda_status rttda_create(const rttda_desc *desc, rttda_ctx **out) {
   const int ns_max = 2 * desc->max_rhs;
   int xv = -1;
   if (desc->n_aux > 0) {
-    xv = auto_variant(desc->precision, desc->n_occ, ns_max, desc->n_virt);
+    xv = auto_variant(desc->precision, desc->n_occ, ns_max, desc->n_virt, L);
     if (xv < 0)
       return fail(RTTDA_E_UNSUPPORTED, "no exchange kernel for o=%d in precision %d", desc->n_occ, desc->precision);
   }
@@ -456,7 +501,7 @@ rttda_status rttda_create(const rttda_desc *desc, rttda_ctx **out) {
   ctx->ws = static_cast<char *>(desc->workspace);
   ctx->xvar = xv;
   if (desc->n_aux > 0) {
-    ctx->sk = auto_splits(variant_of(ctx->prec, xv), ns_max, ctx->v, ctx->nq, L.sk_max);
+    ctx->sk = auto_splits(variant_of(ctx->prec, xv), ctx->o, ns_max, ctx->v, ctx->nq, L.sk_max, L);
     ctx->sj = L.sj_max;
   }
   hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&ctx->h_pulses), sizeof(DevPulse) * ctx->R);
@@ -517,7 +562,7 @@ rttda_status rttda_set_tuning(rttda_ctx *ctx, const rttda_tuning *t) {
   if (t->exchange_variant) {
     const ExchangeVariant *x = variant_of(ctx->prec, t->exchange_variant - 1);
     if (!x) return fail(RTTDA_E_UNSUPPORTED, "exchange variant %d does not exist", t->exchange_variant);
-    if (!x->applies(ctx->o, ctx->v))
+    if (!usable(x, ctx->o, ctx->v, ctx->L))
       return fail(RTTDA_E_UNSUPPORTED, "variant %s does not apply to o=%d v=%d", x->name, ctx->o, ctx->v);
     HIP_TRY(x->prepare());
     xv = t->exchange_variant - 1;
@@ -534,11 +579,13 @@ rttda_status rttda_set_tuning(rttda_ctx *ctx, const rttda_tuning *t) {
   }
   if (t->use_graph && t->use_graph != 1 && t->use_graph != 2) return fail(RTTDA_E_INVAL, "use_graph must be 0, 1 or 2");
   if (t->steps_per_graph < 0 || t->steps_per_graph > 1024) return fail(RTTDA_E_INVAL, "steps_per_graph outside 0..1024");
+  if (t->exchange_chunk < -1) return fail(RTTDA_E_INVAL, "exchange_chunk must be -1, 0 or positive");
   if (ctx->nq > 0) {
     ctx->xvar = xv;
     ctx->sk = sk;
     ctx->sj = sj;
   }
+  if (t->exchange_chunk) ctx->qchunk = t->exchange_chunk < 0 ? 0 : t->exchange_chunk;
   if (t->use_graph) ctx->use_graph = t->use_graph;
   if (t->steps_per_graph) ctx->steps_per_graph = t->steps_per_graph;
   drop_graph(ctx);
@@ -552,6 +599,7 @@ rttda_status rttda_get_tuning(const rttda_ctx *ctx, rttda_tuning *t) {
   t->coulomb_splits = ctx->sj;
   t->use_graph = ctx->use_graph;
   t->steps_per_graph = ctx->steps_per_graph;
+  t->exchange_chunk = ctx->qchunk;
   return RTTDA_OK;
 }
 

@@ -250,6 +250,31 @@ def test_mixed_trace_parity_small(gpu_lib):
         assert err < 1e-4
 
 
+def test_mixed_trace_and_peaks_mid_shape(gpu_lib):
+    """Mixed precision at the o40 v300 N_Q1000 shape (BF16 factors, split exchange), x/y/z kicks as
+    3 RHS for 2000 steps of dt 0.05: traces within 1e-4 of the oracle (FP64 eigen route on the same
+    BF16-rounded factors) and every kick-spectrum peak within 1e-4 Ha (same post-processing)."""
+    from oracle import spectrum as S
+
+    o, v, nq = 40, 300, 1000
+    say("[mixed mid shape] o40 v300 N_Q1000, 2000 steps")
+    shape = I.Shape(o, v, nq, b_scale=0.05, storage="bf16")
+    prob, op, ctx = setup(shape, I.SEED_BASE + 4, 3, "mixed")
+    pulses = I.kick_pulses()
+    dt, n = 0.05, 2000
+    got, _, _ = run_trace(gpu_lib, ctx, pulses, dt, n, o, v)
+    say("   oracle eigh (n = 12001) ...")
+    route = O.EigenRoute(op)
+    for r in range(3):
+        ref = route.propagate_field_free(pulses[r], dt, n)
+        err = rel_trace_err(got[:, r], ref)
+        pk = S.peaks(got[:, r], dt, pulses[r].e0, rel_height=0.05, omega_max=8.0)
+        gold = S.peaks(ref, dt, pulses[r].e0, rel_height=0.05, omega_max=8.0)
+        worst = max(min(abs(p - w) for p, _ in pk) for w, _ in gold)
+        say(f"   rhs {r}: trace rel err {err:.2e}; {len(gold)} peaks, worst position error {worst:.2e} Ha")
+        assert err < 1e-4 and worst < 1e-4
+
+
 def _golden_peaks(name):
     import os
 
@@ -341,7 +366,8 @@ def test_bench_shape_sigma_sampled(gpu_lib):
 def test_pulse_scan_batch_64_rhs(gpu_lib):
     """cfg4 shape (o40 v300 N_Q1000), 64 Gaussian-cos carriers in one launch: the first 10 steps of
     8 RHS spread over the batch match the oracle (trace 1e-5, populations |c0|^2 and sum |c_ia|^2
-    within 1e-5 absolute)."""
+    within 1e-5 absolute, populations of the 8 lowest TI-TDA states within 1e-5 absolute and 1e-4
+    of the largest)."""
     import torch
 
     wl = I.workload(4)
@@ -356,6 +382,7 @@ def test_pulse_scan_batch_64_rhs(gpu_lib):
     torch.cuda.synchronize()
     got = tr.cpu().numpy()
     c0g, cg = gpu_lib.from_planes(c0d, cd)
+    refs = []
     for r in range(0, 64, 9):
         ref, c0f, Cf = O.propagate(op, pulses[r], wl.dt, n)
         err = rel_trace_err(got[:, r], ref)
@@ -363,6 +390,15 @@ def test_pulse_scan_batch_64_rhs(gpu_lib):
         pe = abs(np.sum(np.abs(cg[r]) ** 2) - np.sum(np.abs(Cf) ** 2))
         say(f"   rhs {r}: trace {err:.2e}, |c0|^2 {p0:.1e}, sum|c|^2 {pe:.1e}")
         assert err < 1e-5 and p0 < 1e-5 and pe < 1e-5
+        refs.append((r, c0f, Cf))
+    say("   8 lowest TI-TDA states (oracle eigh) ...")
+    w8, U8 = O.lowest_states(op, 8)
+    for r, c0f, Cf in refs:
+        pg = O.state_populations(U8, c0g[r], cg[r])[1:]
+        pf = O.state_populations(U8, c0f, Cf)[1:]
+        d = np.max(np.abs(pg - pf))
+        say(f"   rhs {r}: state populations max {pf.max():.2e}, worst difference {d:.1e}")
+        assert d < 1e-5 and d < 1e-4 * pf.max()
 
 
 def test_cfg2_full_run_spectrum_peaks(gpu_lib):
@@ -461,7 +497,8 @@ def test_cfg3_batched_equals_single_few_steps(gpu_lib):
 
 @pytest.mark.parametrize("o,v,nq,nrhs,prec", [(60, 400, 23, 3, "fp32"), (40, 300, 9, 5, "fp32"), (32, 96, 7, 2, "fp32"),
                                               (60, 400, 11, 3, "mixed"), (96, 200, 5, 1, "mixed"),
-                                              (240, 136, 3, 1, "mixed")])
+                                              (240, 136, 3, 1, "mixed"), (128, 136, 5, 2, "mixed"),
+                                              (136, 200, 7, 3, "mixed")])
 def test_every_exchange_variant_matches_oracle(gpu_lib, o, v, nq, nrhs, prec):
     """Each exchange tile variant that applies to the shape (and a range of Q splits) gives sigma
     within the precision's tolerance of the oracle."""
@@ -491,3 +528,35 @@ def test_every_exchange_variant_matches_oracle(gpu_lib, o, v, nq, nrhs, prec):
                 assert err < SIGMA_TOL[prec], (ctx.variant_name(k), splits, r, err)
             tried += 1
     assert tried >= 2
+
+
+@pytest.mark.parametrize("o,v,nq,nrhs", [(128, 136, 11, 2), (136, 200, 7, 3), (248, 264, 5, 1)])
+def test_gemm_exchange_chunks_match_oracle(gpu_lib, o, v, nq, nrhs):
+    """Large-o GEMM exchange path: Q in chunks of 1..nq (slabs stored by the first chunk and
+    accumulated by later ones), with more splits than Q per chunk, matches the oracle; a batch and
+    a single RHS give bitwise the same sigma."""
+    import torch
+
+    shape = I.Shape(o, v, nq, b_scale=0.05, storage="bf16")
+    prob, op, ctx = setup(shape, 515 + o, nrhs, "mixed")
+    name = ctx.variant_name(ctx.get_tuning()["exchange_variant"])
+    assert name.startswith("bf16x2gemm"), name  # the default for o >= 128 with o, v multiples of 8
+    c0, c = I.random_state(o, v, nrhs, seed=12)
+    dirs = np.tile([[0.0, 1.0, 0.0]], (nrhs, 1))
+    field = np.full(nrhs, -0.02)
+    ref = [O.apply_H(op, O.dipole_blocks(op, dirs[r]), field[r], c0[r], c[r])[1] for r in range(nrhs)]
+    c0d, cd = gpu_lib.to_planes(c0, c)
+    for chunk in (1, 3, nq):
+        for splits in (1, 2, 5):
+            ctx.set_tuning(exchange_splits=min(splits, nq), exchange_chunk=chunk)
+            say(f"[gemm] {name} o={o} v={v} nq={nq} chunk {chunk} splits {splits}")
+            _, sd = ctx.sigma(field, dirs, c0d, cd)
+            torch.cuda.synchronize()
+            _, sgot = gpu_lib.from_planes(torch.zeros_like(c0d), sd)
+            for r in range(nrhs):
+                err = np.max(np.abs(sgot[r] - ref[r])) / np.max(np.abs(ref[r]))
+                assert err < SIGMA_TOL["mixed"], (chunk, splits, r, err)
+            if nrhs > 1:
+                _, s1 = ctx.sigma(field[-1:], dirs[-1:], c0d[-1:].contiguous(), cd[-1:].contiguous())
+                torch.cuda.synchronize()
+                assert torch.equal(s1[0], sd[-1]), (chunk, splits)

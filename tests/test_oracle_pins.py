@@ -460,3 +460,34 @@ def test_sigma_element_matches_full():
     full = O.apply_A(op, C)
     for i, a in [(0, 0), (2, 4), (1, 3)]:
         assert abs(O.sigma_element(op, C, i, a) - full[i, a]) < 1e-14
+
+
+# ------------------------------------------------------------------------------------------
+# Populations of TI-TDA states by projection (eq. populations; states from eq. casida_tda)
+# ------------------------------------------------------------------------------------------
+def test_populations_projection_complete_and_rk4_decay():
+    """All ov states: populations sum to the norm (completeness of the projection); the subset
+    solver's energies equal numpy's full eigh; an eigenstate's population under field-free RK4
+    decays exactly as |R(-i w dt)|^(2n) and no other state gets any."""
+    op = tiny_op(o=3, v=4, nq=4)
+    n = op.o * op.v
+    w, U = O.lowest_states(op, n)
+    assert np.allclose(w, np.linalg.eigvalsh(O.dense_A(op)), atol=1e-13, rtol=0)
+    rng = np.random.default_rng(3)
+    C = rng.standard_normal((3, 4)) + 1j * rng.standard_normal((3, 4))
+    c0 = 0.3 - 0.2j
+    P = O.state_populations(U, c0, C)
+    assert abs(P.sum() - O.norm2(c0, C)) < 1e-13
+    # the k lowest from a smaller subset are the same states
+    w3, U3 = O.lowest_states(op, 3)
+    assert np.allclose(w3, w[:3], atol=1e-13, rtol=0)
+    assert np.allclose(np.abs(U3.T @ U[:, :3]), np.eye(3), atol=1e-10)
+    # field-free RK4 from the second state: only that population, decaying by |R|^(2n)
+    I_ = 1
+    x0 = U[:, I_].reshape(3, 4).astype(np.complex128)
+    dt, nsteps = 0.3, 40
+    _, c0n, Cn = O.propagate(op, pulse(I.PULSE_NONE), dt, nsteps, c0=0.0 + 0j, C=x0)
+    Pn = O.state_populations(U, c0n, Cn)
+    expect = abs(O.rk4_amplification(-1j * w[I_] * dt)) ** (2 * nsteps)
+    assert abs(Pn[1 + I_] - expect) < 1e-12
+    assert np.max(np.delete(Pn, 1 + I_)) < 1e-24
