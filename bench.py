@@ -157,6 +157,8 @@ def main():
     ap.add_argument("--variant", type=int, default=0)
     ap.add_argument("--splits", type=int, default=0)
     ap.add_argument("--precision", default=None, help="override the workload's precision (fp32 | mixed)")
+    ap.add_argument("--integrator", default="rk4", choices=("rk4", "sso"),
+                    help="rk4 (4 complex sigma per step) or the split operator sso (2 real sigma per step)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -203,7 +205,7 @@ def main():
         tuned = ctx.use_tuned(R)
     tun = ctx.get_tuning()
     c0, c = rttda.ground_state(R, dev.o, dev.v)
-    ctx.propagate(wl.pulses, wl.dt, args.warmup, c0, c)
+    ctx.propagate(wl.pulses, wl.dt, args.warmup, c0, c, integrator=args.integrator)
     torch.cuda.synchronize()
     print(f"# warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
 
@@ -211,7 +213,7 @@ def main():
     trace = torch.empty((args.steps + 1, R), dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ctx.propagate(wl.pulses, wl.dt, args.steps, c0, c, step0=args.warmup, trace=trace)
+    ctx.propagate(wl.pulses, wl.dt, args.steps, c0, c, step0=args.warmup, trace=trace, integrator=args.integrator)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = ctx.get_profile()
@@ -222,12 +224,15 @@ def main():
 
     o, v, nq = dev.o, dev.v, dev.nq
     fc, fx = flops_per_sigma(o, v, nq)
-    sigma_flops = args.steps * 4 * R * (fc + fx)
+    # RK4: 4 complex sigma per step; split operator: 2 real sigma (= 1 complex) per step
+    sigmas_per_step = 4 if args.integrator == "rk4" else 1
+    sigma_flops = args.steps * sigmas_per_step * R * (fc + fx)
     value = sigma_flops / elapsed / 1e9
     fs_h = args.steps * wl.dt * AU_FS * R / (elapsed / 3600.0)
     ex = prof["exchange"]
     ex_avg_ms = ex["ms"] / max(ex["launches"], 1)
-    ex_flops = R * fx  # one launch covers all 2R slices of one stage
+    # one launch covers all slices of one stage: 2R (complex RK4 stage) or R (real half step)
+    ex_flops = R * fx if args.integrator == "rk4" else R * fx / 2
     achieved = ex_flops / (ex_avg_ms * 1e-3) / 1e12
     peak = PEAK[wl.precision]
     breakdown = {k: {"launches": d["launches"], "avg_us": round(1e3 * d["ms"] / max(d["launches"], 1), 2),
@@ -246,6 +251,7 @@ def main():
         "dtype": "f32" if wl.precision == "fp32" else "bf16x2+f32",
         "data": "synthetic",
         "config": {"workload": wl.name, "o": o, "v": v, "n_aux": nq, "nrhs": R, "dt": wl.dt,
+                   "integrator": args.integrator,
                    "precision": wl.precision, "exchange_variant": ctx.variant_name(tun["exchange_variant"]),
                    "exchange_splits": tun["exchange_splits"], "coulomb_splits": tun["coulomb_splits"],
                    "autotuned": tuned,

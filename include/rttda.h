@@ -147,6 +147,17 @@ rttda_status rttda_propagate(rttda_ctx *ctx, int32_t nrhs, const rttda_pulse *pu
                              int64_t step0, int64_t n_steps, double *c0, double *c, double *trace,
                              double *norms);
 
+/* As rttda_propagate with the paper's integrator instead of RK4: the second-order
+ * symplectic split operator on X = q + i p (Propagation Algorithm subsection,
+ * eq. x_real_imagiary and the symplectic form dq/dt = H p, dp/dt = -H q), one
+ * step being  p <- p - dt/2 H(t) q;  q <- q + dt H(t + dt/2) p;  p <- p - dt/2 H(t + dt) q.
+ * Two real sigma per step (the two half kicks of consecutive steps share one),
+ * against four complex sigma for RK4; the norm oscillates at O(dt^2) without
+ * drift.  Same arguments, kick, trace, norms and guard as rttda_propagate. */
+rttda_status rttda_propagate_sso(rttda_ctx *ctx, int32_t nrhs, const rttda_pulse *pulses, double dt,
+                                 int64_t step0, int64_t n_steps, double *c0, double *c, double *trace,
+                                 double *norms);
+
 /* out[r] = Re <X_r | M_dr | X_r> (f64 [nrhs]) for states c0, c and host unit
  * vectors dir ([nrhs][3]): the observable behind every trace sample. */
 rttda_status rttda_dipole_trace(rttda_ctx *ctx, int32_t nrhs, const double *dir, const double *c0,
@@ -154,7 +165,8 @@ rttda_status rttda_dipole_trace(rttda_ctx *ctx, int32_t nrhs, const double *dir,
 
 /* Synchronise the context's stream and report the norm guard of the last
  * rttda_propagate: *first_bad_step = -1 if it never tripped, else the absolute
- * step index; returns RTTDA_E_UNSTABLE in the latter case. */
+ * step index; returns RTTDA_E_UNSTABLE in the latter case.  Covers
+ * rttda_propagate_sso alike. */
 rttda_status rttda_guard(rttda_ctx *ctx, int64_t *first_bad_step);
 
 /* Launch configuration knobs (for the autotuner).  Zero fields keep the

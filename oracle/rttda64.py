@@ -25,6 +25,8 @@ real-time Tamm-Dancoff approximation", arxiv 2601.16949):
   X <- X + i kappa mu.d X before the first step (text on the delta pulse in the
   Propagation Algorithm subsection: the response stays linear in the pulse).
 * The observable: the dipole trace mu(t_n) = Re <X_n | mu.d | X_n>, and the norm.
+* The paper's own integrator, second-order symplectic split operator on X = q + i p
+  (Propagation Algorithm subsection), as a second propagation route.
 
 Arrays: a state is (c0, C) with c0 complex scalar and C complex (o, v).
 """
@@ -288,6 +290,58 @@ def propagate(op: Operator, pulse, dt: float, n_steps: int, c0=1.0 + 0j, C=None,
 
 
 # ----------------------------------------------------------------------------------------
+# Second-order symplectic split-operator (SSO) propagation (Propagation Algorithm
+# subsection: X = q + i p, eq. x_real_imagiary; dq/dt = H p, dp/dt = -H q)
+# ----------------------------------------------------------------------------------------
+def apply_H_real(op: Operator, blocks, E: float, x0: float, X: np.ndarray):
+    """H(t) x for a real vector x = (x0, X); H is real symmetric, so the result is real."""
+    h0, hX = apply_H(op, blocks, E, x0, X)
+    return float(np.real(h0)), np.real(hX)
+
+
+def sso_step(op: Operator, blocks, pulse, dt: float, n: int, q0, Q, p0, P):
+    """One symmetric kick-drift-kick step from t = n dt of the symplectic form:
+        p <- p - dt/2 H(t_n) q;   q <- q + dt H(t_n + dt/2) p;   p <- p - dt/2 H(t_n + dt) q."""
+    h0, hQ = apply_H_real(op, blocks, field_value(pulse, n * dt), q0, Q)
+    p0, P = p0 - 0.5 * dt * h0, P - 0.5 * dt * hQ
+    g0, gP = apply_H_real(op, blocks, field_value(pulse, (n + 0.5) * dt), p0, P)
+    q0, Q = q0 + dt * g0, Q + dt * gP
+    h0, hQ = apply_H_real(op, blocks, field_value(pulse, (n + 1) * dt), q0, Q)
+    p0, P = p0 - 0.5 * dt * h0, P - 0.5 * dt * hQ
+    return q0, Q, p0, P
+
+
+def propagate_sso(op: Operator, pulse, dt: float, n_steps: int, c0=1.0 + 0j, C=None, step0: int = 0,
+                  want_norm: bool = False):
+    """As propagate() with the SSO step instead of RK4 (same kick, trace and norm)."""
+    if C is None:
+        C = np.zeros((op.o, op.v), dtype=np.complex128)
+    c0 = complex(c0)
+    C = np.array(C, dtype=np.complex128)
+    blocks = dipole_blocks(op, pulse.direction)
+    if pulse.kind == PULSE_DELTA and step0 == 0:
+        c0, C = kick(blocks, pulse.e0, c0, C)
+    q0, Q, p0, P = c0.real, C.real.copy(), c0.imag, C.imag.copy()
+    trace = np.empty(n_steps + 1)
+    norms = np.empty(n_steps + 1)
+    trace[0] = dipole_expectation(blocks, c0, C)
+    norms[0] = norm2(c0, C)
+    for n in range(n_steps):
+        q0, Q, p0, P = sso_step(op, blocks, pulse, dt, step0 + n, q0, Q, p0, P)
+        c0, C = complex(q0, p0), Q + 1j * P
+        trace[n + 1] = dipole_expectation(blocks, c0, C)
+        norms[n + 1] = norm2(c0, C)
+    if want_norm:
+        return trace, c0, C, norms
+    return trace, c0, C
+
+
+def sso_mode_matrix(a: float) -> np.ndarray:
+    """The SSO step acting on one field-free eigenmode (q, p) of frequency w, a = w dt."""
+    return np.array([[1.0 - a * a / 2.0, a], [-a * (1.0 - a * a / 4.0), 1.0 - a * a / 2.0]])
+
+
+# ----------------------------------------------------------------------------------------
 # Eigen route (O2): dense A, eigh, and RK4 in the eigenbasis
 # ----------------------------------------------------------------------------------------
 def rk4_amplification(z):
@@ -352,10 +406,17 @@ class EigenRoute:
         Me = self.dipole_eig(pulse.direction)
         R = rk4_amplification(-1j * self.w * dt)
         trace = np.empty(n_steps + 1)
-        for n in range(n_steps + 1):
-            trace[n] = float(np.real(np.conj(y) @ (Me @ y)))
-            if n < n_steps:
-                y = R * y
+        # trace[n] = Re y_n^H Me y_n with y_{n+1} = R y_n, evaluated for a block of steps at a
+        # time (one matrix product per block instead of one matrix-vector product per step)
+        block = 256
+        for n0 in range(0, n_steps + 1, block):
+            nb = min(block, n_steps + 1 - n0)
+            Y = np.empty((nb, y.size), dtype=np.complex128)
+            for k in range(nb):
+                Y[k] = y
+                if n0 + k < n_steps:
+                    y = R * y
+            trace[n0:n0 + nb] = np.real(np.sum(np.conj(Y) * (Y @ Me), axis=1))
         if want_state:
             return trace, y
         return trace

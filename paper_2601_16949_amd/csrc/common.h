@@ -53,6 +53,8 @@ enum : int {
 
 // Epilogue modes.
 enum : int { EP_RK4 = 0, EP_SIGMA = 1 };
+// symplectic split-operator update modes (k_sso_update)
+enum : int { SSO_KICK_FIRST = 0, SSO_KICK = 1, SSO_DRIFT = 2 };
 
 // ---------------------------------------------------------------------------------------------
 // Kernel launchers (all enqueue on `s`, return hipError_t of the launch)
@@ -80,6 +82,12 @@ hipError_t launch_epilogue(hipStream_t s, int prec, int R, int o, int v, int nsl
                            int use_field, double dt, const double *D, const float *P, const double *F,
                            const double *sc, const double *Xin, double *c, double *acc, double *xs64, float *x32,
                            __hip_bfloat16 *xhi, __hip_bfloat16 *xlo, double *s_out);
+hipError_t launch_sso_update(hipStream_t s, int prec, int R, int o, int v, int nslab, int mode, int use_field,
+                             double dt, const double *D, const float *P, const double *F, const double *sc, double *c,
+                             double *c0, double *W, double *W0, float *x32, __hip_bfloat16 *xhi,
+                             __hip_bfloat16 *xlo);
+hipError_t launch_plane_copy(hipStream_t s, int prec, int R, size_t ov, int plane, const double *c, float *x32,
+                             __hip_bfloat16 *xhi, __hip_bfloat16 *xlo);
 hipError_t launch_kick(hipStream_t s, int R, int ov, const DevPulse *pulses, const double *F, const double *sc,
                        double *c, double *c0);
 hipError_t launch_set_state(hipStream_t s, DevState *st, long long step0, double *trace, double *norms);

@@ -101,6 +101,11 @@ __global__ __launch_bounds__(256, 2) void k_exchange_bf16_dl(const __bf16 *__res
   int nvalid = 0;
 #pragma unroll
   for (int cb = 0; cb < WC; ++cb) nvalid += (c_base + (wc * WC + cb) * 32 < v) ? 1 : 0;
+  // (nvalid is wave-uniform)
+  // the zero page's address stays in registers for the whole kernel (re-deriving it inside the
+  // loop puts a scalar memory load among the LDS reads, which forces full LDS waits)
+  const void *zp = g_zero_page_b;
+  asm volatile("" : "+s"(zp));
   const int lrow = lane >> 2;
 
   auto issue = [&](int c) {
@@ -113,8 +118,8 @@ __global__ __launch_bounds__(256, 2) void k_exchange_bf16_dl(const __bf16 *__res
       const int sl = s_base + r / O32, j = r % O32;
       const bool ok = sl < ns && j < o && a < v;
       const size_t off = ((size_t)sl * o + j) * v + a;
-      dma16(ok ? (const void *)(Xh + off) : (const void *)g_zero_page_b, Xh0 + buf * C::XS + r0 * KC);
-      dma16(ok ? (const void *)(Xl + off) : (const void *)g_zero_page_b, Xl0 + buf * C::XS + r0 * KC);
+      dma16(ok ? (const void *)(Xh + off) : zp, Xh0 + buf * C::XS + r0 * KC);
+      dma16(ok ? (const void *)(Xl + off) : zp, Xl0 + buf * C::XS + r0 * KC);
     }
     const __bf16 *Vq = Bvv + (size_t)q * v * v;
 #pragma unroll
@@ -123,7 +128,7 @@ __global__ __launch_bounds__(256, 2) void k_exchange_bf16_dl(const __bf16 *__res
       const int a = a0 + 8 * ((lane & 3) ^ swz(r));
       const int cc = c_base + r;
       const bool ok = cc < v && a < v;
-      dma16(ok ? (const void *)(Vq + (size_t)cc * v + a) : (const void *)g_zero_page_b,
+      dma16(ok ? (const void *)(Vq + (size_t)cc * v + a) : zp,
               Bs0 + buf * C::BS + r0 * KC);
     }
   };
@@ -135,7 +140,7 @@ __global__ __launch_bounds__(256, 2) void k_exchange_bf16_dl(const __bf16 *__res
       const int i = d / (O32 / 2), w = d % (O32 / 2);
       const int jl = 2 * (4 * ((w >> 2) ^ swz_o(i)) + (w & 3));  // logical column (bf16)
       const bool ok = d < C::ODW && i < o && jl < o;
-      dma4(ok ? (const void *)(Oq + (size_t)i * o + jl) : (const void *)g_zero_page_b, Os + 2 * d0);
+      dma4(ok ? (const void *)(Oq + (size_t)i * o + jl) : zp, Os + 2 * d0);
     }
   };
 
@@ -163,29 +168,41 @@ __global__ __launch_bounds__(256, 2) void k_exchange_bf16_dl(const __bf16 *__res
     const __bf16 *Xls = Xl0 + buf * C::XS;
     const __bf16 *Bs = Bs0 + buf * C::BS;
     const int klim = v - kc * KC;
+    // each K step's operand fragments are read into registers before its MFMAs (one LDS wait per
+    // K step instead of one per fragment); the next step's reads overlap these MFMAs
 #pragma unroll
     for (int u = 0; u < 2; ++u) {  // two MFMA K steps of 16 per chunk
-      if (16 * u < klim) {
-        bf8 bf[WC];
+      bf8 bf[WC], ah[WS][JB], al[WS][JB];
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) {
-          const int r = (wc * WC + cb) * 32 + m;
-          bf[cb] = *reinterpret_cast<const bf8 *>(&Bs[r * KC + 8 * ((2 * u + h) ^ swz(r))]);
+      for (int cb = 0; cb < NCB; ++cb) {
+        const int r = (wc * WC + cb) * 32 + m;
+        bf[cb] = *reinterpret_cast<const bf8 *>(&Bs[r * KC + 8 * ((2 * u + h) ^ swz(r))]);
+      }
+#pragma unroll
+      for (int si = 0; si < WS; ++si)
+#pragma unroll
+        for (int jb = 0; jb < JB; ++jb) {
+          const int r = (ws * WS + si) * O32 + jb * 32 + m;
+          const int co = r * KC + 8 * ((2 * u + h) ^ swz(r));
+          ah[si][jb] = *reinterpret_cast<const bf8 *>(&Xhs[co]);
+          al[si][jb] = *reinterpret_cast<const bf8 *>(&Xls[co]);
         }
+      __builtin_amdgcn_sched_barrier(0);
+      if (16 * u < klim) {
 #pragma unroll
         for (int si = 0; si < WS; ++si)
 #pragma unroll
-          for (int jb = 0; jb < JB; ++jb) {
-            const int r = (ws * WS + si) * O32 + jb * 32 + m;
-            const int co = r * KC + 8 * ((2 * u + h) ^ swz(r));
-            const bf8 ah = *reinterpret_cast<const bf8 *>(&Xhs[co]);
-            const bf8 al = *reinterpret_cast<const bf8 *>(&Xls[co]);
+          for (int jb = 0; jb < JB; ++jb)
 #pragma unroll
-            for (int cb = 0; cb < NCB; ++cb) {
-              Wacc[si][jb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bf[cb], Wacc[si][jb][cb], 0, 0, 0);
-              Wacc[si][jb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bf[cb], Wacc[si][jb][cb], 0, 0, 0);
-            }
-          }
+            for (int cb = 0; cb < NCB; ++cb)
+              Wacc[si][jb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[si][jb], bf[cb], Wacc[si][jb][cb], 0, 0, 0);
+#pragma unroll
+        for (int si = 0; si < WS; ++si)
+#pragma unroll
+          for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb)
+              Wacc[si][jb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[si][jb], bf[cb], Wacc[si][jb][cb], 0, 0, 0);
       }
     }
     if (kc == nkc - 1) {
@@ -206,19 +223,27 @@ __global__ __launch_bounds__(256, 2) void k_exchange_bf16_dl(const __bf16 *__res
                 wl[si][cb][e] = (__bf16)(w - (float)hi);
               }
           const int j0 = jb * 32 + 16 * u + 4 * h;
+          bf8 ar[JB];
 #pragma unroll
           for (int ib = 0; ib < JB; ++ib) {
             const int i = ib * 32 + m;
             const bf4 lo4 = os4(i, j0), hi4 = os4(i, j0 + 8);
-            const bf8 ar = bf8{lo4[0], lo4[1], lo4[2], lo4[3], hi4[0], hi4[1], hi4[2], hi4[3]};
+            ar[ib] = bf8{lo4[0], lo4[1], lo4[2], lo4[3], hi4[0], hi4[1], hi4[2], hi4[3]};
+          }
+#pragma unroll
+          for (int ib = 0; ib < JB; ++ib)
 #pragma unroll
             for (int si = 0; si < WS; ++si)
 #pragma unroll
-              for (int cb = 0; cb < NCB; ++cb) {
-                Kacc[si][ib][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar, wh[si][cb], Kacc[si][ib][cb], 0, 0, 0);
-                Kacc[si][ib][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar, wl[si][cb], Kacc[si][ib][cb], 0, 0, 0);
-              }
-          }
+              for (int cb = 0; cb < NCB; ++cb)
+                Kacc[si][ib][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar[ib], wh[si][cb], Kacc[si][ib][cb], 0, 0, 0);
+#pragma unroll
+          for (int ib = 0; ib < JB; ++ib)
+#pragma unroll
+            for (int si = 0; si < WS; ++si)
+#pragma unroll
+              for (int cb = 0; cb < NCB; ++cb)
+                Kacc[si][ib][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar[ib], wl[si][cb], Kacc[si][ib][cb], 0, 0, 0);
         }
 #pragma unroll
       for (int a = 0; a < WS; ++a)

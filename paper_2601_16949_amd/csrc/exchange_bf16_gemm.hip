@@ -116,6 +116,11 @@ __global__ __launch_bounds__(64 * NWC * NWR, 1) void k_xgemm_w(const __bf16 *__r
 #pragma unroll
   for (int cb = 0; cb < CB; ++cb) nvalid += (c_base + (wc * CB + cb) * 32 < v) ? 1 : 0;
   if (r_base + wr * RB * 32 >= M) nvalid = 0;  // no rows of this wave exist
+  // (nvalid is wave-uniform)
+  // the zero page's address stays in registers for the whole kernel (re-deriving it inside the
+  // loop puts a scalar memory load among the LDS reads, which forces full LDS waits)
+  const void *zp = g_zero_page_g;
+  asm volatile("" : "+s"(zp));
 
   auto issue = [&](int kc) {
     const int a0 = kc * KC, buf = kc % 3;
@@ -125,7 +130,7 @@ __global__ __launch_bounds__(64 * NWC * NWR, 1) void k_xgemm_w(const __bf16 *__r
       const int a = a0 + 8 * ((lane & 3) ^ swz(r));
       const int cc = c_base + r;
       const bool ok = cc < v && a < v;
-      dma16(ok ? (const void *)(Vq + (size_t)cc * v + a) : (const void *)g_zero_page_g, As0 + buf * C::AS + r0 * KC);
+      dma16(ok ? (const void *)(Vq + (size_t)cc * v + a) : zp, As0 + buf * C::AS + r0 * KC);
     }
 #pragma unroll
     for (int k = 0; k < NB; ++k) {
@@ -134,8 +139,8 @@ __global__ __launch_bounds__(64 * NWC * NWR, 1) void k_xgemm_w(const __bf16 *__r
       const int rr = r_base + r;
       const bool ok = rr < M && a < v;
       const size_t off = (size_t)rr * v + a;
-      dma16(ok ? (const void *)(Xh + off) : (const void *)g_zero_page_g, Xh0 + buf * C::BS + r0 * KC);
-      dma16(ok ? (const void *)(Xl + off) : (const void *)g_zero_page_g, Xl0 + buf * C::BS + r0 * KC);
+      dma16(ok ? (const void *)(Xh + off) : zp, Xh0 + buf * C::BS + r0 * KC);
+      dma16(ok ? (const void *)(Xl + off) : zp, Xl0 + buf * C::BS + r0 * KC);
     }
   };
 
@@ -145,67 +150,103 @@ __global__ __launch_bounds__(64 * NWC * NWR, 1) void k_xgemm_w(const __bf16 *__r
 #pragma unroll
     for (int b = 0; b < RB; ++b) acc[a][b] = zero16();
 
-  auto compute_n = [&](auto ncb_tag, int kc) {
-    constexpr int NCB = decltype(ncb_tag)::value;
-    const int buf = kc % 3, klim = v - kc * KC;
-    const __bf16 *As = As0 + buf * C::AS;
-    const __bf16 *Xhs = Xh0 + buf * C::BS;
-    const __bf16 *Xls = Xl0 + buf * C::BS;
+  struct Frag {
+    bf8 a[CB], xh[RB], xl[RB];
+  };
+  // part 0: the B_vv fragments and X_hi; part 1: X_lo (used by the second half of the MFMAs)
+  auto read_part = [&](int kc, int u, int part, Frag &F) {
+    const int buf = kc % 3;
+    if (part == 0) {
+      const __bf16 *As = As0 + buf * C::AS;
+      const __bf16 *Xhs = Xh0 + buf * C::BS;
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      if (16 * u < klim) {
-        bf8 bh[RB], bl[RB];
+      for (int cb = 0; cb < CB; ++cb) {
+        const int r = (wc * CB + cb) * 32 + m;
+        F.a[cb] = *reinterpret_cast<const bf8 *>(&As[r * KC + 8 * ((2 * u + h) ^ swz(r))]);
+      }
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb) {
-          const int r = (wr * RB + rb) * 32 + m;
-          const int co = r * KC + 8 * ((2 * u + h) ^ swz(r));
-          bh[rb] = *reinterpret_cast<const bf8 *>(&Xhs[co]);
-          bl[rb] = *reinterpret_cast<const bf8 *>(&Xls[co]);
-        }
+      for (int rb = 0; rb < RB; ++rb) {
+        const int r = (wr * RB + rb) * 32 + m;
+        F.xh[rb] = *reinterpret_cast<const bf8 *>(&Xhs[r * KC + 8 * ((2 * u + h) ^ swz(r))]);
+      }
+    } else {
+      const __bf16 *Xls = Xl0 + buf * C::BS;
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) {
-          const int r = (wc * CB + cb) * 32 + m;
-          const bf8 af = *reinterpret_cast<const bf8 *>(&As[r * KC + 8 * ((2 * u + h) ^ swz(r))]);
-#pragma unroll
-          for (int rb = 0; rb < RB; ++rb) {
-            acc[cb][rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af, bh[rb], acc[cb][rb], 0, 0, 0);
-            acc[cb][rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af, bl[rb], acc[cb][rb], 0, 0, 0);
-          }
-        }
+      for (int rb = 0; rb < RB; ++rb) {
+        const int r = (wr * RB + rb) * 32 + m;
+        F.xl[rb] = *reinterpret_cast<const bf8 *>(&Xls[r * KC + 8 * ((2 * u + h) ^ swz(r))]);
       }
     }
   };
-  auto compute = [&](int kc) {
-    static_assert(CB >= 1 && CB <= 4, "column blocks per wave");
-    if (nvalid == CB) {
-      compute_n(std::integral_constant<int, CB>{}, kc);
-    } else {
-      if constexpr (CB >= 4) {
-        if (nvalid == 3) compute_n(std::integral_constant<int, 3>{}, kc);
-      }
-      if constexpr (CB >= 3) {
-        if (nvalid == 2) compute_n(std::integral_constant<int, 2>{}, kc);
-      }
-      if constexpr (CB >= 2) {
-        if (nvalid == 1) compute_n(std::integral_constant<int, 1>{}, kc);
-      }
-    }
+  // one half of a K step's products: X_hi (part 0) or X_lo (part 1) against the B_vv fragments
+  auto mfma_part = [&](auto ncb_tag, const Frag &F, int part) {
+    constexpr int NCB = decltype(ncb_tag)::value;
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+        acc[cb][rb] =
+            __builtin_amdgcn_mfma_f32_32x32x16_bf16(F.a[cb], part ? F.xl[rb] : F.xh[rb], acc[cb][rb], 0, 0, 0);
   };
 
-  issue(0);
-  if (nkc > 1) {
+  // The pipelined loop, specialised on this wave's count of valid column blocks (wave-uniform;
+  // only the last column tile has fewer than CB).  Choosing the specialisation once, outside the
+  // loop, keeps branches out of it.  Waves without valid blocks (NCB = 0) still take part in
+  // every load and barrier.  Per chunk kc, after the barrier that publishes it: issue the loads of
+  // chunk kc+2, read K step 0's fragments (F0), run K step 1 of chunk kc-1 (F1, read before the
+  // barrier) while they arrive, then the X_hi half of K step 0, then read K step 1's fragments
+  // into F1 while the X_lo half runs (at most 8 LDS reads are outstanding at any wait, inside
+  // the wait counter's range).  Chunks past the end (kc >= nkc) are issued too: their addresses
+  // fall outside [0, v), so they load the zero page into a consumed buffer, which keeps the loop
+  // free of branches around the loads.
+  auto main_loop = [&](auto ncb_tag) {
+    Frag F0, F1;
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) F1.a[cb] = bf8{};  // "K step 1 of chunk -1": adds zero
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) F1.xh[rb] = F1.xl[rb] = bf8{};
+    issue(0);
     issue(1);
-    wait_vm<NL>();
+    for (int kc = 0; kc < nkc; ++kc) {
+      wait_vm<NL>();  // chunk kc has landed (chunk kc+1 may be in flight)
+      lds_barrier();  // publishes chunk kc; every wave has read chunk kc-1's buffer
+      issue(kc + 2);  // into chunk kc-1's buffer, two chunks ahead of its use
+      __builtin_amdgcn_sched_barrier(0);
+      read_part(kc, 0, 0, F0);
+      read_part(kc, 0, 1, F0);
+      __builtin_amdgcn_sched_barrier(0);
+      // second K step of chunk kc-1 (a full chunk: only the last chunk can end inside a step)
+      mfma_part(ncb_tag, F1, 0);
+      mfma_part(ncb_tag, F1, 1);
+      __builtin_amdgcn_sched_barrier(0);
+      mfma_part(ncb_tag, F0, 0);  // K step 0 of a chunk always lies inside [0, v)
+      __builtin_amdgcn_sched_barrier(0);
+      read_part(kc, 1, 0, F1);
+      read_part(kc, 1, 1, F1);
+      __builtin_amdgcn_sched_barrier(0);
+      mfma_part(ncb_tag, F0, 1);
+    }
+    if (16 < v - (nkc - 1) * KC) {
+      mfma_part(ncb_tag, F1, 0);
+      mfma_part(ncb_tag, F1, 1);
+    }
+    wait_vm<0>();  // no LDS write may still be in flight when the workgroup ends
+  };
+  static_assert(CB >= 1 && CB <= 4, "column blocks per wave");
+  if (nvalid == CB) {
+    main_loop(std::integral_constant<int, CB>{});
+  } else if (nvalid == 0) {
+    main_loop(std::integral_constant<int, 0>{});
   } else {
-    wait_vm<0>();
-  }
-  lds_barrier();
-  for (int kc = 0; kc < nkc; ++kc) {
-    const bool more = kc + 2 < nkc;
-    if (more) issue(kc + 2);
-    compute(kc);
-    if (more) wait_vm<NL>(); else wait_vm<0>();
-    lds_barrier();
+    if constexpr (CB >= 4) {
+      if (nvalid == 3) main_loop(std::integral_constant<int, 3>{});
+    }
+    if constexpr (CB >= 3) {
+      if (nvalid == 2) main_loop(std::integral_constant<int, 2>{});
+    }
+    if constexpr (CB >= 2) {
+      if (nvalid == 1) main_loop(std::integral_constant<int, 1>{});
+    }
   }
 
   // store W^T as hi/lo planes: register t of lane (32h + m) holds row c = 8(t/4) + 4h + t%4,
@@ -274,16 +315,22 @@ __global__ __launch_bounds__(64 * NWM * NWN, 1) void k_boo_w(const __bf16 *__res
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) nvalid += (c_base + (wn * NB + nb) * 32 < v) ? 1 : 0;
   if (wm * MB * 32 >= o) nvalid = 0;
+  // (nvalid is wave-uniform)
+  // the zero page's address stays in registers for the whole kernel (re-deriving it inside the
+  // loop puts a scalar memory load among the LDS reads, which forces full LDS waits)
+  const void *zp = g_zero_page_g;
+  asm volatile("" : "+s"(zp));
 
-  auto issue = [&](int c) {
-    const int qq = qa + c / nkj, j0 = (c % nkj) * KC, buf = c % 3;
+  auto issue = [&](int c) {  // chunks c >= NC (past the end) load the zero page
+    const bool live = c < NC;
+    const int qq = live ? qa + c / nkj : qa, j0 = (c % nkj) * KC, buf = c % 3;
     const __bf16 *Oq = Boo + (size_t)(q0 + qq) * o * o;
 #pragma unroll
     for (int k = 0; k < NA; ++k) {
       const int r0 = (wave * NA + k) * 16, r = r0 + lrow;
       const int j = j0 + 8 * ((lane & 3) ^ swz(r));
-      const bool ok = r < o && j < o;
-      dma16(ok ? (const void *)(Oq + (size_t)r * o + j) : (const void *)g_zero_page_g, As0 + buf * C::AS + r0 * KC);
+      const bool ok = live && r < o && j < o;
+      dma16(ok ? (const void *)(Oq + (size_t)r * o + j) : zp, As0 + buf * C::AS + r0 * KC);
     }
     const size_t wq = (size_t)qq * v * M + (size_t)sl * o;
 #pragma unroll
@@ -291,10 +338,10 @@ __global__ __launch_bounds__(64 * NWM * NWN, 1) void k_boo_w(const __bf16 *__res
       const int r0 = (wave * NBL + k) * 16, r = r0 + lrow;
       const int j = j0 + 8 * ((lane & 3) ^ swz(r));
       const int cc = c_base + r;
-      const bool ok = cc < v && j < o;
+      const bool ok = live && cc < v && j < o;
       const size_t off = wq + (size_t)cc * M + j;
-      dma16(ok ? (const void *)(Wh + off) : (const void *)g_zero_page_g, Wh0 + buf * C::BS + r0 * KC);
-      dma16(ok ? (const void *)(Wl + off) : (const void *)g_zero_page_g, Wl0 + buf * C::BS + r0 * KC);
+      dma16(ok ? (const void *)(Wh + off) : zp, Wh0 + buf * C::BS + r0 * KC);
+      dma16(ok ? (const void *)(Wl + off) : zp, Wl0 + buf * C::BS + r0 * KC);
     }
   };
 
@@ -304,69 +351,82 @@ __global__ __launch_bounds__(64 * NWM * NWN, 1) void k_boo_w(const __bf16 *__res
 #pragma unroll
     for (int b = 0; b < NB; ++b) acc[a][b] = zero16();
 
-  auto compute_n = [&](auto nnb_tag, int c) {
-    constexpr int NNB = decltype(nnb_tag)::value;
-    const int buf = c % 3, klim = o - (c % nkj) * KC;
+  // Same pipeline as the first kernel (see there): K step 0's fragments are read right after the
+  // barrier while K step 1 of the previous chunk runs; K step 1's are read during the W_lo half of
+  // K step 0.  Steps past o read zero rows of the B_oo tile and add nothing.
+  struct Frag {
+    bf8 a[MB], wh[NB], wl[NB];
+  };
+  auto read_step = [&](int c, int u, Frag &F) {
+    const int buf = c % 3;
     const __bf16 *As = As0 + buf * C::AS;
     const __bf16 *Whs = Wh0 + buf * C::BS;
     const __bf16 *Wls = Wl0 + buf * C::BS;
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      if (16 * u < klim) {
-        bf8 bh[NB], bl[NB];
+    for (int mb = 0; mb < MB; ++mb) {
+      const int r = (wm * MB + mb) * 32 + m;
+      F.a[mb] = *reinterpret_cast<const bf8 *>(&As[r * KC + 8 * ((2 * u + h) ^ swz(r))]);
+    }
 #pragma unroll
-        for (int nb = 0; nb < NNB; ++nb) {
-          const int r = (wn * NB + nb) * 32 + m;
-          const int co = r * KC + 8 * ((2 * u + h) ^ swz(r));
-          bh[nb] = *reinterpret_cast<const bf8 *>(&Whs[co]);
-          bl[nb] = *reinterpret_cast<const bf8 *>(&Wls[co]);
-        }
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb) {
-          const int r = (wm * MB + mb) * 32 + m;
-          const bf8 af = *reinterpret_cast<const bf8 *>(&As[r * KC + 8 * ((2 * u + h) ^ swz(r))]);
-#pragma unroll
-          for (int nb = 0; nb < NNB; ++nb) {
-            acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af, bh[nb], acc[mb][nb], 0, 0, 0);
-            acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af, bl[nb], acc[mb][nb], 0, 0, 0);
-          }
-        }
-      }
+    for (int nb = 0; nb < NB; ++nb) {
+      const int r = (wn * NB + nb) * 32 + m;
+      const int co = r * KC + 8 * ((2 * u + h) ^ swz(r));
+      F.wh[nb] = *reinterpret_cast<const bf8 *>(&Whs[co]);
+      F.wl[nb] = *reinterpret_cast<const bf8 *>(&Wls[co]);
     }
   };
-  auto compute = [&](int c) {
-    static_assert(NB >= 1 && NB <= 4, "column blocks per wave");
-    if (nvalid == NB) {
-      compute_n(std::integral_constant<int, NB>{}, c);
-    } else {
-      if constexpr (NB >= 4) {
-        if (nvalid == 3) compute_n(std::integral_constant<int, 3>{}, c);
-      }
-      if constexpr (NB >= 3) {
-        if (nvalid == 2) compute_n(std::integral_constant<int, 2>{}, c);
-      }
-      if constexpr (NB >= 2) {
-        if (nvalid == 1) compute_n(std::integral_constant<int, 1>{}, c);
-      }
-    }
+  auto mfma_part = [&](auto nnb_tag, const Frag &F, int part) {
+    constexpr int NNB = decltype(nnb_tag)::value;
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NNB; ++nb)
+        acc[mb][nb] =
+            __builtin_amdgcn_mfma_f32_32x32x16_bf16(F.a[mb], part ? F.wl[nb] : F.wh[nb], acc[mb][nb], 0, 0, 0);
   };
-
-  if (NC > 0) {
+  auto main_loop = [&](auto nnb_tag) {
+    Frag F0, F1;
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) F1.a[mb] = bf8{};
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) F1.wh[nb] = F1.wl[nb] = bf8{};
     issue(0);
-    if (NC > 1) {
-      issue(1);
-      wait_vm<NL>();
-    } else {
-      wait_vm<0>();
+    issue(1);
+    for (int c = 0; c < NC; ++c) {
+      wait_vm<NL>();  // chunk c has landed (chunk c+1 may be in flight)
+      lds_barrier();
+      issue(c + 2);  // into chunk c-1's buffer
+      __builtin_amdgcn_sched_barrier(0);
+      read_step(c, 0, F0);
+      __builtin_amdgcn_sched_barrier(0);
+      mfma_part(nnb_tag, F1, 0);  // K step 1 of chunk c-1 (zero fragments before chunk 0)
+      mfma_part(nnb_tag, F1, 1);
+      __builtin_amdgcn_sched_barrier(0);
+      mfma_part(nnb_tag, F0, 0);
+      __builtin_amdgcn_sched_barrier(0);
+      read_step(c, 1, F1);
+      __builtin_amdgcn_sched_barrier(0);
+      mfma_part(nnb_tag, F0, 1);
     }
-    lds_barrier();
-  }
-  for (int c = 0; c < NC; ++c) {
-    const bool more = c + 2 < NC;
-    if (more) issue(c + 2);
-    compute(c);
-    if (more) wait_vm<NL>(); else wait_vm<0>();
-    lds_barrier();
+    mfma_part(nnb_tag, F1, 0);
+    mfma_part(nnb_tag, F1, 1);
+    wait_vm<0>();  // no LDS write may still be in flight when the workgroup ends
+  };
+  static_assert(NB >= 1 && NB <= 4, "column blocks per wave");
+  if (nvalid == NB) {
+    main_loop(std::integral_constant<int, NB>{});
+  } else if (nvalid == 0) {
+    main_loop(std::integral_constant<int, 0>{});
+  } else {
+    if constexpr (NB >= 4) {
+      if (nvalid == 3) main_loop(std::integral_constant<int, 3>{});
+    }
+    if constexpr (NB >= 3) {
+      if (nvalid == 2) main_loop(std::integral_constant<int, 2>{});
+    }
+    if constexpr (NB >= 2) {
+      if (nvalid == 1) main_loop(std::integral_constant<int, 1>{});
+    }
   }
 
   // a split with no Q in this chunk still stores its (zero) slab on the first chunk

@@ -71,7 +71,11 @@ struct CfgD {
   static_assert(XROWS % 64 == 0 && NT % 64 == 0, "tile must split into whole load instructions");
 };
 
-template <int O16, int WS, int WC>
+// PIPE: the operand fragments of chunk c+1 are read from LDS into a second register set right
+// after the barrier that publishes chunk c+1, and the MFMAs of chunk c then run on fragments that
+// are already in registers; without PIPE each chunk's fragments are read after the barrier and the
+// MFMAs wait for them (all waves at the same moment, since the barrier aligns them).
+template <int O16, int WS, int WC, bool PIPE>
 __global__ __launch_bounds__(256, 2) void k_exchange_f32_dl(const float *__restrict__ Boo,
                                                          const float *__restrict__ Bvv,
                                                          const float *__restrict__ X, int o, int v, int nq, int ns,
@@ -102,6 +106,11 @@ __global__ __launch_bounds__(256, 2) void k_exchange_f32_dl(const float *__restr
   int nvalid = 0;  // column blocks of this wave inside [0, v): WC, or fewer in the last tile
 #pragma unroll
   for (int cb = 0; cb < WC; ++cb) nvalid += (c_base + (wc * WC + cb) * 16 < v) ? 1 : 0;
+  // (nvalid is wave-uniform)
+  // the zero page's address stays in registers for the whole kernel (re-deriving it inside the
+  // loop puts a scalar memory load among the LDS reads, which forces full LDS waits)
+  const float *zp = g_zero_page;
+  asm volatile("" : "+s"(zp));
 
   // this lane's row / logical chunk inside each of its load instructions
   const int lrow = lane >> 2;  // 0..15 within a 16-row block
@@ -115,7 +124,7 @@ __global__ __launch_bounds__(256, 2) void k_exchange_f32_dl(const float *__restr
       const int r0 = (wave * NXW + k) * 16, r = r0 + lrow;
       const int a = a0 + 4 * ((lane & 3) ^ swz(r));
       const int sl = s_base + r / O16, j = r % O16;
-      const float *src = (sl < ns && j < o && a < v) ? X + ((size_t)sl * o + j) * v + a : g_zero_page;
+      const float *src = (sl < ns && j < o && a < v) ? X + ((size_t)sl * o + j) * v + a : zp;
       dma16(src, Xs + r0 * KC);
     }
     const float *Vq = Bvv + (size_t)q * v * v;
@@ -124,7 +133,7 @@ __global__ __launch_bounds__(256, 2) void k_exchange_f32_dl(const float *__restr
       const int r0 = (wave * NBW + k) * 16, r = r0 + lrow;
       const int a = a0 + 4 * ((lane & 3) ^ swz(r));
       const int cc = c_base + r;
-      const float *src = (cc < v && a < v) ? Vq + (size_t)cc * v + a : g_zero_page;  // row cc of symmetric B_vv
+      const float *src = (cc < v && a < v) ? Vq + (size_t)cc * v + a : zp;  // row cc of symmetric B_vv
       dma16(src, Bs + r0 * KC);
     }
   };
@@ -135,7 +144,7 @@ __global__ __launch_bounds__(256, 2) void k_exchange_f32_dl(const float *__restr
       const int e0 = (wave * NOW + k) * 64, e = e0 + lane;  // 16-byte chunk index in the tile
       const int i = e / (O16 / 4), p = e % (O16 / 4);
       const int jc = 4 * (p ^ swz_o<O16>(i));
-      const float *src = (e < C::OCH && i < o && jc < o) ? Oq + (size_t)i * o + jc : g_zero_page;
+      const float *src = (e < C::OCH && i < o && jc < o) ? Oq + (size_t)i * o + jc : zp;
       dma16(src, Os + e0 * 4);
     }
   };
@@ -150,6 +159,83 @@ __global__ __launch_bounds__(256, 2) void k_exchange_f32_dl(const float *__restr
         Kacc[a][b][c] = f4{0.f, 0.f, 0.f, 0.f};
         Wacc[a][b][c] = f4{0.f, 0.f, 0.f, 0.f};
       }
+
+  struct Frag {
+    f4 bf[WC];
+    f4 af[WS][JB];
+  };
+  auto read_frags = [&](int c, Frag &F) {
+    const float *Xs = Xs0 + (c % 3) * C::XS;
+    const float *Bs = Bs0 + (c % 3) * C::BS;
+#pragma unroll
+    for (int cb = 0; cb < WC; ++cb) {
+      const int r = (wc * WC + cb) * 16 + n;
+      F.bf[cb] = *reinterpret_cast<const f4 *>(&Bs[r * KC + 4 * (g ^ swz(r))]);
+    }
+#pragma unroll
+    for (int si = 0; si < WS; ++si)
+#pragma unroll
+      for (int jb = 0; jb < JB; ++jb) {
+        const int r = (ws * WS + si) * O16 + jb * 16 + n;
+        F.af[si][jb] = *reinterpret_cast<const f4 *>(&Xs[r * KC + 4 * (g ^ swz(r))]);
+      }
+  };
+  // MFMAs of chunk c on fragments in registers, then (last chunk of a Q) K += B_oo^Q W
+  auto mfma_n = [&](auto ncb_tag, int c, const Frag &F) {
+    constexpr int NCB = decltype(ncb_tag)::value;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int si = 0; si < WS; ++si)
+#pragma unroll
+        for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb)
+            Wacc[si][jb][cb] =
+                __builtin_amdgcn_mfma_f32_16x16x4f32(F.af[si][jb][t], F.bf[cb][t], Wacc[si][jb][cb], 0, 0, 0);
+    if (c % nkc == nkc - 1) {
+#pragma unroll
+      for (int jb = 0; jb < JB; ++jb) {
+        f4 ar[JB];
+#pragma unroll
+        for (int ib = 0; ib < JB; ++ib) {
+          const int i = ib * 16 + n;
+          ar[ib] = *reinterpret_cast<const f4 *>(&Os[i * O16 + 4 * ((jb * 4 + g) ^ swz_o<O16>(i))]);
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+          for (int ib = 0; ib < JB; ++ib)
+#pragma unroll
+            for (int si = 0; si < WS; ++si)
+#pragma unroll
+              for (int cb = 0; cb < NCB; ++cb)
+                Kacc[si][ib][cb] =
+                    __builtin_amdgcn_mfma_f32_16x16x4f32(ar[ib][t], Wacc[si][jb][cb][t], Kacc[si][ib][cb], 0, 0, 0);
+      }
+#pragma unroll
+      for (int a = 0; a < WS; ++a)
+#pragma unroll
+        for (int b = 0; b < JB; ++b)
+#pragma unroll
+          for (int cc = 0; cc < WC; ++cc) Wacc[a][b][cc] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+  };
+  auto mfma_chunk = [&](int c, const Frag &F) {
+    if (nvalid == WC) {
+      mfma_n(std::integral_constant<int, WC>{}, c, F);
+    } else {
+      if constexpr (WC >= 4) {
+        if (nvalid == 3) mfma_n(std::integral_constant<int, 3>{}, c, F);
+      }
+      if constexpr (WC >= 3) {
+        if (nvalid == 2) mfma_n(std::integral_constant<int, 2>{}, c, F);
+      }
+      if constexpr (WC >= 2) {
+        if (nvalid == 1) mfma_n(std::integral_constant<int, 1>{}, c, F);
+      }
+    }
+  };
 
   // NCB = number of this wave's column blocks inside [0, v) (wave-uniform; only the last column
   // tile has fewer than WC): the MFMA loops are specialised on it instead of testing each block
@@ -230,6 +316,37 @@ __global__ __launch_bounds__(256, 2) void k_exchange_f32_dl(const float *__restr
     }
   };
 
+  if constexpr (PIPE) {
+    Frag F0, F1;  // two named sets (a dynamically indexed pair would live in scratch memory)
+    if (NC > 0) {
+      issue_os(qa);
+      issue(0);
+      if (NC > 1) {
+        issue(1);
+        wait_vm<NXB>();  // B_oo^Q and chunk 0 have landed
+      } else {
+        wait_vm<0>();
+      }
+      lds_barrier();
+      read_frags(0, F0);
+    }
+    auto step = [&](int c, const Frag &cur, Frag &nxt) {
+      const bool more2 = c + 2 < NC;
+      if (more2) issue(c + 2);  // its buffer's fragments were read before the previous barrier
+      if (c + 1 < NC) {
+        if (more2) wait_vm<NXB>(); else wait_vm<0>();  // chunk c+1 (and any B_oo^Q) has landed
+        lds_barrier();  // also: every wave is past the MFMAs of chunk c-1 (and their B_oo reads)
+        if (c > 0 && c % nkc == 0) issue_os(qa + c / nkc);  // needed at chunk c + nkc - 1 >= c + 2
+        read_frags(c + 1, nxt);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      mfma_chunk(c, cur);
+    };
+    for (int c = 0; c < NC; c += 2) {
+      step(c, F0, F1);
+      if (c + 1 < NC) step(c + 1, F1, F0);
+    }
+  } else {
   if (NC > 0) {
     issue_os(qa);
     issue(0);
@@ -255,6 +372,7 @@ __global__ __launch_bounds__(256, 2) void k_exchange_f32_dl(const float *__restr
     }
     lds_barrier();
   }
+  }
 
   float *Pp = P + (size_t)sp * ns * o * v;
 #pragma unroll
@@ -275,7 +393,7 @@ __global__ __launch_bounds__(256, 2) void k_exchange_f32_dl(const float *__restr
   }
 }
 
-template <int O16, int WS, int WC>
+template <int O16, int WS, int WC, bool PIPE>
 hipError_t launch_xf32dl(hipStream_t s, const void *Boo, const void *Bvv, const void *X, const void *, int o, int v,
                          int nq, int ns, int nsplit, float scale, float *P, void *, size_t) {
   using C = CfgD<O16, WS, WC>;
@@ -283,27 +401,33 @@ hipError_t launch_xf32dl(hipStream_t s, const void *Boo, const void *Bvv, const 
   const int n_sg = (ns + C::KS - 1) / C::KS, n_ct = (v + C::NT - 1) / C::NT;
   const int total = n_sg * n_ct * nsplit;
   dim3 grid((total + 7) / 8 * 8);
-  hipLaunchKernelGGL((k_exchange_f32_dl<O16, WS, WC>), grid, dim3(256), C::LDS, s, static_cast<const float *>(Boo),
+  hipLaunchKernelGGL((k_exchange_f32_dl<O16, WS, WC, PIPE>), grid, dim3(256), C::LDS, s, static_cast<const float *>(Boo),
                      static_cast<const float *>(Bvv), static_cast<const float *>(X), o, v, nq, ns, n_sg, n_ct, nsplit,
                      scale, P);
   return hipGetLastError();
 }
 
-template <int O16, int WS, int WC>
+template <int O16, int WS, int WC, bool PIPE>
 hipError_t prepare_xf32dl() {
-  return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_exchange_f32_dl<O16, WS, WC>),
+  return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_exchange_f32_dl<O16, WS, WC, PIPE>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)CfgD<O16, WS, WC>::LDS);
 }
 
-#define XDL(O16, WS, WC)                                                                                 \
+#define XDL(O16, WS, WC, PIPE, NAME)                                                                     \
   ExchangeVariant {                                                                                      \
-    RTTDA_PREC_FP32, O16, CfgD<O16, WS, WC>::KS, CfgD<O16, WS, WC>::NT, "f32dl_o" #O16 "_ws" #WS "_wc" #WC, \
-        &launch_xf32dl<O16, WS, WC>, CfgD<O16, WS, WC>::LDS, &prepare_xf32dl<O16, WS, WC>, 3 * KC, 4, 4   \
+    RTTDA_PREC_FP32, O16, CfgD<O16, WS, WC>::KS, CfgD<O16, WS, WC>::NT, NAME,                            \
+        &launch_xf32dl<O16, WS, WC, PIPE>, CfgD<O16, WS, WC>::LDS, &prepare_xf32dl<O16, WS, WC, PIPE>,   \
+        3 * KC, 4, 4                                                                                     \
   }
+#define XDL2(O16, WS, WC)                                                                                \
+  XDL(O16, WS, WC, false, "f32dl_o" #O16 "_ws" #WS "_wc" #WC),                                           \
+      XDL(O16, WS, WC, true, "f32dlp_o" #O16 "_ws" #WS "_wc" #WC)
 
+// (the register-pipelined form of the larger tiles would spill, so those have only the plain form)
 const ExchangeVariant kF32DlVariants[] = {
-    XDL(32, 1, 2), XDL(32, 2, 2), XDL(48, 2, 2), XDL(64, 1, 2), XDL(64, 2, 2), XDL(64, 1, 4),
-    XDL(96, 1, 2),
+    XDL2(32, 1, 2), XDL2(32, 2, 2), XDL2(48, 2, 2), XDL2(64, 1, 2),
+    XDL(64, 2, 2, false, "f32dl_o64_ws2_wc2"), XDL(64, 1, 4, false, "f32dl_o64_ws1_wc4"),
+    XDL(96, 1, 2, false, "f32dl_o96_ws1_wc2"),
 };
 
 }  // namespace

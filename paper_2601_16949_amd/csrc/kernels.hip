@@ -436,6 +436,94 @@ __global__ __launch_bounds__(256) void k_scalar(int R, int nbf, int stage, int m
 }
 
 // ------------------------------------------------------------------------------------------------
+// Symplectic split-operator step (Propagation Algorithm subsection: X = q + i p, dq/dt = H p,
+// dp/dt = -H q; second order, kick-drift-kick):
+//   drift:  q <- q + dt (H p_h)                    at t_n + dt/2
+//   kick:   p <- p_h - dt/2 (H q);  p_h <- p - dt/2 (H q)   at t_n + dt   (two half kicks merged)
+// with H x = D x + (Coulomb + exchange partials of x) - E F_x on one real plane and ground element
+// (H x)_0 = -E g_x.  c holds (q, p) at whole steps; W (the stage buffer) holds the work state
+// (q, p_h).  The FP32 (+ BF16 hi/lo) copy of the next plane to multiply goes to x32 [R][o][v].
+// One thread per (r, i, a); the ground element of RHS r by the thread with ia == 0.
+// ------------------------------------------------------------------------------------------------
+template <int PREC>
+__global__ __launch_bounds__(256) void k_sso_update(int R, int o, int v, int nslab, int mode, int use_field, double dt,
+                                                    const double *__restrict__ D, const float *__restrict__ P,
+                                                    const double *__restrict__ F, const double *__restrict__ sc,
+                                                    double *__restrict__ c, double *__restrict__ c0,
+                                                    double *__restrict__ W, double *__restrict__ W0,
+                                                    float *__restrict__ x32, __hip_bfloat16 *__restrict__ xhi,
+                                                    __hip_bfloat16 *__restrict__ xlo) {
+  const size_t ov = (size_t)o * v;
+  const size_t total = (size_t)R * ov;
+  const size_t slab = total;  // one plane per RHS: floats per partial slab
+  const int pl = (mode == SSO_DRIFT) ? 1 : 0;  // plane of the multiplied vector
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const size_t r = e / ov, ia = e - r * ov;
+    const size_t iq = r * 2 * ov + ia, ip = iq + ov;
+    const double x = (mode == SSO_KICK_FIRST) ? c[iq] : W[pl ? ip : iq];
+    double psum = 0.0;
+    int sl = 0;
+    for (; sl + 8 <= nslab; sl += 8) {
+      float a[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u] = P[(sl + u) * slab + e];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) psum += (double)a[u];
+    }
+    for (; sl < nslab; ++sl) psum += (double)P[sl * slab + e];
+    const double E = sc[r * SC_STRIDE + SC_E];
+    double hx = D[ia] * x + psum;
+    if (use_field) hx -= E * F[pl ? ip : iq];
+    double nxt;
+    if (mode == SSO_DRIFT) {
+      const double qn = c[iq] + dt * hx;
+      c[iq] = qn;
+      W[iq] = qn;
+      nxt = qn;
+    } else if (mode == SSO_KICK) {
+      const double pn = W[ip] - 0.5 * dt * hx;
+      c[ip] = pn;
+      nxt = pn - 0.5 * dt * hx;
+      W[ip] = nxt;
+    } else {
+      W[iq] = x;
+      nxt = c[ip] - 0.5 * dt * hx;
+      W[ip] = nxt;
+    }
+    x32[e] = (float)nxt;
+    if (PREC == 1) split_bf16(nxt, xhi[e], xlo[e]);
+    if (ia == 0) {
+      const double h0 = use_field ? -E * sc[r * SC_STRIDE + (pl ? SC_GIM : SC_GRE)] : 0.0;
+      if (mode == SSO_DRIFT) {
+        const double q0 = c0[2 * r] + dt * h0;
+        c0[2 * r] = q0;
+        W0[2 * r] = q0;
+      } else if (mode == SSO_KICK) {
+        const double p0 = W0[2 * r + 1] - 0.5 * dt * h0;
+        c0[2 * r + 1] = p0;
+        W0[2 * r + 1] = p0 - 0.5 * dt * h0;
+      } else {
+        W0[2 * r] = c0[2 * r];
+        W0[2 * r + 1] = c0[2 * r + 1] - 0.5 * dt * h0;
+      }
+    }
+  }
+}
+
+// FP32 (+ BF16 hi/lo) copy of one plane of c into x32 [R][o][v].
+template <int PREC>
+__global__ void k_plane_copy(int R, size_t ov, int plane, const double *__restrict__ c, float *__restrict__ x32,
+                             __hip_bfloat16 *__restrict__ xhi, __hip_bfloat16 *__restrict__ xlo) {
+  const size_t total = (size_t)R * ov;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const size_t r = e / ov, ia = e - r * ov;
+    const double x = c[(r * 2 + plane) * ov + ia];
+    x32[e] = (float)x;
+    if (PREC == 1) split_bf16(x, xhi[e], xlo[e]);
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
 // RK4 epilogue (FP64): sigma = D X + sum of Coulomb/exchange partials - E F;  k = -i sigma;
 // stage accumulation into acc, next stage input (FP64 + FP32 or BF16 hi/lo copy), c at stage 4.
 // One thread per (r, i, a), both planes.
@@ -667,6 +755,32 @@ hipError_t launch_epilogue(hipStream_t s, int prec, int R, int o, int v, int nsl
   else
     hipLaunchKernelGGL((k_epilogue<0>), grid, dim3(256), 0, s, R, o, v, nslab, stage, mode, use_field, dt, D, P, F,
                        sc, Xin, c, acc, xs64, x32, xhi, xlo, s_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sso_update(hipStream_t s, int prec, int R, int o, int v, int nslab, int mode, int use_field,
+                             double dt, const double *D, const float *P, const double *F, const double *sc, double *c,
+                             double *c0, double *W, double *W0, float *x32, __hip_bfloat16 *xhi,
+                             __hip_bfloat16 *xlo) {
+  const long long n = (long long)R * o * v;
+  dim3 grid(grid_for(n, 256, 65536));
+  if (prec == RTTDA_PREC_MIXED_BF16)
+    hipLaunchKernelGGL((k_sso_update<1>), grid, dim3(256), 0, s, R, o, v, nslab, mode, use_field, dt, D, P, F, sc, c,
+                       c0, W, W0, x32, xhi, xlo);
+  else
+    hipLaunchKernelGGL((k_sso_update<0>), grid, dim3(256), 0, s, R, o, v, nslab, mode, use_field, dt, D, P, F, sc, c,
+                       c0, W, W0, x32, xhi, xlo);
+  return hipGetLastError();
+}
+
+hipError_t launch_plane_copy(hipStream_t s, int prec, int R, size_t ov, int plane, const double *c, float *x32,
+                             __hip_bfloat16 *xhi, __hip_bfloat16 *xlo) {
+  const long long n = (long long)R * (long long)ov;
+  dim3 grid(grid_for(n, 256, 65536));
+  if (prec == RTTDA_PREC_MIXED_BF16)
+    hipLaunchKernelGGL((k_plane_copy<1>), grid, dim3(256), 0, s, R, ov, plane, c, x32, xhi, xlo);
+  else
+    hipLaunchKernelGGL((k_plane_copy<0>), grid, dim3(256), 0, s, R, ov, plane, c, x32, xhi, xlo);
   return hipGetLastError();
 }
 

@@ -171,7 +171,7 @@ enum { PC_EXCHANGE = 0, PC_COULOMB = 1, PC_FIELD = 2, PC_EPILOGUE = 3 };
 struct GraphEntry {
   bool valid = false;
   // key
-  int nrhs = 0, steps = 0, mode = 0;
+  int nrhs = 0, steps = 0, mode = 0, integ = 0;
   double dt = 0;
   const void *c0 = nullptr, *c = nullptr;
   bool trace = false, norms = false;
@@ -371,10 +371,10 @@ size_t scratch_for(const rttda_ctx *ctx, int ns) {
   return qc * (size_t)ctx->v * ns * ctx->o * 4;
 }
 
-// Coulomb + exchange partials for the current stage input (x32 or xhi/xlo).
-rttda_status enqueue_two_electron(rttda_ctx *ctx, int nrhs) {
+// Coulomb + exchange partials for the current stage input (x32 or xhi/xlo), `ns` real slices
+// (2 per RHS for the complex RK4 stages, 1 per RHS for the split-operator half steps).
+rttda_status enqueue_two_electron(rttda_ctx *ctx, int ns) {
   if (ctx->nq == 0) return RTTDA_OK;
-  const int ns = 2 * nrhs;
   const int ov = (int)ctx->ov;
   hipStream_t s = ctx->stream;
   const bool pr = ctx->prof.on;
@@ -403,7 +403,7 @@ rttda_status enqueue_step(rttda_ctx *ctx, int nrhs, double dt, bool has_field, d
   for (int stage = 0; stage < 4; ++stage) {
     double *Xin = stage == 0 ? c : ctx->xs64();
     double *X0 = stage == 0 ? c0 : ctx->xs0();
-    rttda_status st = enqueue_two_electron(ctx, nrhs);
+    rttda_status st = enqueue_two_electron(ctx, 2 * nrhs);
     if (st != RTTDA_OK) return st;
     const bool need_field = stage == 0 || has_field;
     const bool pr = ctx->prof.on;
@@ -424,6 +424,52 @@ rttda_status enqueue_step(rttda_ctx *ctx, int nrhs, double dt, bool has_field, d
                             ctx->xlo(), nullptr));
     if (pr) HIP_TRY(ctx->prof.end(PC_EPILOGUE, s));
   }
+  return RTTDA_OK;
+}
+
+// One symplectic split-operator step (k_sso_update): trace sample at the step start, drift with
+// H(t_n + dt/2) p_h, kick with H(t_n + dt) q_{n+1}.  Field products only when a pulse is on.
+rttda_status enqueue_sso_step(rttda_ctx *ctx, int nrhs, double dt, bool has_field, double *c0, double *c) {
+  hipStream_t s = ctx->stream;
+  const int o = ctx->o, v = ctx->v;
+  const bool pr = ctx->prof.on;
+  double *W = ctx->xs64(), *W0 = ctx->xs0();
+  rttda_status st;
+  if (pr) HIP_TRY(ctx->prof.begin(PC_FIELD, s));
+  HIP_TRY(launch_field(s, c, c0, ctx->moo(), ctx->mov(), ctx->mvv(), o, v, nrhs, ctx->F(), ctx->part()));
+  HIP_TRY(launch_scalar(s, nrhs, ctx->L.nbf, 0, SM_TRACE, dt, ctx->pulses(), ctx->state(), ctx->part(), ctx->sc(), c0,
+                        ctx->acc0(), ctx->xs0(), nullptr, ctx->normref(), nullptr));
+  if (pr) HIP_TRY(ctx->prof.end(PC_FIELD, s));
+  for (int half = 0; half < 2; ++half) {  // 0: drift (stage node 1/2), 1: kick (node 1)
+    if ((st = enqueue_two_electron(ctx, nrhs)) != RTTDA_OK) return st;
+    if (pr) HIP_TRY(ctx->prof.begin(PC_EPILOGUE, s));
+    if (has_field)
+      HIP_TRY(launch_field(s, W, W0, ctx->moo(), ctx->mov(), ctx->mvv(), o, v, nrhs, ctx->F(), ctx->part()));
+    if (has_field || half == 1)
+      HIP_TRY(launch_scalar(s, nrhs, ctx->L.nbf, half == 0 ? 1 : 3,
+                            (has_field ? SM_EFIELD : 0) | (half == 1 ? SM_INC : 0), dt, ctx->pulses(), ctx->state(),
+                            ctx->part(), ctx->sc(), c0, ctx->acc0(), ctx->xs0(), nullptr, ctx->normref(), nullptr));
+    HIP_TRY(launch_sso_update(s, ctx->prec, nrhs, o, v, nslab(ctx), half == 0 ? SSO_DRIFT : SSO_KICK,
+                              has_field ? 1 : 0, dt, ctx->D(), ctx->P(), ctx->F(), ctx->sc(), c, c0, W, W0, ctx->x32(),
+                              ctx->xhi(), ctx->xlo()));
+    if (pr) HIP_TRY(ctx->prof.end(PC_EPILOGUE, s));
+  }
+  return RTTDA_OK;
+}
+
+// First half kick of a split-operator call: W = (q, p - dt/2 H(t_step0) q), x32 = FP32(p_h).
+rttda_status enqueue_sso_start(rttda_ctx *ctx, int nrhs, double dt, bool has_field, double *c0, double *c) {
+  hipStream_t s = ctx->stream;
+  HIP_TRY(launch_plane_copy(s, ctx->prec, nrhs, ctx->ov, 0, c, ctx->x32(), ctx->xhi(), ctx->xlo()));
+  rttda_status st = enqueue_two_electron(ctx, nrhs);
+  if (st != RTTDA_OK) return st;
+  if (has_field)
+    HIP_TRY(launch_field(s, c, c0, ctx->moo(), ctx->mov(), ctx->mvv(), ctx->o, ctx->v, nrhs, ctx->F(), ctx->part()));
+  HIP_TRY(launch_scalar(s, nrhs, ctx->L.nbf, 0, has_field ? SM_EFIELD : 0, dt, ctx->pulses(), ctx->state(),
+                        ctx->part(), ctx->sc(), c0, ctx->acc0(), ctx->xs0(), nullptr, ctx->normref(), nullptr));
+  HIP_TRY(launch_sso_update(s, ctx->prec, nrhs, ctx->o, ctx->v, nslab(ctx), SSO_KICK_FIRST, has_field ? 1 : 0, dt,
+                            ctx->D(), ctx->P(), ctx->F(), ctx->sc(), c, c0, ctx->xs64(), ctx->xs0(), ctx->x32(),
+                            ctx->xhi(), ctx->xlo()));
   return RTTDA_OK;
 }
 
@@ -630,7 +676,7 @@ rttda_status rttda_sigma(rttda_ctx *ctx, int32_t nrhs, const double *field, cons
   drop_graph(ctx);
   HIP_TRY(launch_mu_blocks(hs, ctx->d.mu, ctx->pulses(), ctx->o, ctx->v, nrhs, ctx->moo(), ctx->mov(), ctx->mvv()));
   if ((st = to_stage_copy(ctx, c, nrhs)) != RTTDA_OK) return st;
-  if ((st = enqueue_two_electron(ctx, nrhs)) != RTTDA_OK) return st;
+  if ((st = enqueue_two_electron(ctx, 2 * nrhs)) != RTTDA_OK) return st;
   HIP_TRY(launch_field(hs, c, c0, ctx->moo(), ctx->mov(), ctx->mvv(), ctx->o, ctx->v, nrhs, ctx->F(), ctx->part()));
   HIP_TRY(launch_scalar(hs, nrhs, ctx->L.nbf, 0, SM_SIGMA0 | SM_KEEP_E, 0.0, ctx->pulses(), ctx->state(),
                         ctx->part(), ctx->sc(), const_cast<double *>(c0), ctx->acc0(), ctx->xs0(), nullptr,
@@ -664,8 +710,14 @@ rttda_status rttda_dipole_trace(rttda_ctx *ctx, int32_t nrhs, const double *dir,
   return RTTDA_OK;
 }
 
-rttda_status rttda_propagate(rttda_ctx *ctx, int32_t nrhs, const rttda_pulse *pulses, double dt, int64_t step0,
-                             int64_t n_steps, double *c0, double *c, double *trace, double *norms) {
+}  // extern "C"
+
+namespace {
+
+enum : int { INTEG_RK4 = 0, INTEG_SSO = 1 };
+
+rttda_status propagate_impl(rttda_ctx *ctx, int32_t nrhs, const rttda_pulse *pulses, double dt, int64_t step0,
+                            int64_t n_steps, double *c0, double *c, double *trace, double *norms, int integ) {
   if (!ctx) return fail(RTTDA_E_INVAL, "ctx is NULL");
   rttda_status st = check_nrhs(ctx, nrhs);
   if (st != RTTDA_OK) return st;
@@ -699,7 +751,15 @@ rttda_status rttda_propagate(rttda_ctx *ctx, int32_t nrhs, const rttda_pulse *pu
                           ctx->acc0(), ctx->xs0(), nullptr, ctx->normref(), nullptr));
     HIP_TRY(launch_kick(hs, nrhs, (int)ctx->ov, ctx->pulses(), ctx->F(), ctx->sc(), c, c0));
   }
-  if ((st = to_stage_copy(ctx, c, nrhs)) != RTTDA_OK) return st;
+  if (integ == INTEG_SSO)
+    st = enqueue_sso_start(ctx, nrhs, dt, has_field, c0, c);
+  else
+    st = to_stage_copy(ctx, c, nrhs);
+  if (st != RTTDA_OK) return st;
+  auto step = [&]() {
+    return integ == INTEG_SSO ? enqueue_sso_step(ctx, nrhs, dt, has_field, c0, c)
+                              : enqueue_step(ctx, nrhs, dt, has_field, c0, c);
+  };
 
   const int spg = ctx->steps_per_graph;
   const bool graph_ok = ctx->use_graph == 1 && !ctx->prof.on && hs != nullptr && n_steps >= 2LL * spg;
@@ -707,14 +767,15 @@ rttda_status rttda_propagate(rttda_ctx *ctx, int32_t nrhs, const rttda_pulse *pu
   if (graph_ok) {
     const int mode = has_field ? 1 : 0;
     GraphEntry &G = ctx->graph;
-    const bool hit = G.valid && G.nrhs == nrhs && G.steps == spg && G.mode == mode && G.dt == dt && G.c0 == c0 &&
-                     G.c == c && G.trace == (trace != nullptr) && G.norms == (norms != nullptr);
+    const bool hit = G.valid && G.nrhs == nrhs && G.steps == spg && G.mode == mode && G.integ == integ &&
+                     G.dt == dt && G.c0 == c0 && G.c == c && G.trace == (trace != nullptr) &&
+                     G.norms == (norms != nullptr);
     if (!hit) {
       drop_graph(ctx);
       hipGraph_t graph = nullptr;
       HIP_TRY(hipStreamBeginCapture(hs, hipStreamCaptureModeThreadLocal));
       rttda_status cst = RTTDA_OK;
-      for (int k = 0; k < spg && cst == RTTDA_OK; ++k) cst = enqueue_step(ctx, nrhs, dt, has_field, c0, c);
+      for (int k = 0; k < spg && cst == RTTDA_OK; ++k) cst = step();
       hipError_t ee = hipStreamEndCapture(hs, &graph);
       if (cst != RTTDA_OK) {
         if (graph) (void)hipGraphDestroy(graph);
@@ -730,6 +791,7 @@ rttda_status rttda_propagate(rttda_ctx *ctx, int32_t nrhs, const rttda_pulse *pu
       G.nrhs = nrhs;
       G.steps = spg;
       G.mode = mode;
+      G.integ = integ;
       G.dt = dt;
       G.c0 = c0;
       G.c = c;
@@ -741,12 +803,26 @@ rttda_status rttda_propagate(rttda_ctx *ctx, int32_t nrhs, const rttda_pulse *pu
     done = reps * spg;
   }
   for (int64_t k = done; k < n_steps; ++k)
-    if ((st = enqueue_step(ctx, nrhs, dt, has_field, c0, c)) != RTTDA_OK) return st;
+    if ((st = step()) != RTTDA_OK) return st;
   // final trace sample at step0 + n_steps
   HIP_TRY(launch_field(hs, c, c0, ctx->moo(), ctx->mov(), ctx->mvv(), o, v, nrhs, ctx->F(), ctx->part()));
   HIP_TRY(launch_scalar(hs, nrhs, ctx->L.nbf, 0, SM_TRACE, dt, ctx->pulses(), ctx->state(), ctx->part(), ctx->sc(),
                         c0, ctx->acc0(), ctx->xs0(), nullptr, ctx->normref(), nullptr));
   return RTTDA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rttda_status rttda_propagate(rttda_ctx *ctx, int32_t nrhs, const rttda_pulse *pulses, double dt, int64_t step0,
+                             int64_t n_steps, double *c0, double *c, double *trace, double *norms) {
+  return propagate_impl(ctx, nrhs, pulses, dt, step0, n_steps, c0, c, trace, norms, INTEG_RK4);
+}
+
+rttda_status rttda_propagate_sso(rttda_ctx *ctx, int32_t nrhs, const rttda_pulse *pulses, double dt, int64_t step0,
+                                 int64_t n_steps, double *c0, double *c, double *trace, double *norms) {
+  return propagate_impl(ctx, nrhs, pulses, dt, step0, n_steps, c0, c, trace, norms, INTEG_SSO);
 }
 
 rttda_status rttda_guard(rttda_ctx *ctx, int64_t *first_bad_step) {

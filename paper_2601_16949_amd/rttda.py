@@ -71,6 +71,9 @@ EXPORTS = {
     "rttda_propagate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(CPulse), ctypes.c_double,
                                        ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.c_void_p]),
+    "rttda_propagate_sso": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(CPulse),
+                                           ctypes.c_double, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "rttda_dipole_trace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "rttda_guard": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
@@ -255,8 +258,14 @@ class Context:
         return s0, s
 
     def propagate(self, pulses, dt: float, n_steps: int, c0, c, step0: int = 0, trace=None, norms=None,
-                  want_trace: bool = True, want_norms: bool = False):
+                  want_trace: bool = True, want_norms: bool = False, integrator: str = "rk4"):
+        """Advance in place with RK4 (rttda_propagate) or the symplectic split operator
+        (integrator="sso", rttda_propagate_sso)."""
         import torch
+
+        if integrator not in ("rk4", "sso"):
+            raise ValueError(f"integrator must be 'rk4' or 'sso', not {integrator!r}")
+        fn = self.lib.rttda_propagate if integrator == "rk4" else self.lib.rttda_propagate_sso
 
         nrhs = c.shape[0]
         _dev_check(c0, torch.float64, (nrhs, 2), "c0")
@@ -267,9 +276,8 @@ class Context:
             norms = torch.empty((n_steps + 1, nrhs), dtype=torch.float64, device=self.device)
         cp = make_pulses(pulses)
         self._enter()
-        _check(self.lib.rttda_propagate(self.handle, nrhs, cp, float(dt), int(step0), int(n_steps), _ptr(c0),
-                                        _ptr(c), _ptr(trace) if trace is not None else None,
-                                        _ptr(norms) if norms is not None else None))
+        _check(fn(self.handle, nrhs, cp, float(dt), int(step0), int(n_steps), _ptr(c0), _ptr(c),
+                  _ptr(trace) if trace is not None else None, _ptr(norms) if norms is not None else None))
         self._leave()
         if want_norms:
             return trace, norms

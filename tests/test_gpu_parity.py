@@ -251,19 +251,19 @@ def test_mixed_trace_parity_small(gpu_lib):
 
 
 def test_mixed_trace_and_peaks_mid_shape(gpu_lib):
-    """Mixed precision at the o40 v300 N_Q1000 shape (BF16 factors, split exchange), x/y/z kicks as
-    3 RHS for 2000 steps of dt 0.05: traces within 1e-4 of the oracle (FP64 eigen route on the same
-    BF16-rounded factors) and every kick-spectrum peak within 1e-4 Ha (same post-processing)."""
+    """Mixed precision at a mid shape (o32 v160 N_Q400; BF16 factors, split exchange), x/y/z kicks
+    as 3 RHS for 2000 steps of dt 0.05: traces within 1e-4 of the oracle (FP64 eigen route on the
+    same BF16-rounded factors) and every kick-spectrum peak within 1e-4 Ha (same post-processing)."""
     from oracle import spectrum as S
 
-    o, v, nq = 40, 300, 1000
-    say("[mixed mid shape] o40 v300 N_Q1000, 2000 steps")
+    o, v, nq = 32, 160, 400
+    say("[mixed mid shape] o32 v160 N_Q400, 2000 steps")
     shape = I.Shape(o, v, nq, b_scale=0.05, storage="bf16")
     prob, op, ctx = setup(shape, I.SEED_BASE + 4, 3, "mixed")
     pulses = I.kick_pulses()
     dt, n = 0.05, 2000
     got, _, _ = run_trace(gpu_lib, ctx, pulses, dt, n, o, v)
-    say("   oracle eigh (n = 12001) ...")
+    say("   oracle eigh (n = 5121) ...")
     route = O.EigenRoute(op)
     for r in range(3):
         ref = route.propagate_field_free(pulses[r], dt, n)

@@ -491,3 +491,55 @@ def test_populations_projection_complete_and_rk4_decay():
     expect = abs(O.rk4_amplification(-1j * w[I_] * dt)) ** (2 * nsteps)
     assert abs(Pn[1 + I_] - expect) < 1e-12
     assert np.max(np.delete(Pn, 1 + I_)) < 1e-24
+
+
+# ------------------------------------------------------------------------------------------
+# Symplectic split operator (Propagation Algorithm subsection; convergence subsection)
+# ------------------------------------------------------------------------------------------
+def test_sso_eigenmode_closed_form_and_invariant():
+    """Field-free SSO from an eigenvector of A: each step is the 2x2 mode map of a = w dt (built
+    from the three half/full updates by hand), the state never leaves the mode, the mode map
+    has determinant 1, and q^2 + p^2 / (1 - a^2/4) is conserved."""
+    op = tiny_op(o=3, v=4, nq=4)
+    w, U = np.linalg.eigh(O.dense_A(op))
+    I_ = 2
+    dt, n = 0.25, 60
+    x0 = U[:, I_].reshape(3, 4).astype(np.complex128)
+    _, c0n, Cn = O.propagate_sso(op, pulse(I.PULSE_NONE), dt, n, c0=0.0 + 0j, C=x0)
+    a = w[I_] * dt
+    Mm = O.sso_mode_matrix(a)
+    assert abs(np.linalg.det(Mm) - 1.0) < 1e-14
+    qp = np.linalg.matrix_power(Mm, n) @ np.array([1.0, 0.0])
+    assert np.allclose(Cn.real.reshape(-1), qp[0] * U[:, I_], atol=1e-12, rtol=0)
+    assert np.allclose(Cn.imag.reshape(-1), qp[1] * U[:, I_], atol=1e-12, rtol=0)
+    assert abs(c0n) < 1e-15
+    inv = qp[0] ** 2 + qp[1] ** 2 / (1.0 - a * a / 4.0)
+    assert abs(inv - 1.0) < 1e-12
+    # the mode map rotates by theta with cos(theta) = 1 - a^2/2 (the modified frequency)
+    theta = math.acos(1.0 - a * a / 2.0)
+    ev = np.linalg.eigvals(Mm)
+    assert np.allclose(sorted(np.angle(ev)), [-theta, theta], atol=1e-12)
+
+
+def test_sso_second_order_and_bounded_norm():
+    """With a Gaussian pulse the SSO global error against a fine reference falls as dt^2 (slope
+    2, the paper's convergence study), and the norm error stays bounded by O(dt^2) without
+    drift over a long field-free run."""
+    op = tiny_op(o=2, v=3, nq=3)
+    p = pulse(I.PULSE_GAUSS, e0=0.05, omega=0.9, t0=6.0, fwhm=5.0, direction=(0, 0, 1))
+    T = 12.0
+    ref, _, _ = O.propagate(op, p, T / 4000, 4000)  # RK4, error ~1e-13
+    errs = []
+    dts = [0.1, 0.05, 0.025]
+    for dt in dts:
+        tr, _, _ = O.propagate_sso(op, p, dt, int(round(T / dt)))
+        errs.append(abs(tr[-1] - ref[-1]))
+    slopes = [math.log(errs[k] / errs[k + 1]) / math.log(2.0) for k in range(2)]
+    assert all(abs(s_ - 2.0) < 0.15 for s_ in slopes), slopes
+    kick = pulse(I.PULSE_DELTA, e0=0.05, direction=(1, 0, 0))
+    for dt in (0.1, 0.05):
+        _, _, _, nr = O.propagate_sso(op, kick, dt, int(400 / dt), want_norm=True)
+        dev = np.abs(nr - nr[0])
+        half = len(dev) // 2
+        assert dev.max() < 0.2 * dt * dt  # bounded at O(dt^2)
+        assert dev[half:].max() < 1.5 * dev[:half].max() + 1e-15  # no drift
