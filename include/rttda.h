@@ -169,6 +169,15 @@ rttda_status rttda_dipole_trace(rttda_ctx *ctx, int32_t nrhs, const double *dir,
  * rttda_propagate_sso alike. */
 rttda_status rttda_guard(rttda_ctx *ctx, int64_t *first_bad_step);
 
+/* Estimate the spectral radius of A (Lanczos on the sigma product with a fixed start
+ * vector, n_iter steps, 2 <= n_iter <= 500): *rho is the largest |Ritz value| and
+ * *rho_bound adds the Ritz residual of the extreme pairs, so that rho(A) <= rho_bound up
+ * to the rounding of the sigma product.  Classic RK4 is stable for rho(A) dt up to about
+ * 2.83 (the split operator for rho(A) dt < 2); callers check rho_bound * dt before a run.
+ * Synchronises the context's stream; uses the workspace's stage buffers (no effect on
+ * the state of later rttda_propagate calls). */
+rttda_status rttda_spectral_radius(rttda_ctx *ctx, int32_t n_iter, double *rho, double *rho_bound);
+
 /* Launch configuration knobs (for the autotuner).  Zero fields keep the
  * library's choice.  Returns RTTDA_E_UNSUPPORTED for a tile variant this build
  * does not have, RTTDA_E_NOMEM when the splits do not fit the workspace. */

@@ -88,6 +88,15 @@ hipError_t launch_sso_update(hipStream_t s, int prec, int R, int o, int v, int n
                              __hip_bfloat16 *xlo);
 hipError_t launch_plane_copy(hipStream_t s, int prec, int R, size_t ov, int plane, const double *c, float *x32,
                              __hip_bfloat16 *xhi, __hip_bfloat16 *xlo);
+// Lanczos guard: block partial sums (at most LZ_BLOCKS_MAX) are written to part[] and added on the host
+constexpr int LZ_BLOCKS_MAX = 1024;
+int lz_blocks(long long n);
+hipError_t launch_lz_init(hipStream_t s, long long n, double *v, double *part);
+hipError_t launch_lz_apply(hipStream_t s, long long n, int nslab, const double *D, const float *P, const double *v,
+                           const double *vprev, double beta, double *w, double *part);
+hipError_t launch_lz_orth(hipStream_t s, long long n, const double *v, double alpha, double *w, double *part);
+hipError_t launch_lz_next(hipStream_t s, int prec, long long n, double scale, const double *w, double *v,
+                          double *vprev, float *x32, __hip_bfloat16 *xhi, __hip_bfloat16 *xlo, int shift);
 hipError_t launch_kick(hipStream_t s, int R, int ov, const DevPulse *pulses, const double *F, const double *sc,
                        double *c, double *c0);
 hipError_t launch_set_state(hipStream_t s, DevState *st, long long step0, double *trace, double *norms);

@@ -31,7 +31,10 @@ __device__ __attribute__((aligned(256))) unsigned int g_zero_page_g[64];  // 256
 
 constexpr int KC = 32;  // bf16 per chunk row: 64 bytes = four 16-byte chunks
 
-__device__ __forceinline__ int swz(int r) { return (r >> 1) & 3; }
+// XOR swizzle of the four 16-byte chunks of a 64-byte row: the 16-byte reads of 8 consecutive rows
+// (one 128-byte bank sweep) and of 16 consecutive rows (one 256-byte sweep) at one logical chunk all
+// land in distinct bank groups
+__device__ __forceinline__ int swz(int r) { return ((r >> 1) & 3) ^ ((r >> 3) & 1); }
 
 __device__ __forceinline__ void dma16(const void *src, void *lds_base) {
   __builtin_amdgcn_global_load_lds(src, (lds_void *)lds_base, 16, 0, 0);

@@ -524,6 +524,86 @@ __global__ void k_plane_copy(int R, size_t ov, int plane, const double *__restri
 }
 
 // ------------------------------------------------------------------------------------------------
+// Lanczos iteration on A (stability guard: the RK4 step is stable for rho(A) dt below ~2.8).
+// Vectors of length ov in FP64; A v = D v + (Coulomb + exchange partials of v) for one real
+// slice.  Block partial sums go to part[blockIdx.x] and are added in a fixed order on the host.
+// ------------------------------------------------------------------------------------------------
+__device__ __forceinline__ double block_sum(double x, double *sh) {
+  x = wave_sum(x);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) sh[wave] = x;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w];
+  return t;
+}
+
+// start vector: a fixed pseudo-random vector (SplitMix64 of the index), part = |v|^2
+__global__ __launch_bounds__(256) void k_lz_init(long long n, double *__restrict__ v, double *__restrict__ part) {
+  __shared__ double sh[4];
+  double acc = 0.0;
+  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < n; e += (long long)gridDim.x * 256) {
+    unsigned long long z = (unsigned long long)e + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    const double x = (double)(z >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0;
+    v[e] = x;
+    acc += x * x;
+  }
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// w = A v - beta vprev, part = <w, v>
+__global__ __launch_bounds__(256) void k_lz_apply(long long n, int nslab, const double *__restrict__ D,
+                                                  const float *__restrict__ P, const double *__restrict__ v,
+                                                  const double *__restrict__ vprev, double beta,
+                                                  double *__restrict__ w, double *__restrict__ part) {
+  __shared__ double sh[4];
+  double acc = 0.0;
+  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < n; e += (long long)gridDim.x * 256) {
+    double s = D[e] * v[e];
+    for (int k = 0; k < nslab; ++k) s += (double)P[(size_t)k * n + e];
+    s -= beta * vprev[e];
+    w[e] = s;
+    acc += s * v[e];
+  }
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// w -= alpha v, part = |w|^2
+__global__ __launch_bounds__(256) void k_lz_orth(long long n, const double *__restrict__ v, double alpha,
+                                                 double *__restrict__ w, double *__restrict__ part) {
+  __shared__ double sh[4];
+  double acc = 0.0;
+  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < n; e += (long long)gridDim.x * 256) {
+    const double x = w[e] - alpha * v[e];
+    w[e] = x;
+    acc += x * x;
+  }
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// vprev = v; v = w * scale; FP32 (+ BF16 hi/lo) copy of v for the next product
+template <int PREC>
+__global__ __launch_bounds__(256) void k_lz_next(long long n, double scale, const double *__restrict__ w,
+                                                 double *__restrict__ v, double *__restrict__ vprev,
+                                                 float *__restrict__ x32, __hip_bfloat16 *__restrict__ xhi,
+                                                 __hip_bfloat16 *__restrict__ xlo, int shift) {
+  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < n; e += (long long)gridDim.x * 256) {
+    if (shift) vprev[e] = v[e];
+    const double x = w[e] * scale;
+    v[e] = x;
+    x32[e] = (float)x;
+    if (PREC == 1) split_bf16(x, xhi[e], xlo[e]);
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
 // RK4 epilogue (FP64): sigma = D X + sum of Coulomb/exchange partials - E F;  k = -i sigma;
 // stage accumulation into acc, next stage input (FP64 + FP32 or BF16 hi/lo copy), c at stage 4.
 // One thread per (r, i, a), both planes.
@@ -781,6 +861,32 @@ hipError_t launch_plane_copy(hipStream_t s, int prec, int R, size_t ov, int plan
     hipLaunchKernelGGL((k_plane_copy<1>), grid, dim3(256), 0, s, R, ov, plane, c, x32, xhi, xlo);
   else
     hipLaunchKernelGGL((k_plane_copy<0>), grid, dim3(256), 0, s, R, ov, plane, c, x32, xhi, xlo);
+  return hipGetLastError();
+}
+
+int lz_blocks(long long n) { return (int)std::min<long long>(LZ_BLOCKS_MAX, std::max<long long>(1, (n + 255) / 256)); }
+
+hipError_t launch_lz_init(hipStream_t s, long long n, double *v, double *part) {
+  hipLaunchKernelGGL(k_lz_init, dim3(lz_blocks(n)), dim3(256), 0, s, n, v, part);
+  return hipGetLastError();
+}
+hipError_t launch_lz_apply(hipStream_t s, long long n, int nslab, const double *D, const float *P, const double *v,
+                           const double *vprev, double beta, double *w, double *part) {
+  hipLaunchKernelGGL(k_lz_apply, dim3(lz_blocks(n)), dim3(256), 0, s, n, nslab, D, P, v, vprev, beta, w, part);
+  return hipGetLastError();
+}
+hipError_t launch_lz_orth(hipStream_t s, long long n, const double *v, double alpha, double *w, double *part) {
+  hipLaunchKernelGGL(k_lz_orth, dim3(lz_blocks(n)), dim3(256), 0, s, n, v, alpha, w, part);
+  return hipGetLastError();
+}
+hipError_t launch_lz_next(hipStream_t s, int prec, long long n, double scale, const double *w, double *v,
+                          double *vprev, float *x32, __hip_bfloat16 *xhi, __hip_bfloat16 *xlo, int shift) {
+  if (prec == RTTDA_PREC_MIXED_BF16)
+    hipLaunchKernelGGL((k_lz_next<1>), dim3(lz_blocks(n)), dim3(256), 0, s, n, scale, w, v, vprev, x32, xhi, xlo,
+                       shift);
+  else
+    hipLaunchKernelGGL((k_lz_next<0>), dim3(lz_blocks(n)), dim3(256), 0, s, n, scale, w, v, vprev, x32, xhi, xlo,
+                       shift);
   return hipGetLastError();
 }
 

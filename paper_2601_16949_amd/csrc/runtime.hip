@@ -59,6 +59,7 @@ inline bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 
 struct Layout {
   size_t D, moo, mov, mvv, xs64, xs0, acc, acc0, F, part, sc, x32, xhi, xlo, dvec, P, pulses, state, normref;
   size_t scratch, scratch_bytes;  // W hi/lo of the large-o exchange path (0 bytes when it does not apply)
+  size_t lz, lzp;                 // Lanczos guard: three FP64 vectors of ov, block partial sums
   size_t total;
   int nbf;
   int sk_max, sj_max;
@@ -102,6 +103,8 @@ Layout make_layout(int o, int v, int nq, int R, int prec) {
     L.scratch_bytes = std::min((size_t)nq * per_q, std::max(per_q, XGEMM_SCRATCH_MAX));
   }
   L.scratch = take(L.scratch_bytes);
+  L.lz = take(3 * ov * 8);
+  L.lzp = take((size_t)LZ_BLOCKS_MAX * 8);
   L.total = off;
   return L;
 }
@@ -246,6 +249,8 @@ struct rttda_ctx {
   float *dvec() const { return at<float>(L.dvec); }
   float *P() const { return at<float>(L.P); }
   void *scratch() const { return L.scratch_bytes ? static_cast<void *>(ws + L.scratch) : nullptr; }
+  double *lz() const { return at<double>(L.lz); }
+  double *lzp() const { return at<double>(L.lzp); }
   DevPulse *pulses() const { return at<DevPulse>(L.pulses); }
   DevState *state() const { return at<DevState>(L.state); }
   double *normref() const { return at<double>(L.normref); }
@@ -485,6 +490,65 @@ rttda_status to_stage_copy(rttda_ctx *ctx, const double *c, int nrhs) {
 void drop_graph(rttda_ctx *ctx) {
   if (ctx->graph.valid && ctx->graph.exec) (void)hipGraphExecDestroy(ctx->graph.exec);
   ctx->graph = GraphEntry{};
+}
+
+// Symmetric tridiagonal T (diagonal a[0..k-1], off-diagonal b[0..k-2]): number of eigenvalues
+// below x by the Sturm sequence of the LDL^T pivots.
+int sturm_below(const std::vector<double> &a, const std::vector<double> &b, double x) {
+  int cnt = 0;
+  double d = 1.0;
+  for (size_t i = 0; i < a.size(); ++i) {
+    const double bb = i ? b[i - 1] * b[i - 1] : 0.0;
+    d = (a[i] - x) - (i ? bb / d : 0.0);
+    if (d == 0.0) d = -1e-300;
+    if (d < 0.0) ++cnt;
+  }
+  return cnt;
+}
+
+// The m-th smallest eigenvalue of T (m = 0..k-1) by bisection inside the Gershgorin interval.
+double tridiag_eig(const std::vector<double> &a, const std::vector<double> &b, int m) {
+  double lo = 1e300, hi = -1e300;
+  for (size_t i = 0; i < a.size(); ++i) {
+    const double r = (i ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < a.size() ? std::fabs(b[i]) : 0.0);
+    lo = std::min(lo, a[i] - r);
+    hi = std::max(hi, a[i] + r);
+  }
+  for (int it = 0; it < 200 && hi - lo > 1e-15 * std::max(1.0, std::fabs(hi) + std::fabs(lo)); ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (sturm_below(a, b, mid) > m) hi = mid; else lo = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+// |last component| of the unit eigenvector of T for eigenvalue theta (inverse iteration with the
+// tridiagonal solve of (T - mu I) y = x, mu = theta slightly shifted).
+double tridiag_last_component(const std::vector<double> &a, const std::vector<double> &b, double theta) {
+  const size_t k = a.size();
+  const double mu = theta + 1e-10 * std::max(1.0, std::fabs(theta));
+  std::vector<double> x(k, 1.0), c(k), d(k);
+  for (int it = 0; it < 4; ++it) {
+    // Thomas algorithm on the shifted matrix
+    std::vector<double> y(k);
+    double den = a[0] - mu;
+    if (den == 0.0) den = 1e-300;
+    c[0] = k > 1 ? b[0] / den : 0.0;
+    d[0] = x[0] / den;
+    for (size_t i = 1; i < k; ++i) {
+      den = (a[i] - mu) - b[i - 1] * c[i - 1];
+      if (den == 0.0) den = 1e-300;
+      c[i] = i + 1 < k ? b[i] / den : 0.0;
+      d[i] = (x[i] - b[i - 1] * d[i - 1]) / den;
+    }
+    y[k - 1] = d[k - 1];
+    for (size_t i = k - 1; i-- > 0;) y[i] = d[i] - c[i] * y[i + 1];
+    double nrm = 0.0;
+    for (double t : y) nrm += t * t;
+    nrm = std::sqrt(nrm);
+    if (!(nrm > 0.0) || !std::isfinite(nrm)) break;
+    for (size_t i = 0; i < k; ++i) x[i] = y[i] / nrm;
+  }
+  return std::fabs(x[k - 1]);
 }
 
 rttda_status check_nrhs(const rttda_ctx *ctx, int nrhs) {
@@ -823,6 +887,54 @@ rttda_status rttda_propagate(rttda_ctx *ctx, int32_t nrhs, const rttda_pulse *pu
 rttda_status rttda_propagate_sso(rttda_ctx *ctx, int32_t nrhs, const rttda_pulse *pulses, double dt, int64_t step0,
                                  int64_t n_steps, double *c0, double *c, double *trace, double *norms) {
   return propagate_impl(ctx, nrhs, pulses, dt, step0, n_steps, c0, c, trace, norms, INTEG_SSO);
+}
+
+rttda_status rttda_spectral_radius(rttda_ctx *ctx, int32_t n_iter, double *rho, double *rho_bound) {
+  if (!ctx || !rho || !rho_bound) return fail(RTTDA_E_INVAL, "NULL argument");
+  if (n_iter < 2 || n_iter > 500) return fail(RTTDA_E_INVAL, "n_iter %d outside 2..500", n_iter);
+  hipStream_t hs = ctx->stream;
+  const long long n = (long long)ctx->ov;
+  double *v = ctx->lz(), *vprev = v + n, *w = v + 2 * n, *part = ctx->lzp();
+  const int nb = lz_blocks(n);
+  std::vector<double> hp(nb);
+  auto host_sum = [&](double &out) -> rttda_status {
+    HIP_TRY(hipMemcpyAsync(hp.data(), part, nb * sizeof(double), hipMemcpyDeviceToHost, hs));
+    HIP_TRY(hipStreamSynchronize(hs));
+    out = 0.0;
+    for (double t : hp) out += t;
+    return RTTDA_OK;
+  };
+  rttda_status st;
+  double n0 = 0.0;
+  HIP_TRY(launch_lz_init(hs, n, w, part));
+  if ((st = host_sum(n0)) != RTTDA_OK) return st;
+  HIP_TRY(hipMemsetAsync(vprev, 0, n * sizeof(double), hs));
+  HIP_TRY(launch_lz_next(hs, ctx->prec, n, 1.0 / std::sqrt(n0), w, v, vprev, ctx->x32(), ctx->xhi(), ctx->xlo(), 0));
+  std::vector<double> alpha, beta;
+  double bj = 0.0, blast = 0.0;
+  const int kmax = (int)std::min<long long>(n_iter, n);
+  for (int j = 0; j < kmax; ++j) {
+    if (ctx->nq > 0 && (st = enqueue_two_electron(ctx, 1)) != RTTDA_OK) return st;
+    double aj = 0.0, b2 = 0.0;
+    HIP_TRY(launch_lz_apply(hs, n, nslab(ctx), ctx->D(), ctx->P(), v, vprev, bj, w, part));
+    if ((st = host_sum(aj)) != RTTDA_OK) return st;
+    HIP_TRY(launch_lz_orth(hs, n, v, aj, w, part));
+    if ((st = host_sum(b2)) != RTTDA_OK) return st;
+    alpha.push_back(aj);
+    const double b = std::sqrt(std::max(b2, 0.0));
+    blast = b;
+    if (j + 1 == kmax || !(b > 1e-13 * std::max(1.0, std::fabs(aj)))) break;  // done, or invariant subspace
+    beta.push_back(b);
+    HIP_TRY(launch_lz_next(hs, ctx->prec, n, 1.0 / b, w, v, vprev, ctx->x32(), ctx->xhi(), ctx->xlo(), 1));
+    bj = b;
+  }
+  const int k = (int)alpha.size();
+  const double tmin = tridiag_eig(alpha, beta, 0), tmax = tridiag_eig(alpha, beta, k - 1);
+  const double emin = blast * tridiag_last_component(alpha, beta, tmin);
+  const double emax = blast * tridiag_last_component(alpha, beta, tmax);
+  *rho = std::max(std::fabs(tmin), std::fabs(tmax));
+  *rho_bound = std::max(std::fabs(tmin) + emin, std::fabs(tmax) + emax);
+  return RTTDA_OK;
 }
 
 rttda_status rttda_guard(rttda_ctx *ctx, int64_t *first_bad_step) {

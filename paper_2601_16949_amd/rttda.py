@@ -77,6 +77,8 @@ EXPORTS = {
     "rttda_dipole_trace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "rttda_guard": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
+    "rttda_spectral_radius": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                             ctypes.POINTER(ctypes.c_double)]),
     "rttda_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(CTuning)]),
     "rttda_get_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(CTuning)]),
     "rttda_exchange_variants": (ctypes.c_int32, [ctypes.c_int32]),
@@ -282,6 +284,14 @@ class Context:
         if want_norms:
             return trace, norms
         return trace
+
+    def spectral_radius(self, n_iter: int = 30):
+        """(rho, rho_bound) of A from n_iter Lanczos steps on the device (rttda_spectral_radius)."""
+        rho, bound = ctypes.c_double(), ctypes.c_double()
+        self._enter()
+        _check(self.lib.rttda_spectral_radius(self.handle, int(n_iter), ctypes.byref(rho), ctypes.byref(bound)))
+        self._leave()
+        return rho.value, bound.value
 
     def dipole_trace(self, dirs, c0, c, out=None):
         import torch

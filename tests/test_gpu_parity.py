@@ -560,3 +560,21 @@ def test_gemm_exchange_chunks_match_oracle(gpu_lib, o, v, nq, nrhs):
                 _, s1 = ctx.sigma(field[-1:], dirs[-1:], c0d[-1:].contiguous(), cd[-1:].contiguous())
                 torch.cuda.synchronize()
                 assert torch.equal(s1[0], sd[-1]), (chunk, splits)
+
+
+@pytest.mark.parametrize("o,v,nq,prec", [(10, 40, 120, "fp32"), (2, 3, 2, "fp32"), (24, 96, 64, "mixed"),
+                                         (40, 120, 80, "fp32")])
+def test_spectral_radius_brackets_rho(gpu_lib, o, v, nq, prec):
+    """Lanczos estimate of rho(A) on the device (the stability guard): the estimate does not
+    exceed the oracle's largest |eigenvalue| (beyond the sigma's rounding) and the bound does
+    not fall below it; 60 steps get within 2 % of it."""
+    shape = I.Shape(o, v, nq, b_scale=0.05, storage="f32" if prec == "fp32" else "bf16")
+    prob, op, ctx = setup(shape, 321 + o, 1, prec)
+    rho, bound = ctx.spectral_radius(60)
+    A = O.dense_A_blas(op) if o * v > 600 else O.dense_A(op)
+    true = float(np.max(np.abs(np.linalg.eigvalsh(A))))
+    tol = 1e-5 if prec == "fp32" else 1e-4
+    say(f"[spectral radius] o={o} v={v} nq={nq} {prec}: rho {rho:.8f} bound {bound:.8f} oracle {true:.8f}")
+    assert rho <= true * (1 + tol)
+    assert bound >= true * (1 - tol)
+    assert rho >= 0.98 * true
