@@ -169,6 +169,40 @@ rttda_status rttda_dipole_trace(rttda_ctx *ctx, int32_t nrhs, const double *dir,
  * rttda_propagate_sso alike. */
 rttda_status rttda_guard(rttda_ctx *ctx, int64_t *first_bad_step);
 
+/* ---------------------------------------------------------------------------------------
+ * Serving pool: continuous batching of propagation requests on one GPU.
+ *
+ * A request is a context (its operator, workspace and stream) plus states, pulses, dt and
+ * a step count.  The pool admits a request when its declared HBM footprint fits the
+ * budget, advances every admitted request in chunks of steps (each on its own context's
+ * stream, so the work of different requests overlaps on the device; at most one chunk per
+ * request is in flight), and frees the budget when the request is released.  A request's
+ * result is the same as that of one rttda_propagate(_sso) call over all its steps: the
+ * chunks resume at the request's own step counter.  The pool owns no device memory and
+ * is not thread-safe; contexts admitted to a pool must not be used elsewhere until released.
+ * --------------------------------------------------------------------------------------- */
+typedef struct rttda_pool rttda_pool;
+typedef enum { RTTDA_INTEG_RK4 = 0, RTTDA_INTEG_SSO = 1 } rttda_integrator;
+rttda_status rttda_pool_create(size_t budget_bytes, rttda_pool **out);
+rttda_status rttda_pool_destroy(rttda_pool *pool); /* waits for in-flight chunks */
+/* Admit a request; *slot receives its id.  pulses (host, [nrhs]) are copied; c0, c
+ * (device, updated in place) and trace (device [n_steps+1][nrhs] or NULL) must outlive the
+ * slot.  RTTDA_E_NOMEM when footprint_bytes does not fit the remaining budget. */
+rttda_status rttda_pool_admit(rttda_pool *pool, rttda_ctx *ctx, int32_t nrhs, const rttda_pulse *pulses,
+                              double dt, int64_t n_steps, int32_t integrator, double *c0, double *c,
+                              double *trace, size_t footprint_bytes, int32_t *slot);
+/* For every admitted request whose previous chunk has finished and that has steps left,
+ * enqueue its next chunk of up to chunk_steps steps.  Does not block; *issued receives
+ * the number of chunks enqueued (may be NULL). */
+rttda_status rttda_pool_step(rttda_pool *pool, int64_t chunk_steps, int32_t *issued);
+/* Non-blocking progress of a slot: steps enqueued so far and whether all its steps have
+ * finished on the device. */
+rttda_status rttda_pool_poll(rttda_pool *pool, int32_t slot, int64_t *steps_enqueued, int32_t *finished);
+/* Wait for a slot's work, return its footprint to the budget and retire the slot. */
+rttda_status rttda_pool_release(rttda_pool *pool, int32_t slot);
+/* Budget in use and number of admitted (unreleased) requests. */
+rttda_status rttda_pool_usage(const rttda_pool *pool, size_t *used_bytes, int32_t *active);
+
 /* Estimate the spectral radius of A (Lanczos on the sigma product with a fixed start
  * vector, n_iter steps, 2 <= n_iter <= 500): *rho is the largest |Ritz value| and
  * *rho_bound adds the Ritz residual of the extreme pairs, so that rho(A) <= rho_bound up

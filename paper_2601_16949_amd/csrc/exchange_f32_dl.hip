@@ -79,8 +79,9 @@ struct CfgD {
 // after the barrier that publishes chunk c+1, and the MFMAs of chunk c then run on fragments that
 // are already in registers; without PIPE each chunk's fragments are read after the barrier and the
 // MFMAs wait for them (all waves at the same moment, since the barrier aligns them).
-template <int O16, int WS, int WC, bool PIPE>
-__global__ __launch_bounds__(256, 2) void k_exchange_f32_dl(const float *__restrict__ Boo,
+// OCC: workgroups per CU the register budget is sized for (2, or 3 where three fit the LDS).
+template <int O16, int WS, int WC, bool PIPE, int OCC>
+__global__ __launch_bounds__(256, OCC) void k_exchange_f32_dl(const float *__restrict__ Boo,
                                                          const float *__restrict__ Bvv,
                                                          const float *__restrict__ X, int o, int v, int nq, int ns,
                                                          int n_sg, int n_ct, int nsplit, float scale,
@@ -397,7 +398,7 @@ __global__ __launch_bounds__(256, 2) void k_exchange_f32_dl(const float *__restr
   }
 }
 
-template <int O16, int WS, int WC, bool PIPE>
+template <int O16, int WS, int WC, bool PIPE, int OCC>
 hipError_t launch_xf32dl(hipStream_t s, const void *Boo, const void *Bvv, const void *X, const void *, int o, int v,
                          int nq, int ns, int nsplit, float scale, float *P, void *, size_t) {
   using C = CfgD<O16, WS, WC>;
@@ -405,33 +406,34 @@ hipError_t launch_xf32dl(hipStream_t s, const void *Boo, const void *Bvv, const 
   const int n_sg = (ns + C::KS - 1) / C::KS, n_ct = (v + C::NT - 1) / C::NT;
   const int total = n_sg * n_ct * nsplit;
   dim3 grid((total + 7) / 8 * 8);
-  hipLaunchKernelGGL((k_exchange_f32_dl<O16, WS, WC, PIPE>), grid, dim3(256), C::LDS, s, static_cast<const float *>(Boo),
+  hipLaunchKernelGGL((k_exchange_f32_dl<O16, WS, WC, PIPE, OCC>), grid, dim3(256), C::LDS, s, static_cast<const float *>(Boo),
                      static_cast<const float *>(Bvv), static_cast<const float *>(X), o, v, nq, ns, n_sg, n_ct, nsplit,
                      scale, P);
   return hipGetLastError();
 }
 
-template <int O16, int WS, int WC, bool PIPE>
+template <int O16, int WS, int WC, bool PIPE, int OCC>
 hipError_t prepare_xf32dl() {
-  return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_exchange_f32_dl<O16, WS, WC, PIPE>),
+  return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_exchange_f32_dl<O16, WS, WC, PIPE, OCC>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)CfgD<O16, WS, WC>::LDS);
 }
 
-#define XDL(O16, WS, WC, PIPE, NAME)                                                                     \
+#define XDL(O16, WS, WC, PIPE, OCC, NAME)                                                                \
   ExchangeVariant {                                                                                      \
     RTTDA_PREC_FP32, O16, CfgD<O16, WS, WC>::KS, CfgD<O16, WS, WC>::NT, NAME,                            \
-        &launch_xf32dl<O16, WS, WC, PIPE>, CfgD<O16, WS, WC>::LDS, &prepare_xf32dl<O16, WS, WC, PIPE>,   \
-        3 * KC, 4, 4                                                                                     \
+        &launch_xf32dl<O16, WS, WC, PIPE, OCC>, CfgD<O16, WS, WC>::LDS,                                  \
+        &prepare_xf32dl<O16, WS, WC, PIPE, OCC>, 3 * KC, 4, 4                                            \
   }
 #define XDL2(O16, WS, WC)                                                                                \
-  XDL(O16, WS, WC, false, "f32dl_o" #O16 "_ws" #WS "_wc" #WC),                                           \
-      XDL(O16, WS, WC, true, "f32dlp_o" #O16 "_ws" #WS "_wc" #WC)
+  XDL(O16, WS, WC, false, 2, "f32dl_o" #O16 "_ws" #WS "_wc" #WC),                                        \
+      XDL(O16, WS, WC, true, 2, "f32dlp_o" #O16 "_ws" #WS "_wc" #WC)
 
-// (the register-pipelined form of the larger tiles would spill, so those have only the plain form)
+// (the register-pipelined form of the larger tiles would spill, so those have only the plain form;
+// o64 ws1 wc2 already fits three workgroups per CU: 134 registers, 52 KiB of LDS)
 const ExchangeVariant kF32DlVariants[] = {
     XDL2(32, 1, 2), XDL2(32, 2, 2), XDL2(48, 2, 2), XDL2(64, 1, 2),
-    XDL(64, 2, 2, false, "f32dl_o64_ws2_wc2"), XDL(64, 1, 4, false, "f32dl_o64_ws1_wc4"),
-    XDL(96, 1, 2, false, "f32dl_o96_ws1_wc2"),
+    XDL(64, 2, 2, false, 2, "f32dl_o64_ws2_wc2"), XDL(64, 1, 4, false, 2, "f32dl_o64_ws1_wc4"),
+    XDL(96, 1, 2, false, 2, "f32dl_o96_ws1_wc2"),
 };
 
 }  // namespace

@@ -1,5 +1,6 @@
 // Host runtime of the RT-TDA library: argument validation, workspace layout, the RK4 step
 // sequence (direct launches or replay of a captured HIP graph) and the C ABI.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -934,6 +935,145 @@ rttda_status rttda_spectral_radius(rttda_ctx *ctx, int32_t n_iter, double *rho, 
   const double emax = blast * tridiag_last_component(alpha, beta, tmax);
   *rho = std::max(std::fabs(tmin), std::fabs(tmax));
   *rho_bound = std::max(std::fabs(tmin) + emin, std::fabs(tmax) + emax);
+  return RTTDA_OK;
+}
+
+}  // extern "C"
+
+struct rttda_pool {
+  struct Slot {
+    rttda_ctx *ctx = nullptr;
+    int nrhs = 0, integ = 0;
+    std::vector<rttda_pulse> pulses;
+    double dt = 0.0;
+    int64_t n_steps = 0, done = 0;
+    double *c0 = nullptr, *c = nullptr, *trace = nullptr;
+    size_t bytes = 0;
+    hipEvent_t ev = nullptr;
+    bool live = false, pending = false;
+  };
+  size_t budget = 0, used = 0;
+  std::vector<Slot> slots;
+};
+
+extern "C" {
+
+rttda_status rttda_pool_create(size_t budget_bytes, rttda_pool **out) {
+  if (!out) return fail(RTTDA_E_INVAL, "out is NULL");
+  *out = new rttda_pool();
+  (*out)->budget = budget_bytes;
+  return RTTDA_OK;
+}
+
+rttda_status rttda_pool_destroy(rttda_pool *pool) {
+  if (!pool) return fail(RTTDA_E_INVAL, "pool is NULL");
+  for (auto &sl : pool->slots)
+    if (sl.ev) {
+      (void)hipEventSynchronize(sl.ev);
+      (void)hipEventDestroy(sl.ev);
+    }
+  delete pool;
+  return RTTDA_OK;
+}
+
+rttda_status rttda_pool_admit(rttda_pool *pool, rttda_ctx *ctx, int32_t nrhs, const rttda_pulse *pulses,
+                              double dt, int64_t n_steps, int32_t integrator, double *c0, double *c,
+                              double *trace, size_t footprint_bytes, int32_t *slot) {
+  if (!pool || !ctx || !pulses || !c0 || !c || !slot) return fail(RTTDA_E_INVAL, "NULL argument");
+  rttda_status st = check_nrhs(ctx, nrhs);
+  if (st != RTTDA_OK) return st;
+  if (integrator != RTTDA_INTEG_RK4 && integrator != RTTDA_INTEG_SSO)
+    return fail(RTTDA_E_INVAL, "integrator must be RTTDA_INTEG_RK4 or RTTDA_INTEG_SSO");
+  if (!(dt > 0.0) || !std::isfinite(dt) || n_steps < 0) return fail(RTTDA_E_INVAL, "bad dt or n_steps");
+  for (const auto &sl : pool->slots)
+    if (sl.live && sl.ctx == ctx) return fail(RTTDA_E_STATE, "context already admitted");
+  if (footprint_bytes > pool->budget - std::min(pool->used, pool->budget))
+    return fail(RTTDA_E_NOMEM, "footprint %zu bytes exceeds the %zu bytes left of the budget", footprint_bytes,
+                pool->budget - std::min(pool->used, pool->budget));
+  size_t k = 0;
+  while (k < pool->slots.size() && pool->slots[k].live) ++k;
+  if (k == pool->slots.size()) pool->slots.emplace_back();
+  rttda_pool::Slot &sl = pool->slots[k];
+  if (!sl.ev) HIP_TRY(hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming));
+  sl.ctx = ctx;
+  sl.nrhs = nrhs;
+  sl.integ = integrator;
+  sl.pulses.assign(pulses, pulses + nrhs);
+  sl.dt = dt;
+  sl.n_steps = n_steps;
+  sl.done = 0;
+  sl.c0 = c0;
+  sl.c = c;
+  sl.trace = trace;
+  sl.bytes = footprint_bytes;
+  sl.live = true;
+  sl.pending = false;
+  pool->used += footprint_bytes;
+  *slot = (int32_t)k;
+  return RTTDA_OK;
+}
+
+rttda_status rttda_pool_step(rttda_pool *pool, int64_t chunk_steps, int32_t *issued) {
+  if (!pool || chunk_steps < 1) return fail(RTTDA_E_INVAL, "pool is NULL or chunk_steps < 1");
+  int32_t n = 0;
+  for (auto &sl : pool->slots) {
+    if (!sl.live || sl.done >= sl.n_steps) continue;
+    if (sl.pending) {
+      const hipError_t q = hipEventQuery(sl.ev);
+      if (q == hipErrorNotReady) continue;  // previous chunk still running
+      if (q != hipSuccess) return fail(RTTDA_E_DEVICE, "pool: %s", hipGetErrorString(q));
+    }
+    const int64_t k = std::min(chunk_steps, sl.n_steps - sl.done);
+    double *tr = sl.trace ? sl.trace + (size_t)sl.done * sl.nrhs : nullptr;
+    rttda_status st = propagate_impl(sl.ctx, sl.nrhs, sl.pulses.data(), sl.dt, sl.done, k, sl.c0, sl.c, tr,
+                                     nullptr, sl.integ == RTTDA_INTEG_SSO ? INTEG_SSO : INTEG_RK4);
+    if (st != RTTDA_OK) return st;
+    HIP_TRY(hipEventRecord(sl.ev, sl.ctx->stream));
+    sl.pending = true;
+    sl.done += k;
+    ++n;
+  }
+  if (issued) *issued = n;
+  return RTTDA_OK;
+}
+
+rttda_status rttda_pool_poll(rttda_pool *pool, int32_t slot, int64_t *steps_enqueued, int32_t *finished) {
+  if (!pool || slot < 0 || slot >= (int32_t)pool->slots.size() || !pool->slots[slot].live)
+    return fail(RTTDA_E_INVAL, "no such slot");
+  rttda_pool::Slot &sl = pool->slots[slot];
+  int32_t fin = 0;
+  if (sl.done >= sl.n_steps) {
+    if (!sl.pending) {
+      fin = 1;
+    } else {
+      const hipError_t q = hipEventQuery(sl.ev);
+      if (q == hipSuccess) fin = 1;
+      else if (q != hipErrorNotReady) return fail(RTTDA_E_DEVICE, "pool: %s", hipGetErrorString(q));
+    }
+  }
+  if (steps_enqueued) *steps_enqueued = sl.done;
+  if (finished) *finished = fin;
+  return RTTDA_OK;
+}
+
+rttda_status rttda_pool_release(rttda_pool *pool, int32_t slot) {
+  if (!pool || slot < 0 || slot >= (int32_t)pool->slots.size() || !pool->slots[slot].live)
+    return fail(RTTDA_E_INVAL, "no such slot");
+  rttda_pool::Slot &sl = pool->slots[slot];
+  if (sl.pending) HIP_TRY(hipEventSynchronize(sl.ev));
+  sl.pending = false;
+  sl.live = false;
+  sl.ctx = nullptr;
+  pool->used -= std::min(pool->used, sl.bytes);
+  return RTTDA_OK;
+}
+
+rttda_status rttda_pool_usage(const rttda_pool *pool, size_t *used_bytes, int32_t *active) {
+  if (!pool) return fail(RTTDA_E_INVAL, "pool is NULL");
+  int32_t a = 0;
+  for (const auto &sl : pool->slots) a += sl.live ? 1 : 0;
+  if (used_bytes) *used_bytes = pool->used;
+  if (active) *active = a;
   return RTTDA_OK;
 }
 

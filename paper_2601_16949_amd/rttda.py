@@ -58,7 +58,18 @@ class CProfile(ctypes.Structure):
 
 PROFILE_CLASSES = ("exchange", "coulomb", "field", "epilogue")
 
+_VP, _I32, _I64, _SZ, _D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_double
+INTEG_RK4, INTEG_SSO = 0, 1
+
 EXPORTS = {
+    "rttda_pool_create": (ctypes.c_int, [_SZ, ctypes.POINTER(_VP)]),
+    "rttda_pool_destroy": (ctypes.c_int, [_VP]),
+    "rttda_pool_admit": (ctypes.c_int, [_VP, _VP, _I32, ctypes.POINTER(CPulse), _D, _I64, _I32, _VP, _VP, _VP, _SZ,
+                                        ctypes.POINTER(_I32)]),
+    "rttda_pool_step": (ctypes.c_int, [_VP, _I64, ctypes.POINTER(_I32)]),
+    "rttda_pool_poll": (ctypes.c_int, [_VP, _I32, ctypes.POINTER(_I64), ctypes.POINTER(_I32)]),
+    "rttda_pool_release": (ctypes.c_int, [_VP, _I32]),
+    "rttda_pool_usage": (ctypes.c_int, [_VP, ctypes.POINTER(_SZ), ctypes.POINTER(_I32)]),
     "rttda_set_profiling": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "rttda_get_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(CProfile)]),
     "rttda_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(CDesc), ctypes.POINTER(ctypes.c_size_t)]),
@@ -384,3 +395,68 @@ def from_planes(c0p, cp):
     a = c0p.detach().cpu().numpy()
     b = cp.detach().cpu().numpy()
     return a[:, 0] + 1j * a[:, 1], b[:, 0] + 1j * b[:, 1]
+
+
+class Pool:
+    """The library's serving pool (rttda_pool_*): admission by HBM footprint against a budget,
+    chunked stepping of every admitted request on its own context's stream, polling, release."""
+
+    def __init__(self, budget_bytes: int):
+        self.lib = load()
+        h = ctypes.c_void_p()
+        _check(self.lib.rttda_pool_create(int(budget_bytes), ctypes.byref(h)))
+        self.handle = h
+        self._keep = {}  # slot -> objects that must outlive it (pulse array, tensors)
+
+    def admit(self, ctx: "Context", pulses, dt: float, n_steps: int, c0, c, trace=None, footprint: int = 0,
+              integrator: str = "rk4") -> int:
+        """Slot id; raises RttdaError(E_NOMEM) when the footprint does not fit."""
+        import torch
+
+        nrhs = c.shape[0]
+        _dev_check(c0, torch.float64, (nrhs, 2), "c0")
+        _dev_check(c, torch.float64, (nrhs, 2, ctx.o, ctx.v), "c")
+        if trace is not None:
+            _dev_check(trace, torch.float64, (n_steps + 1, nrhs), "trace")
+        cp = make_pulses(pulses)
+        slot = ctypes.c_int32()
+        ctx._enter()  # the request's chunks run on the context's stream, after work queued so far
+        _check(self.lib.rttda_pool_admit(self.handle, ctx.handle, nrhs, cp, float(dt), int(n_steps),
+                                         INTEG_RK4 if integrator == "rk4" else INTEG_SSO, _ptr(c0), _ptr(c),
+                                         _ptr(trace) if trace is not None else None, int(footprint),
+                                         ctypes.byref(slot)))
+        self._keep[slot.value] = (cp, ctx, c0, c, trace)
+        return slot.value
+
+    def step(self, chunk_steps: int) -> int:
+        """Enqueue the next chunk of every request whose previous chunk finished; returns the count."""
+        n = ctypes.c_int32()
+        _check(self.lib.rttda_pool_step(self.handle, int(chunk_steps), ctypes.byref(n)))
+        return n.value
+
+    def poll(self, slot: int):
+        """(steps enqueued, finished) of a slot, without blocking."""
+        done, fin = ctypes.c_int64(), ctypes.c_int32()
+        _check(self.lib.rttda_pool_poll(self.handle, int(slot), ctypes.byref(done), ctypes.byref(fin)))
+        return done.value, bool(fin.value)
+
+    def release(self, slot: int):
+        _check(self.lib.rttda_pool_release(self.handle, int(slot)))
+        self._keep.pop(slot, None)
+
+    def usage(self):
+        used, active = ctypes.c_size_t(), ctypes.c_int32()
+        _check(self.lib.rttda_pool_usage(self.handle, ctypes.byref(used), ctypes.byref(active)))
+        return used.value, active.value
+
+    def close(self):
+        if self.handle:
+            self.lib.rttda_pool_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

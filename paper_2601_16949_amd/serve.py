@@ -1,12 +1,12 @@
 """Continuous-batching serving loop for RT-TDA propagation requests on one GPU.
 
-Requests (o, v, N_Q, pulse, steps) arrive over time.  The server admits a request as soon as
-its HBM footprint (factor tensors + library workspace + state + trace) fits the remaining
-budget, keeps its factors and amplitudes resident, and advances every admitted request in
-chunks of RK4 steps, each request on its own HIP stream so that the work of different
-requests overlaps on the device.  A request is retired (memory released, latency recorded)
-when its last chunk has finished.  All device work goes through the C ABI (one context per
-request); this module only schedules.
+Requests (o, v, N_Q, pulse, steps) arrive over time.  The library's serving pool (rttda_pool_*)
+does the batching: it admits a request when its HBM footprint (factor tensors + library
+workspace + state + trace) fits the remaining budget, advances every admitted request in chunks
+of RK4 steps, each on its own HIP stream so that the work of different requests overlaps on the
+device, and returns a request's budget when it is released.  This module keeps the arrival
+queue (first come, first served, with later requests filling memory that earlier ones do not
+fit), creates each request's context and device tensors, and records latencies.
 
 Each request's result does not depend on what else is resident: the kernels use no atomics
 and no cross-request state, so a request's trace in a mix is bitwise the trace it gets alone.
@@ -55,9 +55,7 @@ class Slot:
     stream: object
     bytes: int
     t_admit: float
-    done: int = 0
-    event: object = None
-    t_first_chunk: float = 0.0
+    pool_slot: int = -1
 
 
 @dataclass
@@ -88,11 +86,15 @@ class Server:
         self.device = device
         self.keep_traces = keep_traces
         self.max_active = max_active
-        self.used = 0
+        self.pool = rttda.Pool(self.budget)
         self.peak_used = 0
         self.active: List[Slot] = []
         self.queue: deque = deque()
         self.results: Dict[int, Result] = {}
+
+    @property
+    def used(self) -> int:
+        return self.pool.usage()[0]
 
     # ------------------------------------------------------------------------------------
     def _admit(self, req: I.Request, now: float) -> Slot:
@@ -106,28 +108,18 @@ class Server:
             ctx = rttda.Context(dev, max_rhs=1, stream=stream, sync_streams=False)
             c0, c = rttda.ground_state(1, req.shape.o, req.shape.v, device=self.device)
             trace = torch.empty((req.n_steps + 1, 1), dtype=torch.float64, device=self.device)
-        self.used += nb
+        slot = Slot(req, ctx, dev, c0, c, trace, stream, nb, now)
+        slot.pool_slot = self.pool.admit(ctx, [req.pulse], req.dt, req.n_steps, c0, c, trace, footprint=nb)
         self.peak_used = max(self.peak_used, self.used)
-        return Slot(req, ctx, dev, c0, c, trace, stream, nb, now)
-
-    def _issue(self, s: Slot):
-        import torch
-
-        n = min(self.chunk, s.req.n_steps - s.done)
-        with torch.cuda.stream(s.stream):
-            s.ctx.propagate([s.req.pulse], s.req.dt, n, s.c0, s.c, step0=s.done,
-                            trace=s.trace[s.done:s.done + n + 1])
-            s.event = torch.cuda.Event()
-            s.event.record(s.stream)
-        s.done += n
+        return slot
 
     def _retire(self, s: Slot, now: float):
+        self.pool.release(s.pool_slot)
         tr = s.trace.cpu().numpy()[:, 0] if self.keep_traces else None
         bad = s.ctx.guard()
         if bad != -1:
             raise rttda.RttdaError(rttda.E_UNSTABLE, f"request {s.req.rid}: norm guard at step {bad}")
         s.ctx.close()
-        self.used -= s.bytes
         self.results[s.req.rid] = Result(s.req.rid, s.req.shape.o, s.req.n_steps, s.req.arrival, s.t_admit, now, tr)
 
     # ------------------------------------------------------------------------------------
@@ -145,28 +137,22 @@ class Server:
         while pending or self.queue or self.active:
             now = clock()
             while pending and (not realtime or pending[0].arrival * time_scale <= now):
-                r = pending.popleft()
-                self.queue.append(r)
+                self.queue.append(pending.popleft())
             # retire finished requests
             for s in list(self.active):
-                if s.done >= s.req.n_steps and s.event.query():
+                if self.pool.poll(s.pool_slot)[1]:
                     self.active.remove(s)
                     self._retire(s, clock())
             # admit in arrival order while memory and slots allow (later requests may backfill)
             for r in list(self.queue):
                 if len(self.active) >= self.max_active:
                     break
-                nb = footprint(r.shape, r.n_steps, self.precision)
-                if self.used + nb <= self.budget:
+                if self.used + footprint(r.shape, r.n_steps, self.precision) <= self.budget:
                     self.queue.remove(r)
                     self.active.append(self._admit(r, clock()))
             max_concurrent = max(max_concurrent, len(self.active))
-            # keep every resident request's stream busy
-            issued = False
-            for s in self.active:
-                if s.done < s.req.n_steps and (s.event is None or s.event.query()):
-                    self._issue(s)
-                    issued = True
+            # next chunk of every resident request whose previous chunk has finished
+            issued = self.pool.step(self.chunk) if self.active else 0
             if not issued:
                 if self.active:
                     time.sleep(2e-4)

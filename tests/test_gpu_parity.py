@@ -16,8 +16,9 @@ pytestmark = pytest.mark.gpu
 
 
 def say(msg):
-    print(msg, flush=True)
-    sys.stdout.flush()
+    """Progress line straight to the terminal (also under pytest's output capture), so that a
+    long GPU case shows that it is alive."""
+    print(msg, file=sys.__stdout__, flush=True)
 
 
 def setup(shape, seed, max_rhs, precision="fp32"):

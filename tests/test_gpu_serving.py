@@ -13,7 +13,9 @@ pytestmark = pytest.mark.gpu
 
 
 def say(msg):
-    print(msg, flush=True)
+    """Progress line straight to the terminal (also under pytest's output capture), so that a
+    long GPU case shows that it is alive."""
+    print(msg, file=sys.__stdout__, flush=True)
 
 
 def small_requests(n, seed=11, o_max=24):
@@ -66,3 +68,40 @@ def test_probe_request_matches_oracle(gpu_lib):
     err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
     say(f"   trace rel err {err:.2e}")
     assert err < 1e-4
+
+
+@pytest.mark.parametrize("integrator", ["rk4", "sso"])
+def test_pool_api_budget_chunks_and_release(gpu_lib, integrator):
+    """The library pool: admission beyond the budget is refused (E_NOMEM); a request stepped in
+    chunks through the pool gives bitwise the trace and state of one direct propagate call; the
+    budget returns on release."""
+    import torch
+    from paper_2601_16949_amd import rttda
+
+    o, v = 12, 30
+    prob = I.make_problem(I.Shape(o, v, 24), 3)
+    dev = rttda.DeviceProblem(prob, "fp32")
+    pulses = [I.Pulse(kind=I.PULSE_GAUSS, e0=0.03, omega=0.5, t0=2.0, fwhm=2.0, direction=(0, 0, 1)),
+              I.Pulse(kind=I.PULSE_DELTA, e0=1e-3, direction=(1, 0, 0))]
+    n = 137
+    say(f"[pool] {integrator}")
+    ctx_a, ctx_b = rttda.Context(dev, 2), rttda.Context(dev, 2)
+    c0a, ca = gpu_lib.ground_state(2, o, v)
+    c0b, cb = gpu_lib.ground_state(2, o, v)
+    direct = ctx_a.propagate(pulses, 0.05, n, c0a, ca, integrator=integrator)
+    pool = rttda.Pool(1000)
+    trace = torch.empty((n + 1, 2), dtype=torch.float64, device="cuda")
+    with pytest.raises(rttda.RttdaError):
+        pool.admit(ctx_b, pulses, 0.05, n, c0b, cb, trace, footprint=2000, integrator=integrator)
+    slot = pool.admit(ctx_b, pulses, 0.05, n, c0b, cb, trace, footprint=600, integrator=integrator)
+    assert pool.usage() == (600, 1)
+    chunks = 0
+    while not pool.poll(slot)[1]:
+        chunks += pool.step(40)
+    assert chunks == 4 and pool.poll(slot)[0] == n
+    pool.release(slot)
+    assert pool.usage() == (0, 0)
+    torch.cuda.synchronize()
+    assert torch.equal(trace, direct)
+    assert torch.equal(cb, ca) and torch.equal(c0b, c0a)
+    pool.close()
