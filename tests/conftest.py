@@ -8,9 +8,24 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 
+_CAPTURE = None
+
+
 def pytest_configure(config):
+    global _CAPTURE
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: long-running CPU oracle case")
+    _CAPTURE = config.pluginmanager.getplugin("capturemanager")
+
+
+def say(msg):
+    """A progress line that reaches the terminal even under pytest's output capture, so that a
+    long GPU case shows that it is alive."""
+    if _CAPTURE is not None:
+        with _CAPTURE.global_and_fixture_disabled():
+            print(msg, flush=True)
+    else:
+        print(msg, flush=True)
 
 
 @pytest.fixture(scope="session")

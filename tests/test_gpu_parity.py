@@ -8,6 +8,7 @@ import sys
 
 import numpy as np
 import pytest
+from conftest import say
 
 from oracle import rttda64 as O
 from paper_2601_16949_amd import inputs as I
@@ -15,10 +16,6 @@ from paper_2601_16949_amd import inputs as I
 pytestmark = pytest.mark.gpu
 
 
-def say(msg):
-    """Progress line straight to the terminal (also under pytest's output capture), so that a
-    long GPU case shows that it is alive."""
-    print(msg, file=sys.__stdout__, flush=True)
 
 
 def setup(shape, seed, max_rhs, precision="fp32"):
