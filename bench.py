@@ -34,15 +34,20 @@ AU_FS = 0.02418884326585747
 # scaled by the counters' readings for a plain 1 GiB copy: factors 2.0 and 1.0), keyed by
 # (variant, workload, splits); valid only while the kernel's source file hashes to `src`.
 TRAFFIC = {
-    ("f32_o64_ws1_wc2_kc16", "o60_v400_nq1500_kick_xyz", 119):
-        {"file": "exchange_f32.hip", "src": "13c2ccdc9a206c1c",
-         "fetch_bytes": 516335.5 * 1024 * 2.0, "write_bytes": 69345.8 * 1024 * 1.0},
-    ("f32dl_o64_ws1_wc2", "o60_v400_nq1500_kick_xyz", 119):
-        {"file": "exchange_f32_dl.hip", "src": "cbe66e8930b46a99",
-         "fetch_bytes": 770082.34375 * 1024 * 2.0, "write_bytes": 68752.4609375 * 1024 * 1.0},
+    # HBM bytes per exchange launch from rocprofv3 FETCH_SIZE / WRITE_SIZE (KiB per dispatch),
+    # scaled by what the same counters read for a plain device copy (2.0 and 1.0), keyed by
+    # (variant, workload, Q splits) and tied to the kernel source they were taken on
+    ("f32dl_o64_ws1_wc2", "o60_v400_nq1500_kick_xyz", 192):
+        {"file": "exchange_f32_dl.hip", "src": "02131cff42304d22",
+         "fetch_bytes": 628507.9765625 * 1024 * 2.0, "write_bytes": 112572.58203125 * 1024 * 1.0},
     ("bf16x2dl_o64_ws1_wc2", "o60_v400_nq1500_kick_xyz", 192):
-        {"file": "exchange_bf16_dl.hip", "src": "f255ad1eb16b4f05",
-         "fetch_bytes": 263676.1 * 1024 * 2.0, "write_bytes": 111747.0 * 1024 * 1.0},
+        {"file": "exchange_bf16_dl.hip", "src": "4d5f4be9ea744bf9",
+         "fetch_bytes": 257631.98046875 * 1024 * 2.0, "write_bytes": 112104.60546875 * 1024 * 1.0},
+    # the GEMM path: one exchange stage is 200 chunks of 25 Q, each a k_xgemm_w + k_boo_w pair
+    ("bf16x2gemm_a256x256w8_b256x128w8", "o240_v1800_nq5000_kick_xyz_mixed", 2):
+        {"file": "exchange_bf16_gemm.hip", "src": "7dc7d8bb3f4ee411",
+         "fetch_bytes": 200 * (631754.39 + 163649.59) * 1024 * 2.0,
+         "write_bytes": 200 * (271632.23 + 20838.12) * 1024 * 1.0},
 }
 PEAK = {"fp32": 157.3, "mixed": 2516.6}  # dense MFMA TFLOP/s: FP32, BF16
 HBM_PEAK_GBS = 8000.0
