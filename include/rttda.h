@@ -227,6 +227,9 @@ typedef struct rttda_tuning {
 } rttda_tuning;
 rttda_status rttda_set_tuning(rttda_ctx *ctx, const rttda_tuning *t);
 rttda_status rttda_get_tuning(const rttda_ctx *ctx, rttda_tuning *t);
+/* Largest exchange_splits the context's workspace holds: min(768, N_Q, the number of
+ * partial K slabs of 2*max_rhs*o*v floats that fit 256 MiB, but at least 32). */
+rttda_status rttda_exchange_splits_max(const rttda_ctx *ctx, int32_t *out);
 
 /* Per-kernel-class timing with HIP events on the context's stream.  While profiling is
  * on, rttda_propagate launches kernels directly (no graph replay) and brackets each

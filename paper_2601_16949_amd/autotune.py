@@ -63,9 +63,10 @@ def lookup(ctx, nrhs: int, cache_path: str = DEFAULT_CACHE) -> Optional[dict]:
 GEMM_CHUNKS = (0, 6, 12)  # Q per chunk tried for the large-o GEMM path (0 = as many as fit)
 
 
-def candidates(ctx, max_per_variant: int = 4) -> List[tuple]:
-    """(variant, splits, Q chunk) triples: every variant holding o, with splits around the
-    library's default; the GEMM path also over a few chunk lengths (0 elsewhere)."""
+def candidates(ctx, max_per_variant: int = 5) -> List[tuple]:
+    """(variant, splits, Q chunk) triples: every variant holding o, with splits from half to four
+    times the library's default (at most what the workspace holds); the GEMM path also over a
+    few chunk lengths (0 elsewhere)."""
     lib = ctx.lib
     prec = ctx.desc.precision
     n = lib.rttda_exchange_variants(prec)
@@ -78,7 +79,8 @@ def candidates(ctx, max_per_variant: int = 4) -> List[tuple]:
             continue  # variant does not hold o
         s0 = ctx.get_tuning()["exchange_splits"]
         chunks = GEMM_CHUNKS if ctx.variant_name(k).startswith("bf16x2gemm") else (0,)
-        for s in sorted({max(1, s0 // 2), s0, s0 * 2, s0 * 3})[:max_per_variant]:
+        smax = ctx.max_splits()
+        for s in sorted({min(smax, max(1, s0 * m // 2)) for m in (1, 2, 4, 6, 8)})[:max_per_variant]:
             for ch in chunks:
                 out.append((k, s, ch))
     ctx.set_tuning(exchange_variant=base["exchange_variant"], exchange_splits=base["exchange_splits"])
@@ -86,7 +88,8 @@ def candidates(ctx, max_per_variant: int = 4) -> List[tuple]:
 
 
 def measure(ctx, pulses, dt: float, c0, c, steps: int = 3) -> float:
-    """Average exchange launch time (ms) over `steps` RK4 steps."""
+    """Average time (ms) per RK4 stage of the exchange launch plus the stage epilogue (which
+    reads one partial slab per Q split, so more splits cost there) over `steps` RK4 steps."""
     import torch
 
     ctx.set_profiling(True)
@@ -94,8 +97,8 @@ def measure(ctx, pulses, dt: float, c0, c, steps: int = 3) -> float:
     torch.cuda.synchronize()
     prof = ctx.get_profile()
     ctx.set_profiling(False)
-    ex = prof["exchange"]
-    return ex["ms"] / max(ex["launches"], 1)
+    ex, ep = prof["exchange"], prof["epilogue"]
+    return (ex["ms"] + ep["ms"]) / max(ex["launches"], 1)
 
 
 def tune(ctx, pulses, dt: float, nrhs: Optional[int] = None, steps: int = 3, cache_path: str = DEFAULT_CACHE,

@@ -124,6 +124,7 @@ struct ExchangeVariant {
   int o_mod = 1;
   int o_min = 1;
   bool scratch = false;  // needs the W scratch region of the workspace
+  int rank = 0;          // preference among variants of equal tile waste (higher first)
   bool applies(int o, int v) const {
     return o <= o16 && o >= o_min && v >= v_min && v % v_mod == 0 && o % o_mod == 0;
   }

@@ -71,7 +71,11 @@ struct CfgBD {
   static_assert(XROWS % 64 == 0 && NT % 64 == 0, "tile must split into whole load instructions");
 };
 
-template <int O32, int WS, int WC>
+// PIPE: half-chunk software pipeline.  The fragments of one 16-wide K step are read from LDS
+// while the matrix cores work on the other step, and the barrier that publishes chunk c+1 sits
+// between the two steps of chunk c, so every LDS read has a batch of MFMAs to hide behind; the
+// loop is specialised once on the number of valid column blocks (no branches on it inside).
+template <int O32, int WS, int WC, bool PIPE>
 __global__ __launch_bounds__(256, 2) void k_exchange_bf16_dl(const __bf16 *__restrict__ Boo,
                                                              const __bf16 *__restrict__ Bvv,
                                                              const __bf16 *__restrict__ Xh,
@@ -96,7 +100,9 @@ __global__ __launch_bounds__(256, 2) void k_exchange_bf16_dl(const __bf16 *__res
   const int qa = (int)((long long)sp * nq / nsplit), qb = (int)((long long)(sp + 1) * nq / nsplit);
   const int s_base = sg * C::KS, c_base = ct * C::NT;
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // (the pipelined loop holds the wave index in a scalar register, and with it the LDS destinations
+  // of the loads; in the plain loop that moves more values into vector registers than fit)
+  const int tid = threadIdx.x, lane = tid & 63, wave = PIPE ? __builtin_amdgcn_readfirstlane(tid >> 6) : tid >> 6;
   const int h = lane >> 5, m = lane & 31;
   const int ws = wave >> 1, wc = wave & 1;
   const int nkc = (v + KC - 1) / KC;
@@ -111,9 +117,10 @@ __global__ __launch_bounds__(256, 2) void k_exchange_bf16_dl(const __bf16 *__res
   asm volatile("" : "+s"(zp));
   const int lrow = lane >> 2;
 
-  auto issue = [&](int c) {
-    const int q = qa + c / nkc, kc = c % nkc, a0 = kc * KC;
-    const int buf = c % 3;
+  // loads of the chunk (Q index q, K chunk kc) into LDS buffer buf; with live false (chunks past
+  // the end, pipelined loop) the B_vv lanes read the zero page
+  auto issue_at = [&](int q, int kc, int buf, bool live) {
+    const int a0 = kc * KC;
 #pragma unroll
     for (int k = 0; k < NXW; ++k) {
       const int r0 = (wave * NXW + k) * 16, r = r0 + lrow;
@@ -124,22 +131,27 @@ __global__ __launch_bounds__(256, 2) void k_exchange_bf16_dl(const __bf16 *__res
       dma16(ok ? (const void *)(Xh + off) : zp, Xh0 + buf * C::XS + r0 * KC);
       dma16(ok ? (const void *)(Xl + off) : zp, Xl0 + buf * C::XS + r0 * KC);
     }
-    const __bf16 *Vq = Bvv + (size_t)q * v * v;
+    const __bf16 *Vq = Bvv + (size_t)(live ? q : 0) * v * v;
 #pragma unroll
     for (int k = 0; k < NBW; ++k) {
       const int r0 = (wave * NBW + k) * 16, r = r0 + lrow;
       const int a = a0 + 8 * ((lane & 3) ^ swz(r));
       const int cc = c_base + r;
-      const bool ok = cc < v && a < v;
+      const bool ok = live && cc < v && a < v;
       dma16(ok ? (const void *)(Vq + (size_t)cc * v + a) : zp,
               Bs0 + buf * C::BS + r0 * KC);
     }
   };
+  auto issue = [&](int c) { issue_at(qa + c / nkc, c % nkc, c % 3, true); };
   auto issue_os = [&](int q) {
     const __bf16 *Oq = Boo + (size_t)q * o * o;
+    // (once per Q: the per-lane addresses are recomputed here rather than held in registers
+    // through the loop, which the pipelined form has none to spare for)
+    int ln = lane;
+    if constexpr (PIPE) asm volatile("" : "+v"(ln));
 #pragma unroll
     for (int k = 0; k < NOW; ++k) {
-      const int d0 = (wave * NOW + k) * 64, d = d0 + lane;  // dword index in the tile
+      const int d0 = (wave * NOW + k) * 64, d = d0 + ln;  // dword index in the tile
       const int i = d / (O32 / 2), w = d % (O32 / 2);
       const int jl = 2 * (4 * ((w >> 2) ^ swz_o(i)) + (w & 3));  // logical column (bf16)
       const bool ok = d < C::ODW && i < o && jl < o;
@@ -164,6 +176,55 @@ __global__ __launch_bounds__(256, 2) void k_exchange_bf16_dl(const __bf16 *__res
     return *reinterpret_cast<const bf4 *>(&Os[i * O32 + 8 * ch + (j & 7)]);
   };
 
+  // K += B_oo^Q W for the Q whose last chunk was just multiplied (W split into hi + lo), then W = 0
+  auto compute_k = [&](auto ncb_tag) {
+    constexpr int NCB = decltype(ncb_tag)::value;
+#pragma unroll
+    for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        bf8 wh[WS][WC], wl[WS][WC];
+#pragma unroll
+        for (int si = 0; si < WS; ++si)
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+              const float w = Wacc[si][jb][cb][8 * u + e];
+              const __bf16 hi = (__bf16)w;
+              wh[si][cb][e] = hi;
+              wl[si][cb][e] = (__bf16)(w - (float)hi);
+            }
+        const int j0 = jb * 32 + 16 * u + 4 * h;
+        bf8 ar[JB];
+#pragma unroll
+        for (int ib = 0; ib < JB; ++ib) {
+          const int i = ib * 32 + m;
+          const bf4 lo4 = os4(i, j0), hi4 = os4(i, j0 + 8);
+          ar[ib] = bf8{lo4[0], lo4[1], lo4[2], lo4[3], hi4[0], hi4[1], hi4[2], hi4[3]};
+        }
+#pragma unroll
+        for (int ib = 0; ib < JB; ++ib)
+#pragma unroll
+          for (int si = 0; si < WS; ++si)
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb)
+              Kacc[si][ib][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar[ib], wh[si][cb], Kacc[si][ib][cb], 0, 0, 0);
+#pragma unroll
+        for (int ib = 0; ib < JB; ++ib)
+#pragma unroll
+          for (int si = 0; si < WS; ++si)
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb)
+              Kacc[si][ib][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar[ib], wl[si][cb], Kacc[si][ib][cb], 0, 0, 0);
+      }
+#pragma unroll
+    for (int a = 0; a < WS; ++a)
+#pragma unroll
+      for (int b = 0; b < JB; ++b)
+#pragma unroll
+        for (int cc = 0; cc < WC; ++cc) Wacc[a][b][cc] = zero16();
+  };
   auto compute_n = [&](auto ncb_tag, int c) {
     constexpr int NCB = decltype(ncb_tag)::value;
     const int kc = c % nkc, buf = c % 3;
@@ -208,53 +269,7 @@ __global__ __launch_bounds__(256, 2) void k_exchange_bf16_dl(const __bf16 *__res
               Wacc[si][jb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[si][jb], bf[cb], Wacc[si][jb][cb], 0, 0, 0);
       }
     }
-    if (kc == nkc - 1) {
-#pragma unroll
-      for (int jb = 0; jb < JB; ++jb)
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          bf8 wh[WS][WC], wl[WS][WC];
-#pragma unroll
-          for (int si = 0; si < WS; ++si)
-#pragma unroll
-            for (int cb = 0; cb < NCB; ++cb)
-#pragma unroll
-              for (int e = 0; e < 8; ++e) {
-                const float w = Wacc[si][jb][cb][8 * u + e];
-                const __bf16 hi = (__bf16)w;
-                wh[si][cb][e] = hi;
-                wl[si][cb][e] = (__bf16)(w - (float)hi);
-              }
-          const int j0 = jb * 32 + 16 * u + 4 * h;
-          bf8 ar[JB];
-#pragma unroll
-          for (int ib = 0; ib < JB; ++ib) {
-            const int i = ib * 32 + m;
-            const bf4 lo4 = os4(i, j0), hi4 = os4(i, j0 + 8);
-            ar[ib] = bf8{lo4[0], lo4[1], lo4[2], lo4[3], hi4[0], hi4[1], hi4[2], hi4[3]};
-          }
-#pragma unroll
-          for (int ib = 0; ib < JB; ++ib)
-#pragma unroll
-            for (int si = 0; si < WS; ++si)
-#pragma unroll
-              for (int cb = 0; cb < NCB; ++cb)
-                Kacc[si][ib][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar[ib], wh[si][cb], Kacc[si][ib][cb], 0, 0, 0);
-#pragma unroll
-          for (int ib = 0; ib < JB; ++ib)
-#pragma unroll
-            for (int si = 0; si < WS; ++si)
-#pragma unroll
-              for (int cb = 0; cb < NCB; ++cb)
-                Kacc[si][ib][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar[ib], wl[si][cb], Kacc[si][ib][cb], 0, 0, 0);
-        }
-#pragma unroll
-      for (int a = 0; a < WS; ++a)
-#pragma unroll
-        for (int b = 0; b < JB; ++b)
-#pragma unroll
-          for (int cc = 0; cc < WC; ++cc) Wacc[a][b][cc] = zero16();
-    }
+    if (kc == nkc - 1) compute_k(ncb_tag);
   };
   // nvalid == 0: this wave's columns lie beyond v; it only takes part in loads and barriers
   auto compute = [&](int c) {
@@ -274,6 +289,117 @@ __global__ __launch_bounds__(256, 2) void k_exchange_bf16_dl(const __bf16 *__res
     }
   };
 
+  if constexpr (PIPE) {
+    struct Frag {
+      bf8 b[WC], h[WS][JB], l[WS][JB];
+    };
+    // operand fragments of K step u (0 or 1) of chunk c
+    auto read_frag = [&](auto ncb_tag, int buf, int u, Frag &F) {
+      constexpr int NCB = decltype(ncb_tag)::value;
+      const __bf16 *Xhs = Xh0 + buf * C::XS;
+      const __bf16 *Xls = Xl0 + buf * C::XS;
+      const __bf16 *Bs = Bs0 + buf * C::BS;
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        const int r = (wc * WC + cb) * 32 + m;
+        F.b[cb] = *reinterpret_cast<const bf8 *>(&Bs[r * KC + 8 * ((2 * u + h) ^ swz(r))]);
+      }
+      if constexpr (NCB > 0) {
+#pragma unroll
+        for (int si = 0; si < WS; ++si)
+#pragma unroll
+          for (int jb = 0; jb < JB; ++jb) {
+            const int r = (ws * WS + si) * O32 + jb * 32 + m;
+            const int co = r * KC + 8 * ((2 * u + h) ^ swz(r));
+            F.h[si][jb] = *reinterpret_cast<const bf8 *>(&Xhs[co]);
+            F.l[si][jb] = *reinterpret_cast<const bf8 *>(&Xls[co]);
+          }
+      }
+    };
+    // half of K step F: the X_hi products (part 0) or the X_lo products (part 1)
+    auto mfma_w = [&](auto ncb_tag, const Frag &F, int part) {
+      constexpr int NCB = decltype(ncb_tag)::value;
+#pragma unroll
+      for (int si = 0; si < WS; ++si)
+#pragma unroll
+        for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb)
+            Wacc[si][jb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(part ? F.l[si][jb] : F.h[si][jb], F.b[cb],
+                                                                       Wacc[si][jb][cb], 0, 0, 0);
+    };
+    // Per chunk c, after the barrier that publishes it: issue the loads of chunk c+2 (into chunk
+    // c-1's buffer), read K step 0's fragments (F0), run K step 1 of chunk c-1 (F1, read before the
+    // barrier) and, at the end of a Q, its K product while they arrive, then the X_hi half of K
+    // step 0, then read K step 1's fragments into F1 while the X_lo half runs.  Every LDS wait is
+    // then a wait for all outstanding reads.  Chunks past the end are issued too (zero page), so
+    // the loads need no branch; the B_oo^Q tile of the Q that starts at chunk s is loaded at chunk
+    // s+1, after the barrier behind which every wave finished the previous Q's K product, ahead of
+    // that chunk's own loads so that the per-chunk wait count stays the same.
+    auto main_loop = [&](auto ncb_tag) {
+      constexpr int NCB = decltype(ncb_tag)::value;
+      Frag F0, F1;
+#pragma unroll
+      for (int cb = 0; cb < WC; ++cb) F1.b[cb] = bf8{};  // "K step 1 of chunk -1": adds zero
+#pragma unroll
+      for (int si = 0; si < WS; ++si)
+#pragma unroll
+        for (int jb = 0; jb < JB; ++jb) F1.h[si][jb] = F1.l[si][jb] = bf8{};
+      if (NC == 0) return;
+      issue_os(qa);
+      issue_at(qa, 0, 0, true);
+      issue_at(qa, 1, 1, true);  // NC >= nkc >= 3
+      const bool tail1 = 16 < v - (nkc - 1) * KC;  // K step 1 of a Q's last chunk lies inside [0, v)
+      int kcc = 0, qc = qa, buf = 0;               // chunk c's K chunk, Q index and LDS buffer
+      for (int c = 0; c < NC; ++c) {
+        wait_vm<NXB>();  // chunk c (and a B_oo^Q tile issued before it) has landed
+        lds_barrier();   // publishes chunk c; every wave has read chunk c-1 and run the last K product
+        if (kcc == 1 && c > 1) issue_os(qc);  // chunk c-1 opened Q qc; the K product before it is done
+        {
+          const bool wrap = kcc + 2 >= nkc;  // chunk c+2 (nkc >= 3: at most one Q ahead)
+          issue_at(wrap ? qc + 1 : qc, wrap ? kcc + 2 - nkc : kcc + 2, buf == 0 ? 2 : buf - 1, c + 2 < NC);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        read_frag(ncb_tag, buf, 0, F0);
+        __builtin_amdgcn_sched_barrier(0);
+        if (c > 0 && (kcc != 0 || tail1)) {  // K step 1 of chunk c-1
+          mfma_w(ncb_tag, F1, 0);
+          mfma_w(ncb_tag, F1, 1);
+        }
+        if constexpr (NCB > 0) {
+          if (c > 0 && kcc == 0) compute_k(ncb_tag);  // chunk c-1 closed its Q
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        mfma_w(ncb_tag, F0, 0);
+        __builtin_amdgcn_sched_barrier(0);
+        read_frag(ncb_tag, buf, 1, F1);
+        __builtin_amdgcn_sched_barrier(0);
+        mfma_w(ncb_tag, F0, 1);
+        if (++kcc == nkc) { kcc = 0; ++qc; }
+        buf = buf == 2 ? 0 : buf + 1;
+      }
+      if (tail1) {
+        mfma_w(ncb_tag, F1, 0);
+        mfma_w(ncb_tag, F1, 1);
+      }
+      if constexpr (NCB > 0) compute_k(ncb_tag);
+      wait_vm<0>();  // no LDS write may still be in flight when the workgroup ends
+    };
+    if (nvalid == WC) {
+      main_loop(std::integral_constant<int, WC>{});
+    } else {
+      if constexpr (WC >= 4) {
+        if (nvalid == 3) main_loop(std::integral_constant<int, 3>{});
+      }
+      if constexpr (WC >= 3) {
+        if (nvalid == 2) main_loop(std::integral_constant<int, 2>{});
+      }
+      if constexpr (WC >= 2) {
+        if (nvalid == 1) main_loop(std::integral_constant<int, 1>{});
+      }
+      if (nvalid == 0) main_loop(std::integral_constant<int, 0>{});
+    }
+  } else {
   if (NC > 0) {
     issue_os(qa);
     issue(0);
@@ -298,6 +424,7 @@ __global__ __launch_bounds__(256, 2) void k_exchange_bf16_dl(const __bf16 *__res
     }
     lds_barrier();
   }
+  }
 
   float *Pp = P + (size_t)sp * ns * o * v;
 #pragma unroll
@@ -318,7 +445,7 @@ __global__ __launch_bounds__(256, 2) void k_exchange_bf16_dl(const __bf16 *__res
   }
 }
 
-template <int O32, int WS, int WC>
+template <int O32, int WS, int WC, bool PIPE>
 hipError_t launch_xbf16dl(hipStream_t s, const void *Boo, const void *Bvv, const void *X, const void *Xlo, int o,
                           int v, int nq, int ns, int nsplit, float scale, float *P, void *, size_t) {
   using C = CfgBD<O32, WS, WC>;
@@ -326,27 +453,30 @@ hipError_t launch_xbf16dl(hipStream_t s, const void *Boo, const void *Bvv, const
   const int n_sg = (ns + C::KS - 1) / C::KS, n_ct = (v + C::NT - 1) / C::NT;
   const int total = n_sg * n_ct * nsplit;
   dim3 grid((total + 7) / 8 * 8);
-  hipLaunchKernelGGL((k_exchange_bf16_dl<O32, WS, WC>), grid, dim3(256), C::LDS, s, static_cast<const __bf16 *>(Boo),
+  hipLaunchKernelGGL((k_exchange_bf16_dl<O32, WS, WC, PIPE>), grid, dim3(256), C::LDS, s, static_cast<const __bf16 *>(Boo),
                      static_cast<const __bf16 *>(Bvv), static_cast<const __bf16 *>(X),
                      static_cast<const __bf16 *>(Xlo), o, v, nq, ns, n_sg, n_ct, nsplit, scale, P);
   return hipGetLastError();
 }
 
-template <int O32, int WS, int WC>
+template <int O32, int WS, int WC, bool PIPE>
 hipError_t prepare_xbf16dl() {
-  return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_exchange_bf16_dl<O32, WS, WC>),
+  return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_exchange_bf16_dl<O32, WS, WC, PIPE>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)CfgBD<O32, WS, WC>::LDS);
 }
 
-#define XBD(O32, WS, WC)                                                                                    \
+#define XBD(O32, WS, WC, PIPE, NAME)                                                                        \
   ExchangeVariant {                                                                                         \
-    RTTDA_PREC_MIXED_BF16, O32, CfgBD<O32, WS, WC>::KS, CfgBD<O32, WS, WC>::NT,                             \
-        "bf16x2dl_o" #O32 "_ws" #WS "_wc" #WC, &launch_xbf16dl<O32, WS, WC>, CfgBD<O32, WS, WC>::LDS,      \
-        &prepare_xbf16dl<O32, WS, WC>, 3 * KC, 8, 2                                                         \
+    RTTDA_PREC_MIXED_BF16, O32, CfgBD<O32, WS, WC>::KS, CfgBD<O32, WS, WC>::NT, NAME,                       \
+        &launch_xbf16dl<O32, WS, WC, PIPE>, CfgBD<O32, WS, WC>::LDS, &prepare_xbf16dl<O32, WS, WC, PIPE>,    \
+        3 * KC, 8, 2, 1, false, PIPE ? 2 : 1                                                                \
   }
+#define XBD2(O32, WS, WC)                                                                                   \
+  XBD(O32, WS, WC, false, "bf16x2dl_o" #O32 "_ws" #WS "_wc" #WC),                                           \
+      XBD(O32, WS, WC, true, "bf16x2dlp_o" #O32 "_ws" #WS "_wc" #WC)
 
 const ExchangeVariant kBf16DlVariants[] = {
-    XBD(32, 1, 1), XBD(32, 2, 1), XBD(64, 1, 1), XBD(64, 1, 2), XBD(64, 2, 1),
+    XBD2(32, 1, 1), XBD2(32, 2, 1), XBD2(64, 1, 1), XBD2(64, 1, 2), XBD2(64, 2, 1),
 };
 
 }  // namespace

@@ -75,10 +75,8 @@ struct CfgD {
   static_assert(XROWS % 64 == 0 && NT % 64 == 0, "tile must split into whole load instructions");
 };
 
-// PIPE: the operand fragments of chunk c+1 are read from LDS into a second register set right
-// after the barrier that publishes chunk c+1, and the MFMAs of chunk c then run on fragments that
-// are already in registers; without PIPE each chunk's fragments are read after the barrier and the
-// MFMAs wait for them (all waves at the same moment, since the barrier aligns them).
+// PIPE: half-chunk software pipeline (described at the loop) instead of reading each chunk's
+// fragments after its barrier and waiting for them before its MFMAs.
 // OCC: workgroups per CU the register budget is sized for (2, or 3 where three fit the LDS).
 template <int O16, int WS, int WC, bool PIPE, int OCC>
 __global__ __launch_bounds__(256, OCC) void k_exchange_f32_dl(const float *__restrict__ Boo,
@@ -120,10 +118,12 @@ __global__ __launch_bounds__(256, OCC) void k_exchange_f32_dl(const float *__res
   // this lane's row / logical chunk inside each of its load instructions
   const int lrow = lane >> 2;  // 0..15 within a 16-row block
 
-  auto issue = [&](int c) {
-    const int q = qa + c / nkc, kc = c % nkc, a0 = kc * KC;
-    float *Xs = Xs0 + (c % 3) * C::XS;
-    float *Bs = Bs0 + (c % 3) * C::BS;
+  // loads of the chunk (Q index q, K chunk kc) into LDS buffer buf; with live false (chunks past
+  // the end, pipelined loop) the B_vv lanes read the zero page
+  auto issue_at = [&](int q, int kc, int buf, bool live) {
+    const int a0 = kc * KC;
+    float *Xs = Xs0 + buf * C::XS;
+    float *Bs = Bs0 + buf * C::BS;
 #pragma unroll
     for (int k = 0; k < NXW; ++k) {
       const int r0 = (wave * NXW + k) * 16, r = r0 + lrow;
@@ -132,16 +132,17 @@ __global__ __launch_bounds__(256, OCC) void k_exchange_f32_dl(const float *__res
       const float *src = (sl < ns && j < o && a < v) ? X + ((size_t)sl * o + j) * v + a : zp;
       dma16(src, Xs + r0 * KC);
     }
-    const float *Vq = Bvv + (size_t)q * v * v;
+    const float *Vq = Bvv + (size_t)(live ? q : 0) * v * v;
 #pragma unroll
     for (int k = 0; k < NBW; ++k) {
       const int r0 = (wave * NBW + k) * 16, r = r0 + lrow;
       const int a = a0 + 4 * ((lane & 3) ^ swz(r));
       const int cc = c_base + r;
-      const float *src = (cc < v && a < v) ? Vq + (size_t)cc * v + a : zp;  // row cc of symmetric B_vv
+      const float *src = (live && cc < v && a < v) ? Vq + (size_t)cc * v + a : zp;  // row cc of symmetric B_vv
       dma16(src, Bs + r0 * KC);
     }
   };
+  auto issue = [&](int c) { issue_at(qa + c / nkc, c % nkc, c % 3, true); };
   auto issue_os = [&](int q) {
     const float *Oq = Boo + (size_t)q * o * o;
 #pragma unroll
@@ -164,83 +165,6 @@ __global__ __launch_bounds__(256, OCC) void k_exchange_f32_dl(const float *__res
         Kacc[a][b][c] = f4{0.f, 0.f, 0.f, 0.f};
         Wacc[a][b][c] = f4{0.f, 0.f, 0.f, 0.f};
       }
-
-  struct Frag {
-    f4 bf[WC];
-    f4 af[WS][JB];
-  };
-  auto read_frags = [&](int c, Frag &F) {
-    const float *Xs = Xs0 + (c % 3) * C::XS;
-    const float *Bs = Bs0 + (c % 3) * C::BS;
-#pragma unroll
-    for (int cb = 0; cb < WC; ++cb) {
-      const int r = (wc * WC + cb) * 16 + n;
-      F.bf[cb] = *reinterpret_cast<const f4 *>(&Bs[r * KC + 4 * (g ^ swz(r))]);
-    }
-#pragma unroll
-    for (int si = 0; si < WS; ++si)
-#pragma unroll
-      for (int jb = 0; jb < JB; ++jb) {
-        const int r = (ws * WS + si) * O16 + jb * 16 + n;
-        F.af[si][jb] = *reinterpret_cast<const f4 *>(&Xs[r * KC + 4 * (g ^ swz(r))]);
-      }
-  };
-  // MFMAs of chunk c on fragments in registers, then (last chunk of a Q) K += B_oo^Q W
-  auto mfma_n = [&](auto ncb_tag, int c, const Frag &F) {
-    constexpr int NCB = decltype(ncb_tag)::value;
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-      for (int si = 0; si < WS; ++si)
-#pragma unroll
-        for (int jb = 0; jb < JB; ++jb)
-#pragma unroll
-          for (int cb = 0; cb < NCB; ++cb)
-            Wacc[si][jb][cb] =
-                __builtin_amdgcn_mfma_f32_16x16x4f32(F.af[si][jb][t], F.bf[cb][t], Wacc[si][jb][cb], 0, 0, 0);
-    if (c % nkc == nkc - 1) {
-#pragma unroll
-      for (int jb = 0; jb < JB; ++jb) {
-        f4 ar[JB];
-#pragma unroll
-        for (int ib = 0; ib < JB; ++ib) {
-          const int i = ib * 16 + n;
-          ar[ib] = *reinterpret_cast<const f4 *>(&Os[i * O16 + 4 * ((jb * 4 + g) ^ swz_o<O16>(i))]);
-        }
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-#pragma unroll
-          for (int ib = 0; ib < JB; ++ib)
-#pragma unroll
-            for (int si = 0; si < WS; ++si)
-#pragma unroll
-              for (int cb = 0; cb < NCB; ++cb)
-                Kacc[si][ib][cb] =
-                    __builtin_amdgcn_mfma_f32_16x16x4f32(ar[ib][t], Wacc[si][jb][cb][t], Kacc[si][ib][cb], 0, 0, 0);
-      }
-#pragma unroll
-      for (int a = 0; a < WS; ++a)
-#pragma unroll
-        for (int b = 0; b < JB; ++b)
-#pragma unroll
-          for (int cc = 0; cc < WC; ++cc) Wacc[a][b][cc] = f4{0.f, 0.f, 0.f, 0.f};
-    }
-  };
-  auto mfma_chunk = [&](int c, const Frag &F) {
-    if (nvalid == WC) {
-      mfma_n(std::integral_constant<int, WC>{}, c, F);
-    } else {
-      if constexpr (WC >= 4) {
-        if (nvalid == 3) mfma_n(std::integral_constant<int, 3>{}, c, F);
-      }
-      if constexpr (WC >= 3) {
-        if (nvalid == 2) mfma_n(std::integral_constant<int, 2>{}, c, F);
-      }
-      if constexpr (WC >= 2) {
-        if (nvalid == 1) mfma_n(std::integral_constant<int, 1>{}, c, F);
-      }
-    }
-  };
 
   // NCB = number of this wave's column blocks inside [0, v) (wave-uniform; only the last column
   // tile has fewer than WC): the MFMA loops are specialised on it instead of testing each block
@@ -322,34 +246,168 @@ __global__ __launch_bounds__(256, OCC) void k_exchange_f32_dl(const float *__res
   };
 
   if constexpr (PIPE) {
-    Frag F0, F1;  // two named sets (a dynamically indexed pair would live in scratch memory)
-    if (NC > 0) {
-      issue_os(qa);
-      issue(0);
-      if (NC > 1) {
-        issue(1);
-        wait_vm<NXB>();  // B_oo^Q and chunk 0 have landed
-      } else {
-        wait_vm<0>();
-      }
-      lds_barrier();
-      read_frags(0, F0);
-    }
-    auto step = [&](int c, const Frag &cur, Frag &nxt) {
-      const bool more2 = c + 2 < NC;
-      if (more2) issue(c + 2);  // its buffer's fragments were read before the previous barrier
-      if (c + 1 < NC) {
-        if (more2) wait_vm<NXB>(); else wait_vm<0>();  // chunk c+1 (and any B_oo^Q) has landed
-        lds_barrier();  // also: every wave is past the MFMAs of chunk c-1 (and their B_oo reads)
-        if (c > 0 && c % nkc == 0) issue_os(qa + c / nkc);  // needed at chunk c + nkc - 1 >= c + 2
-        read_frags(c + 1, nxt);
-        __builtin_amdgcn_sched_barrier(0);
-      }
-      mfma_chunk(c, cur);
+    // Half-chunk software pipeline.  A chunk's MFMAs split into half 0 (row blocks jb < JH) and
+    // half 1 (jb >= JH).  Per chunk c, after the barrier that publishes it: issue the loads of
+    // chunk c+2, read chunk c's B_vv fragments and half-0 X fragments, run half 1 of chunk c-1
+    // (fragments read before the barrier) and, at the end of a Q, its K product while they
+    // arrive, then half 0 of chunk c in two parts with the half-1 reads between them.  Every LDS
+    // wait is then a wait for all outstanding reads.  The chunk, K-chunk and Q counters advance
+    // incrementally (no divisions in the loop); chunks past the end are issued too (zero page for
+    // B_vv) so the loads need no branch; the B_oo^Q tile of the Q that starts at chunk s is loaded
+    // at chunk s+1, after the barrier behind which every wave finished the previous Q's K product,
+    // ahead of that chunk's own loads so that the per-chunk wait count stays the same.
+    constexpr int JH = (JB + 1) / 2;  // row blocks of half 0
+    struct FragB {
+      f4 b[WC];
     };
-    for (int c = 0; c < NC; c += 2) {
-      step(c, F0, F1);
-      if (c + 1 < NC) step(c + 1, F1, F0);
+    struct FragA {
+      f4 a[WS][JH];
+    };
+    auto read_b = [&](auto ncb_tag, int buf, FragB &F) __attribute__((always_inline)) {
+      constexpr int NCB = decltype(ncb_tag)::value;
+      const float *Bs = Bs0 + buf * C::BS;
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        const int r = (wc * WC + cb) * 16 + n;
+        F.b[cb] = *reinterpret_cast<const f4 *>(&Bs[r * KC + 4 * (g ^ swz(r))]);
+      }
+    };
+    auto read_a = [&](auto ncb_tag, auto half_tag, int buf, FragA &F) __attribute__((always_inline)) {
+      constexpr int NCB = decltype(ncb_tag)::value, HF = decltype(half_tag)::value;
+      const float *Xs = Xs0 + buf * C::XS;
+      if constexpr (NCB > 0) {
+#pragma unroll
+        for (int si = 0; si < WS; ++si)
+#pragma unroll
+          for (int jj = 0; jj < JH; ++jj) {
+            const int jb = HF * JH + jj;
+            if (jb < JB) {
+              const int r = (ws * WS + si) * O16 + jb * 16 + n;
+              F.a[si][jj] = *reinterpret_cast<const f4 *>(&Xs[r * KC + 4 * (g ^ swz(r))]);
+            }
+          }
+      }
+    };
+    // W += X B_vv for one half's row blocks, K values t0 <= t < t1 of the chunk
+    auto mfma_half = [&](auto ncb_tag, auto half_tag, const FragB &B, const FragA &A, auto t0_tag, auto t1_tag) __attribute__((always_inline)) {
+      constexpr int NCB = decltype(ncb_tag)::value, HF = decltype(half_tag)::value;
+      constexpr int t0 = decltype(t0_tag)::value, t1 = decltype(t1_tag)::value;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        if (t < t0 || t >= t1) continue;
+#pragma unroll
+        for (int si = 0; si < WS; ++si)
+#pragma unroll
+          for (int jj = 0; jj < JH; ++jj) {
+            const int jb = HF * JH + jj;
+            if (jb < JB) {
+#pragma unroll
+              for (int cb = 0; cb < NCB; ++cb)
+                Wacc[si][jb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(A.a[si][jj][t], B.b[cb][t], Wacc[si][jb][cb], 0, 0, 0);
+            }
+          }
+      }
+    };
+    // K += B_oo^Q W for the Q whose last chunk was just multiplied, then W = 0
+    auto compute_k = [&](auto ncb_tag) __attribute__((always_inline)) {
+      constexpr int NCB = decltype(ncb_tag)::value;
+#pragma unroll
+      for (int jb = 0; jb < JB; ++jb) {
+        f4 ar[JB];
+#pragma unroll
+        for (int ib = 0; ib < JB; ++ib) {
+          const int i = ib * 16 + n;
+          ar[ib] = *reinterpret_cast<const f4 *>(&Os[i * O16 + 4 * ((jb * 4 + g) ^ swz_o<O16>(i))]);
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+          for (int ib = 0; ib < JB; ++ib)
+#pragma unroll
+            for (int si = 0; si < WS; ++si)
+#pragma unroll
+              for (int cb = 0; cb < NCB; ++cb)
+                Kacc[si][ib][cb] =
+                    __builtin_amdgcn_mfma_f32_16x16x4f32(ar[ib][t], Wacc[si][jb][cb][t], Kacc[si][ib][cb], 0, 0, 0);
+      }
+#pragma unroll
+      for (int a = 0; a < WS; ++a)
+#pragma unroll
+        for (int b = 0; b < JB; ++b)
+#pragma unroll
+          for (int cc = 0; cc < WC; ++cc) Wacc[a][b][cc] = f4{0.f, 0.f, 0.f, 0.f};
+    };
+    using H0 = std::integral_constant<int, 0>;
+    using H1 = std::integral_constant<int, 1>;
+    using T0 = std::integral_constant<int, 0>;
+    using T2 = std::integral_constant<int, 2>;
+    using T4 = std::integral_constant<int, 4>;
+    auto main_loop = [&](auto ncb_tag) __attribute__((always_inline)) {
+      constexpr int NCB = decltype(ncb_tag)::value;
+      if (NC == 0) return;
+      FragB B0, B1;
+      FragA A0, A1;
+      issue_os(qa);
+      issue_at(qa, 0, 0, true);
+      // chunk c+2's (Q, K chunk, buffer), advanced one chunk per iteration
+      int q2 = qa, kc2 = 1, b2 = 1;
+      if (kc2 == nkc) { kc2 = 0; ++q2; }
+      issue_at(q2, kc2, b2, NC > 1);
+      auto adv2 = [&]() __attribute__((always_inline)) {
+        if (++kc2 == nkc) { kc2 = 0; ++q2; }
+        b2 = b2 == 2 ? 0 : b2 + 1;
+      };
+      adv2();
+      int kcc = 0, qc = qa, buf = 0;  // chunk c's K chunk, Q index and LDS buffer
+      auto step = [&](int c, FragB &Bc, const FragB &Bp) __attribute__((always_inline)) {
+        wait_vm<NXB>();  // chunk c (and a B_oo^Q tile issued before it) has landed
+        lds_barrier();   // publishes chunk c; every wave has read chunk c-1 and run the last K product
+        if (kcc == 1 && c > 1) issue_os(qc);  // chunk c-1 opened Q qc; the K product before it is done
+        issue_at(q2, kc2, b2, c + 2 < NC);
+        adv2();
+        __builtin_amdgcn_sched_barrier(0);
+        read_b(ncb_tag, buf, Bc);
+        read_a(ncb_tag, H0{}, buf, A0);
+        __builtin_amdgcn_sched_barrier(0);
+        if (c > 0) {
+          mfma_half(ncb_tag, H1{}, Bp, A1, T0{}, T4{});  // chunk c-1, half 1
+          if constexpr (NCB > 0) {
+            if (kcc == 0) compute_k(ncb_tag);  // chunk c-1 closed its Q
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        mfma_half(ncb_tag, H0{}, Bc, A0, T0{}, T2{});
+        __builtin_amdgcn_sched_barrier(0);
+        read_a(ncb_tag, H1{}, buf, A1);
+        __builtin_amdgcn_sched_barrier(0);
+        mfma_half(ncb_tag, H0{}, Bc, A0, T2{}, T4{});
+        if (++kcc == nkc) { kcc = 0; ++qc; }
+        buf = buf == 2 ? 0 : buf + 1;
+      };
+      for (int c = 0; c < NC; c += 2) {
+        step(c, B0, B1);
+        if (c + 1 < NC) step(c + 1, B1, B0);
+      }
+      if (NC & 1)  // chunk NC-1, half 1 (a select between the two sets would put them in memory)
+        mfma_half(ncb_tag, H1{}, B0, A1, T0{}, T4{});
+      else
+        mfma_half(ncb_tag, H1{}, B1, A1, T0{}, T4{});
+      if constexpr (NCB > 0) compute_k(ncb_tag);
+      wait_vm<0>();  // no LDS write may still be in flight when the workgroup ends
+    };
+    if (nvalid == WC) {
+      main_loop(std::integral_constant<int, WC>{});
+    } else {
+      if constexpr (WC >= 4) {
+        if (nvalid == 3) main_loop(std::integral_constant<int, 3>{});
+      }
+      if constexpr (WC >= 3) {
+        if (nvalid == 2) main_loop(std::integral_constant<int, 2>{});
+      }
+      if constexpr (WC >= 2) {
+        if (nvalid == 1) main_loop(std::integral_constant<int, 1>{});
+      }
+      if (nvalid == 0) main_loop(std::integral_constant<int, 0>{});
     }
   } else {
   if (NC > 0) {
@@ -422,18 +480,15 @@ hipError_t prepare_xf32dl() {
   ExchangeVariant {                                                                                      \
     RTTDA_PREC_FP32, O16, CfgD<O16, WS, WC>::KS, CfgD<O16, WS, WC>::NT, NAME,                            \
         &launch_xf32dl<O16, WS, WC, PIPE, OCC>, CfgD<O16, WS, WC>::LDS,                                  \
-        &prepare_xf32dl<O16, WS, WC, PIPE, OCC>, 3 * KC, 4, 4                                            \
+        &prepare_xf32dl<O16, WS, WC, PIPE, OCC>, 3 * KC, 4, 4, 1, false, PIPE ? 2 : 1                    \
   }
 #define XDL2(O16, WS, WC)                                                                                \
   XDL(O16, WS, WC, false, 2, "f32dl_o" #O16 "_ws" #WS "_wc" #WC),                                        \
       XDL(O16, WS, WC, true, 2, "f32dlp_o" #O16 "_ws" #WS "_wc" #WC)
 
-// (the register-pipelined form of the larger tiles would spill, so those have only the plain form;
-// o64 ws1 wc2 already fits three workgroups per CU: 134 registers, 52 KiB of LDS)
+// (o64 ws1 wc2 fits three workgroups per CU in both forms: at most 152 registers, 52 KiB of LDS)
 const ExchangeVariant kF32DlVariants[] = {
-    XDL2(32, 1, 2), XDL2(32, 2, 2), XDL2(48, 2, 2), XDL2(64, 1, 2),
-    XDL(64, 2, 2, false, 2, "f32dl_o64_ws2_wc2"), XDL(64, 1, 4, false, 2, "f32dl_o64_ws1_wc4"),
-    XDL(96, 1, 2, false, 2, "f32dl_o96_ws1_wc2"),
+    XDL2(32, 1, 2), XDL2(32, 2, 2), XDL2(48, 2, 2), XDL2(64, 1, 2), XDL2(64, 2, 2), XDL2(64, 1, 4), XDL2(96, 1, 2),
 };
 
 }  // namespace

@@ -51,7 +51,9 @@ rttda_status fail(rttda_status st, const char *fmt, ...) {
 
 constexpr int MAX_RHS = 4096;
 constexpr int SJ_MAX = 8;    // Coulomb second-product Q splits
-constexpr int SK_MAX = 192;  // exchange Q splits
+constexpr int SK_MAX = 768;  // exchange Q splits
+// the exchange's partial K slabs (one per split) take at most this much workspace, or 32 slabs
+constexpr size_t SK_SLAB_BYTES = (size_t)256 << 20;
 constexpr size_t ALIGN = 256;
 
 inline size_t up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
@@ -78,7 +80,7 @@ Layout make_layout(int o, int v, int nq, int R, int prec) {
   };
   L.nbf = field_blocks_a(v) * field_blocks_i(o);
   L.sj_max = nq > 0 ? std::min(SJ_MAX, nq) : 0;
-  L.sk_max = nq > 0 ? std::min(SK_MAX, nq) : 0;
+  L.sk_max = nq > 0 ? std::min({SK_MAX, nq, (int)std::max<size_t>(32, SK_SLAB_BYTES / (ns * ov * 4))}) : 0;
   L.D = take(ov * 8);
   L.moo = take((size_t)R * o * o * 8);
   L.mov = take((size_t)R * ov * 8);
@@ -305,8 +307,9 @@ int auto_variant(int prec, int o, int ns, int v, const Layout &L) {
     if (x->scratch && usable(x, o, v, L)) return k;
   }
   // else the smallest padded occupied size that holds o; among those prefer the variant whose
-  // tile wastes the least of the (slices x columns) space, then the larger tile.
-  int best = -1;
+  // tile wastes the least of the (slices x columns) space, then the larger tile, then the
+  // variant's rank (the pipelined direct-to-LDS kernels over the plain ones over the register ones).
+  int best = -1, best_rank = -1;
   double best_score = 1e300;
   int o16_best = 1 << 30;
   for (int k = 0; k < n; ++k) {
@@ -320,8 +323,9 @@ int auto_variant(int prec, int o, int ns, int v, const Layout &L) {
     const double cols = (double)((v + x->nt - 1) / x->nt) * x->nt;
     const double waste = rows * cols / ((double)ns * v);
     const double score = waste * (1.0 + 8.0 / (x->ks * x->nt));  // mild preference for big tiles
-    if (score < best_score) {
+    if (score < best_score * (1.0 - 1e-12) || (score <= best_score * (1.0 + 1e-12) && x->rank > best_rank)) {
       best_score = score;
+      best_rank = x->rank;
       best = k;
     }
   }
@@ -711,6 +715,12 @@ rttda_status rttda_get_tuning(const rttda_ctx *ctx, rttda_tuning *t) {
   t->use_graph = ctx->use_graph;
   t->steps_per_graph = ctx->steps_per_graph;
   t->exchange_chunk = ctx->qchunk;
+  return RTTDA_OK;
+}
+
+rttda_status rttda_exchange_splits_max(const rttda_ctx *ctx, int32_t *out) {
+  if (!ctx || !out) return fail(RTTDA_E_INVAL, "NULL argument");
+  *out = ctx->L.sk_max;
   return RTTDA_OK;
 }
 

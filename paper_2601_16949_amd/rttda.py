@@ -92,6 +92,7 @@ EXPORTS = {
                                              ctypes.POINTER(ctypes.c_double)]),
     "rttda_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(CTuning)]),
     "rttda_get_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(CTuning)]),
+    "rttda_exchange_splits_max": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_I32)]),
     "rttda_exchange_variants": (ctypes.c_int32, [ctypes.c_int32]),
     "rttda_exchange_variant_name": (ctypes.c_char_p, [ctypes.c_int32, ctypes.c_int32]),
     "rttda_last_error": (ctypes.c_char_p, []),
@@ -337,8 +338,10 @@ class Context:
         return {k: getattr(t, k) for k, _ in CTuning._fields_}
 
     def max_splits(self) -> int:
-        """Largest exchange split count the workspace holds (min(192, N_Q))."""
-        return max(1, min(192, self.dev.nq))
+        """Largest exchange split count the workspace holds."""
+        n = _I32()
+        _check(self.lib.rttda_exchange_splits_max(self.handle, ctypes.byref(n)))
+        return max(1, int(n.value))
 
     def use_tuned(self, nrhs: int) -> bool:
         """Apply the packaged autotune choice for (shape, nrhs) if there is one."""
