@@ -212,6 +212,29 @@ rttda_status rttda_pool_usage(const rttda_pool *pool, size_t *used_bytes, int32_
  * the state of later rttda_propagate calls). */
 rttda_status rttda_spectral_radius(rttda_ctx *ctx, int32_t n_iter, double *rho, double *rho_bound);
 
+/* The k lowest eigenpairs of A: the TI-TDA eigenproblem A X = omega X (eq. casida_tda), by block
+ * Davidson on the sigma product (Coulomb and exchange kernels of the context's precision plus the
+ * diagonal e_a - e_i; FP64 vectors, Rayleigh-Ritz on the host).  The search space starts from unit
+ * vectors at the smallest entries of diag(A), holds at most m_max vectors (3k <= m_max <= 64, at
+ * most o*v) and restarts from the 2k lowest Ritz vectors when full; corrections use diag(A) as the
+ * preconditioner (D + 2 sum_Q B_ia^2 - c_x sum_Q B_ii B_aa, formed on the device).
+ * work: device buffer of at least rttda_eigen_workspace_bytes (256-byte aligned, caller-owned);
+ * evals, resid: host [k], the Ritz values (ascending) and residual norms |A x - w x| of the unit
+ * Ritz vectors; evecs: device [k][o][v] FP64 Ritz vectors, or NULL.  Stops when every residual is
+ * at most tol, after max_iter iterations, or when the space stops growing; *iters (may be NULL)
+ * receives the iterations used; callers compare resid with tol.  Synchronises the context's stream
+ * and uses its stage buffers (no effect on the state of later rttda_propagate calls). */
+rttda_status rttda_eigen_workspace_bytes(const rttda_ctx *ctx, int32_t k, int32_t m_max, size_t *bytes);
+rttda_status rttda_eigen_lowest(rttda_ctx *ctx, int32_t k, int32_t m_max, int32_t max_iter, double tol, void *work,
+                                size_t work_bytes, double *evals, double *resid, double *evecs, int32_t *iters);
+
+/* Eigenstate populations (eq. populations): out[r][I] = |<U_I, c_r>|^2 for the k real unit
+ * vectors U (device [k][o][v] FP64, e.g. from rttda_eigen_lowest) and the states c (device
+ * [nrhs][2][o][v] FP64 planes), 1 <= k <= 64, 1 <= nrhs <= 32.  work: device buffer of at least
+ * k*2*nrhs doubles; out: host [nrhs][k].  Synchronises the context's stream. */
+rttda_status rttda_populations(rttda_ctx *ctx, int32_t k, const double *evecs, int32_t nrhs, const double *c,
+                               void *work, size_t work_bytes, double *out);
+
 /* Launch configuration knobs (for the autotuner).  Zero fields keep the
  * library's choice.  Returns RTTDA_E_UNSUPPORTED for a tile variant this build
  * does not have, RTTDA_E_NOMEM when the splits do not fit the workspace. */

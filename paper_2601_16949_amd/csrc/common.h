@@ -97,6 +97,25 @@ hipError_t launch_lz_apply(hipStream_t s, long long n, int nslab, const double *
 hipError_t launch_lz_orth(hipStream_t s, long long n, const double *v, double alpha, double *w, double *part);
 hipError_t launch_lz_next(hipStream_t s, int prec, long long n, double scale, const double *w, double *v,
                           double *vprev, float *x32, __hip_bfloat16 *xhi, __hip_bfloat16 *xlo, int shift);
+// Block Davidson (lowest eigenpairs of A) and populations: FP64 vectors of n = o*v stored one after
+// another; per-block partial sums (at most DV_BLOCKS_MAX per vector) are added on the host.
+constexpr int DV_BLOCKS_MAX = 1024;
+constexpr int DV_SPACE_MAX = 64;  // largest search space (vectors)
+int dv_blocks(long long n);
+hipError_t launch_dv_apply(hipStream_t s, long long n, int nb, int nslab, const double *D, const float *P,
+                           const double *V, double *W);
+hipError_t launch_dv_dots(hipStream_t s, long long n, int m, const double *V, int nt, const double *T, double *out);
+hipError_t launch_dv_combine(hipStream_t s, long long n, int m, const double *V, int nc, const double *C, int ldc,
+                             int mode, double *out);
+hipError_t launch_dv_resid(hipStream_t s, long long n, int nc, const double *X, const double *AX, const double *theta,
+                           double *R, double *part);
+hipError_t launch_dv_precond(hipStream_t s, long long n, int nc, const double *R, const double *theta,
+                             const double *D, double *T);
+hipError_t launch_dv_norm2(hipStream_t s, long long n, const double *T, double *part);
+hipError_t launch_dv_scale(hipStream_t s, long long n, double scale, const double *T, double *out);
+hipError_t launch_dv_unit(hipStream_t s, long long n, long long idx, double *V);
+hipError_t launch_dv_diag(hipStream_t s, int b_dtype, int o, int v, int nq, const void *Bov, const void *Boo,
+                          const void *Bvv, double cx, const double *D, double *diag);
 hipError_t launch_kick(hipStream_t s, int R, int ov, const DevPulse *pulses, const double *F, const double *sc,
                        double *c, double *c0);
 hipError_t launch_set_state(hipStream_t s, DevState *st, long long step0, double *trace, double *norms);

@@ -483,6 +483,15 @@ rttda_status enqueue_sso_start(rttda_ctx *ctx, int nrhs, double dt, bool has_fie
   return RTTDA_OK;
 }
 
+// FP32 (and BF16 hi/lo) stage copies of cnt FP64 values, cnt at most the 2R slices the buffers hold
+rttda_status to_stage_copy_n(rttda_ctx *ctx, const double *c, long long cnt) {
+  if (ctx->prec == RTTDA_PREC_FP32)
+    HIP_TRY(launch_to_f32(ctx->stream, c, cnt, ctx->x32()));
+  else
+    HIP_TRY(launch_to_bf16x2(ctx->stream, c, cnt, ctx->x32(), ctx->xhi(), ctx->xlo()));
+  return RTTDA_OK;
+}
+
 rttda_status to_stage_copy(rttda_ctx *ctx, const double *c, int nrhs) {
   const long long n = 2LL * nrhs * (long long)ctx->ov;
   if (ctx->prec == RTTDA_PREC_FP32)
@@ -528,6 +537,79 @@ double tridiag_eig(const std::vector<double> &a, const std::vector<double> &b, i
 
 // |last component| of the unit eigenvector of T for eigenvalue theta (inverse iteration with the
 // tridiagonal solve of (T - mu I) y = x, mu = theta slightly shifted).
+// Eigen-decomposition of a symmetric m x m matrix (row-major, overwritten) by cyclic Jacobi
+// rotations: w ascending, z the matching eigenvectors as columns (row-major m x m).
+void jacobi_eig(int m, std::vector<double> &a, std::vector<double> &w, std::vector<double> &z) {
+  z.assign((size_t)m * m, 0.0);
+  for (int i = 0; i < m; ++i) z[(size_t)i * m + i] = 1.0;
+  double scale = 0.0;
+  for (double x : a) scale += x * x;
+  for (int sweep = 0; sweep < 64; ++sweep) {
+    double off = 0.0;
+    for (int p = 0; p < m; ++p)
+      for (int q = p + 1; q < m; ++q) off += a[(size_t)p * m + q] * a[(size_t)p * m + q];
+    if (!(off > 1e-30 * scale)) break;
+    for (int p = 0; p < m; ++p)
+      for (int q = p + 1; q < m; ++q) {
+        const double apq = a[(size_t)p * m + q];
+        if (apq == 0.0) continue;
+        const double th = (a[(size_t)q * m + q] - a[(size_t)p * m + p]) / (2.0 * apq);
+        const double t = (th >= 0.0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+        for (int k = 0; k < m; ++k) {  // A J
+          const double akp = a[(size_t)k * m + p], akq = a[(size_t)k * m + q];
+          a[(size_t)k * m + p] = c * akp - sn * akq;
+          a[(size_t)k * m + q] = sn * akp + c * akq;
+        }
+        for (int k = 0; k < m; ++k) {  // J^T (A J)
+          const double apk = a[(size_t)p * m + k], aqk = a[(size_t)q * m + k];
+          a[(size_t)p * m + k] = c * apk - sn * aqk;
+          a[(size_t)q * m + k] = sn * apk + c * aqk;
+        }
+        for (int k = 0; k < m; ++k) {  // Z J
+          const double zkp = z[(size_t)k * m + p], zkq = z[(size_t)k * m + q];
+          z[(size_t)k * m + p] = c * zkp - sn * zkq;
+          z[(size_t)k * m + q] = sn * zkp + c * zkq;
+        }
+      }
+  }
+  std::vector<int> ord(m);
+  for (int i = 0; i < m; ++i) ord[i] = i;
+  std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return a[(size_t)x * m + x] < a[(size_t)y * m + y]; });
+  std::vector<double> zs((size_t)m * m);
+  w.resize(m);
+  for (int j = 0; j < m; ++j) {
+    w[j] = a[(size_t)ord[j] * m + ord[j]];
+    for (int k = 0; k < m; ++k) zs[(size_t)k * m + j] = z[(size_t)k * m + ord[j]];
+  }
+  z.swap(zs);
+}
+
+// Layout of the eigen-solver workspace: V, W (search space and its image, m_max vectors each),
+// Z (2k Ritz vectors, their images, k residuals / corrections), the diagonal of A, small arrays.
+struct EigLayout {
+  size_t V, W, Z, diag, C, theta, dots, part, total;
+};
+EigLayout eig_layout(size_t n, int k, int m_max) {
+  EigLayout e{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off += up(bytes > 0 ? bytes : 1);
+    return at;
+  };
+  e.V = take((size_t)m_max * n * 8);
+  e.W = take((size_t)m_max * n * 8);
+  e.Z = take((size_t)5 * k * n * 8);
+  e.diag = take(n * 8);
+  e.C = take((size_t)m_max * m_max * 8);
+  e.theta = take((size_t)m_max * 8);
+  e.dots = take((size_t)m_max * m_max * 8);
+  e.part = take((size_t)std::max(m_max, 3 * k) * DV_BLOCKS_MAX * 8);
+  e.total = off;
+  return e;
+}
+
 double tridiag_last_component(const std::vector<double> &a, const std::vector<double> &b, double theta) {
   const size_t k = a.size();
   const double mu = theta + 1e-10 * std::max(1.0, std::fabs(theta));
@@ -945,6 +1027,199 @@ rttda_status rttda_spectral_radius(rttda_ctx *ctx, int32_t n_iter, double *rho, 
   const double emax = blast * tridiag_last_component(alpha, beta, tmax);
   *rho = std::max(std::fabs(tmin), std::fabs(tmax));
   *rho_bound = std::max(std::fabs(tmin) + emin, std::fabs(tmax) + emax);
+  return RTTDA_OK;
+}
+
+rttda_status rttda_eigen_workspace_bytes(const rttda_ctx *ctx, int32_t k, int32_t m_max, size_t *bytes) {
+  if (!ctx || !bytes) return fail(RTTDA_E_INVAL, "NULL argument");
+  if (k < 1 || m_max < 3 * k || m_max > DV_SPACE_MAX || (size_t)m_max > ctx->ov)
+    return fail(RTTDA_E_INVAL, "need 1 <= k, 3k <= m_max <= min(%d, o*v) (k=%d m_max=%d)", DV_SPACE_MAX, k, m_max);
+  *bytes = eig_layout(ctx->ov, k, m_max).total;
+  return RTTDA_OK;
+}
+
+rttda_status rttda_eigen_lowest(rttda_ctx *ctx, int32_t k, int32_t m_max, int32_t max_iter, double tol, void *work,
+                                size_t work_bytes, double *evals, double *resid, double *evecs, int32_t *iters) {
+  if (!ctx || !work || !evals || !resid) return fail(RTTDA_E_INVAL, "NULL argument");
+  size_t need = 0;
+  rttda_status st = rttda_eigen_workspace_bytes(ctx, k, m_max, &need);
+  if (st != RTTDA_OK) return st;
+  if (work_bytes < need) return fail(RTTDA_E_NOMEM, "eigen workspace %zu bytes < %zu needed", work_bytes, need);
+  if ((reinterpret_cast<uintptr_t>(work) & (ALIGN - 1)) != 0) return fail(RTTDA_E_INVAL, "work not 256-byte aligned");
+  if (max_iter < 1 || !(tol > 0.0)) return fail(RTTDA_E_INVAL, "need max_iter >= 1 and tol > 0");
+  hipStream_t hs = ctx->stream;
+  const long long n = (long long)ctx->ov;
+  const EigLayout E = eig_layout(ctx->ov, k, m_max);
+  char *wb = static_cast<char *>(work);
+  double *V = reinterpret_cast<double *>(wb + E.V), *W = reinterpret_cast<double *>(wb + E.W);
+  double *Xr = reinterpret_cast<double *>(wb + E.Z), *AXr = Xr + (size_t)2 * k * n, *Rr = Xr + (size_t)4 * k * n;
+  double *diag = reinterpret_cast<double *>(wb + E.diag);
+  double *Cd = reinterpret_cast<double *>(wb + E.C), *thd = reinterpret_cast<double *>(wb + E.theta);
+  double *dotd = reinterpret_cast<double *>(wb + E.dots), *partd = reinterpret_cast<double *>(wb + E.part);
+  const int nblk = dv_blocks(n);
+  const int batch = 2 * ctx->R;  // real vectors per sigma launch (the stage buffers hold 2R slices)
+
+  // diagonal of A (preconditioner and start vectors), with a host copy
+  if (ctx->nq > 0)
+    HIP_TRY(launch_dv_diag(hs, ctx->d.b_dtype, ctx->o, ctx->v, ctx->nq, ctx->d.b_ov, ctx->d.b_oo, ctx->d.b_vv,
+                           ctx->d.cx, ctx->D(), diag));
+  else
+    HIP_TRY(hipMemcpyAsync(diag, ctx->D(), n * sizeof(double), hipMemcpyDeviceToDevice, hs));
+  std::vector<double> Dh(n);
+  HIP_TRY(hipMemcpyAsync(Dh.data(), diag, n * sizeof(double), hipMemcpyDeviceToHost, hs));
+  HIP_TRY(hipStreamSynchronize(hs));
+  auto upload = [&](double *dst, const std::vector<double> &src) -> rttda_status {
+    HIP_TRY(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(double), hipMemcpyHostToDevice, hs));
+    HIP_TRY(hipStreamSynchronize(hs));
+    return RTTDA_OK;
+  };
+  auto download = [&](std::vector<double> &dst, const double *src, size_t cnt) -> rttda_status {
+    dst.resize(cnt);
+    HIP_TRY(hipMemcpyAsync(dst.data(), src, cnt * sizeof(double), hipMemcpyDeviceToHost, hs));
+    HIP_TRY(hipStreamSynchronize(hs));
+    return RTTDA_OK;
+  };
+  // W[j0..j1) = A V[j0..j1), in launches of at most `batch` vectors
+  auto apply = [&](int j0, int j1) -> rttda_status {
+    for (int b0 = j0; b0 < j1; b0 += batch) {
+      const int nb = std::min(batch, j1 - b0);
+      rttda_status s2 = to_stage_copy_n(ctx, V + (size_t)b0 * n, (long long)nb * n);
+      if (s2 != RTTDA_OK) return s2;
+      if (ctx->nq > 0 && (s2 = enqueue_two_electron(ctx, nb)) != RTTDA_OK) return s2;
+      HIP_TRY(launch_dv_apply(hs, n, nb, nslab(ctx), ctx->D(), ctx->P(), V + (size_t)b0 * n, W + (size_t)b0 * n));
+    }
+    return RTTDA_OK;
+  };
+  std::vector<double> hbuf;
+  // <V_i, T_j> for i < m, j < nt, on the host as [m][nt]
+  auto dots = [&](int m, const double *T, int nt, std::vector<double> &out) -> rttda_status {
+    HIP_TRY(launch_dv_dots(hs, n, m, V, nt, T, dotd));
+    return download(out, dotd, (size_t)m * nt);
+  };
+  auto norm2 = [&](const double *T, double &out) -> rttda_status {
+    HIP_TRY(launch_dv_norm2(hs, n, T, partd));
+    rttda_status s2 = download(hbuf, partd, nblk);
+    if (s2 != RTTDA_OK) return s2;
+    out = 0.0;
+    for (double t : hbuf) out += t;
+    return RTTDA_OK;
+  };
+
+  // start: unit vectors at the smallest diagonal entries
+  std::vector<long long> idx(n);
+  for (long long e = 0; e < n; ++e) idx[e] = e;
+  const int m0 = std::min(m_max / 2, std::max(k, std::min(2 * k, m_max / 2)));
+  std::partial_sort(idx.begin(), idx.begin() + m0, idx.end(), [&](long long x, long long y) {
+    return Dh[x] < Dh[y] || (Dh[x] == Dh[y] && x < y);
+  });
+  for (int j = 0; j < m0; ++j) HIP_TRY(launch_dv_unit(hs, n, idx[j], V + (size_t)j * n));
+  int m = m0;
+  if ((st = apply(0, m)) != RTTDA_OK) return st;
+  std::vector<double> H((size_t)m_max * m_max, 0.0), d;
+  if ((st = dots(m, W, m, d)) != RTTDA_OK) return st;
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) H[(size_t)i * m_max + j] = 0.5 * (d[(size_t)i * m + j] + d[(size_t)j * m + i]);
+
+  std::vector<double> theta, Y, a, rn(k, 0.0);
+  int it = 0;
+  for (;; ++it) {
+    a.assign((size_t)m * m, 0.0);
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) a[(size_t)i * m + j] = H[(size_t)i * m_max + j];
+    jacobi_eig(m, a, theta, Y);
+    // the nr lowest Ritz vectors X = V Y, their images A X = W Y (the first k are the answer, all
+    // nr are kept at a restart), residuals R = A X - theta X of the first k
+    const int nr = std::min(2 * k, m);
+    std::vector<double> Ck((size_t)m * nr), thk(theta.begin(), theta.begin() + k);
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < nr; ++j) Ck[(size_t)i * nr + j] = Y[(size_t)i * m + j];
+    if ((st = upload(Cd, Ck)) != RTTDA_OK) return st;
+    if ((st = upload(thd, thk)) != RTTDA_OK) return st;
+    for (int j0 = 0; j0 < nr; j0 += 16) {
+      const int nc = std::min(16, nr - j0);
+      HIP_TRY(launch_dv_combine(hs, n, m, V, nc, Cd + j0, nr, 0, Xr + (size_t)j0 * n));
+      HIP_TRY(launch_dv_combine(hs, n, m, W, nc, Cd + j0, nr, 0, AXr + (size_t)j0 * n));
+    }
+    HIP_TRY(launch_dv_resid(hs, n, k, Xr, AXr, thd, Rr, partd));
+    if ((st = download(hbuf, partd, (size_t)k * nblk)) != RTTDA_OK) return st;
+    std::vector<int> open;
+    for (int j = 0; j < k; ++j) {
+      double r2 = 0.0;
+      for (int b = 0; b < nblk; ++b) r2 += hbuf[(size_t)j * nblk + b];
+      rn[j] = std::sqrt(std::max(r2, 0.0));
+      if (!(rn[j] <= tol)) open.push_back(j);
+    }
+    if (open.empty() || it + 1 >= max_iter) break;
+    // corrections from the diagonal preconditioner (in place of the residuals)
+    HIP_TRY(launch_dv_precond(hs, n, k, Rr, thd, diag, Rr));
+    if (m + (int)open.size() > m_max) {  // restart from the nr lowest Ritz vectors and their images
+      HIP_TRY(hipMemcpyAsync(V, Xr, (size_t)nr * n * sizeof(double), hipMemcpyDeviceToDevice, hs));
+      HIP_TRY(hipMemcpyAsync(W, AXr, (size_t)nr * n * sizeof(double), hipMemcpyDeviceToDevice, hs));
+      std::fill(H.begin(), H.end(), 0.0);
+      for (int j = 0; j < nr; ++j) H[(size_t)j * m_max + j] = theta[j];
+      m = nr;
+    }
+    const int m_old = m;
+    for (int j : open) {
+      double *t = Rr + (size_t)j * n;
+      double n0 = 0.0, n1 = 0.0;
+      if ((st = norm2(t, n0)) != RTTDA_OK) return st;
+      for (int pass = 0; pass < 2; ++pass) {  // classical Gram-Schmidt against the space, twice
+        std::vector<double> c;
+        if ((st = dots(m, t, 1, c)) != RTTDA_OK) return st;
+        if ((st = upload(Cd, c)) != RTTDA_OK) return st;
+        HIP_TRY(launch_dv_combine(hs, n, m, V, 1, Cd, 1, 1, t));
+      }
+      if ((st = norm2(t, n1)) != RTTDA_OK) return st;
+      if (!(n1 > 1e-10 * n0) || !(n1 > 0.0)) continue;  // nothing new in this direction
+      HIP_TRY(launch_dv_scale(hs, n, 1.0 / std::sqrt(n1), t, V + (size_t)m * n));
+      ++m;
+    }
+    if (m == m_old) break;  // the space stopped growing
+    if ((st = apply(m_old, m)) != RTTDA_OK) return st;
+    const int nn = m - m_old;
+    if ((st = dots(m, W + (size_t)m_old * n, nn, d)) != RTTDA_OK) return st;
+    for (int i = 0; i < m; ++i)
+      for (int jj = 0; jj < nn; ++jj) {
+        const int j = m_old + jj;
+        const double x = d[(size_t)i * nn + jj];
+        if (i < m_old) {
+          H[(size_t)i * m_max + j] = H[(size_t)j * m_max + i] = x;
+        } else if (i <= j) {
+          const double y = d[(size_t)j * nn + (i - m_old)];
+          H[(size_t)i * m_max + j] = H[(size_t)j * m_max + i] = 0.5 * (x + y);
+        }
+      }
+  }
+  for (int j = 0; j < k; ++j) {
+    evals[j] = theta[j];
+    resid[j] = rn[j];
+  }
+  if (evecs) HIP_TRY(hipMemcpyAsync(evecs, Xr, (size_t)k * n * sizeof(double), hipMemcpyDeviceToDevice, hs));
+  HIP_TRY(hipStreamSynchronize(hs));
+  if (iters) *iters = it + 1;
+  return RTTDA_OK;
+}
+
+rttda_status rttda_populations(rttda_ctx *ctx, int32_t k, const double *evecs, int32_t nrhs, const double *c,
+                               void *work, size_t work_bytes, double *out) {
+  if (!ctx || !evecs || !c || !work || !out) return fail(RTTDA_E_INVAL, "NULL argument");
+  if (k < 1 || k > DV_SPACE_MAX) return fail(RTTDA_E_INVAL, "k=%d outside 1..%d", k, DV_SPACE_MAX);
+  if (nrhs < 1 || nrhs > DV_SPACE_MAX / 2) return fail(RTTDA_E_INVAL, "nrhs=%d outside 1..%d", nrhs, DV_SPACE_MAX / 2);
+  const size_t need = (size_t)k * 2 * nrhs * sizeof(double);
+  if (work_bytes < need) return fail(RTTDA_E_NOMEM, "populations workspace %zu bytes < %zu needed", work_bytes, need);
+  hipStream_t hs = ctx->stream;
+  const long long n = (long long)ctx->ov;
+  double *dd = static_cast<double *>(work);
+  HIP_TRY(launch_dv_dots(hs, n, k, evecs, 2 * nrhs, c, dd));
+  std::vector<double> h((size_t)k * 2 * nrhs);
+  HIP_TRY(hipMemcpyAsync(h.data(), dd, h.size() * sizeof(double), hipMemcpyDeviceToHost, hs));
+  HIP_TRY(hipStreamSynchronize(hs));
+  for (int r = 0; r < nrhs; ++r)
+    for (int i = 0; i < k; ++i) {
+      const double re = h[(size_t)i * 2 * nrhs + 2 * r], im = h[(size_t)i * 2 * nrhs + 2 * r + 1];
+      out[(size_t)r * k + i] = re * re + im * im;
+    }
   return RTTDA_OK;
 }
 

@@ -90,6 +90,10 @@ EXPORTS = {
     "rttda_guard": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
     "rttda_spectral_radius": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                              ctypes.POINTER(ctypes.c_double)]),
+    "rttda_eigen_workspace_bytes": (ctypes.c_int, [_VP, _I32, _I32, ctypes.POINTER(_SZ)]),
+    "rttda_eigen_lowest": (ctypes.c_int, [_VP, _I32, _I32, _I32, _D, _VP, _SZ, ctypes.POINTER(_D), ctypes.POINTER(_D),
+                                          _VP, ctypes.POINTER(_I32)]),
+    "rttda_populations": (ctypes.c_int, [_VP, _I32, _VP, _I32, _VP, _VP, _SZ, ctypes.POINTER(_D)]),
     "rttda_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(CTuning)]),
     "rttda_get_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(CTuning)]),
     "rttda_exchange_splits_max": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_I32)]),
@@ -304,6 +308,50 @@ class Context:
         _check(self.lib.rttda_spectral_radius(self.handle, int(n_iter), ctypes.byref(rho), ctypes.byref(bound)))
         self._leave()
         return rho.value, bound.value
+
+    def eigen_lowest(self, k: int, m_max: int = 0, max_iter: int = 200, tol: float = 1e-5, want_vectors: bool = True):
+        """The k lowest eigenpairs of A by block Davidson on the device (rttda_eigen_lowest):
+        (evals [k] numpy, residual norms [k] numpy, Ritz vectors torch [k, o, v] FP64 or None,
+        iterations).  m_max defaults to min(64, max(4k, 16), o*v)."""
+        import torch
+
+        k = int(k)
+        if not m_max:
+            m_max = min(64, max(4 * k, 16), self.o * self.v)
+        nbytes = ctypes.c_size_t()
+        _check(self.lib.rttda_eigen_workspace_bytes(self.handle, k, int(m_max), ctypes.byref(nbytes)))
+        work = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=self.device)
+        base = (work.data_ptr() + 255) // 256 * 256
+        evecs = torch.empty((k, self.o, self.v), dtype=torch.float64, device=self.device) if want_vectors else None
+        ev = (ctypes.c_double * k)()
+        rs = (ctypes.c_double * k)()
+        its = ctypes.c_int32()
+        self._enter()
+        try:
+            _check(self.lib.rttda_eigen_lowest(self.handle, k, int(m_max), int(max_iter), float(tol), base,
+                                               int(nbytes.value), ev, rs, _ptr(evecs) if evecs is not None else None,
+                                               ctypes.byref(its)))
+        finally:
+            self._leave()
+        return np.array(ev[:]), np.array(rs[:]), evecs, int(its.value)
+
+    def populations(self, evecs, c):
+        """|<U_I, c_r>|^2 for unit vectors evecs [k, o, v] and states c [nrhs, 2, o, v] (device,
+        FP64): numpy [nrhs, k] (rttda_populations)."""
+        import torch
+
+        k, nrhs = int(evecs.shape[0]), int(c.shape[0])
+        _dev_check(evecs, torch.float64, (k, self.o, self.v), "evecs")
+        _dev_check(c, torch.float64, (nrhs, 2, self.o, self.v), "c")
+        work = torch.empty(k * 2 * nrhs, dtype=torch.float64, device=self.device)
+        out = (ctypes.c_double * (k * nrhs))()
+        self._enter()
+        try:
+            _check(self.lib.rttda_populations(self.handle, k, _ptr(evecs), nrhs, _ptr(c), _ptr(work),
+                                              work.numel() * 8, out))
+        finally:
+            self._leave()
+        return np.array(out[:]).reshape(nrhs, k)
 
     def dipole_trace(self, dirs, c0, c, out=None):
         import torch
