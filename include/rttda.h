@@ -158,6 +158,14 @@ rttda_status rttda_propagate_sso(rttda_ctx *ctx, int32_t nrhs, const rttda_pulse
                                  int64_t step0, int64_t n_steps, double *c0, double *c, double *trace,
                                  double *norms);
 
+/* Time-correlation output for the next rttda_propagate or rttda_propagate_sso call on ctx (that
+ * call only; NULL clears it): corr (device [n_steps+1][nrhs][2] FP64, 16-byte aligned, caller-
+ * owned) receives R_r(t_n) = <X_r(start) | X_r(t_n)> (eq. time_correlation_function) as (real,
+ * imaginary) pairs for n = 0..n_steps, where X_r(start) is the state at the start of the call
+ * after its delta kicks (the paper's epsilon just after the pulse) and the inner product runs over
+ * the ground amplitude and both planes. */
+rttda_status rttda_set_correlation(rttda_ctx *ctx, double *corr);
+
 /* out[r] = Re <X_r | M_dr | X_r> (f64 [nrhs]) for states c0, c and host unit
  * vectors dir ([nrhs][3]): the observable behind every trace sample. */
 rttda_status rttda_dipole_trace(rttda_ctx *ctx, int32_t nrhs, const double *dir, const double *c0,

@@ -336,6 +336,35 @@ def propagate_sso(op: Operator, pulse, dt: float, n_steps: int, c0=1.0 + 0j, C=N
     return trace, c0, C
 
 
+def correlation(c0ref, Cref, c0, C) -> complex:
+    """Time-correlation function (eq. time_correlation_function): <X_ref | X>, the sum over the
+    ground amplitude and the amplitudes c_ia of conj(reference) times state."""
+    return complex(np.conj(complex(c0ref)) * complex(c0)
+                   + np.vdot(np.asarray(Cref, dtype=np.complex128).reshape(-1),
+                             np.asarray(C, dtype=np.complex128).reshape(-1)))
+
+
+def propagate_correlation(op: Operator, pulse, dt: float, n_steps: int, integrator: str = "rk4"):
+    """R(t_n) = <X(0+) | X(t_n)> for n = 0..n_steps from the ground state, X(0+) being the state
+    after the delta kick (direct route, RK4 or the split operator)."""
+    blocks = dipole_blocks(op, pulse.direction)
+    c0, C = 1.0 + 0j, np.zeros((op.o, op.v), dtype=np.complex128)
+    if pulse.kind == PULSE_DELTA:
+        c0, C = kick(blocks, pulse.e0, c0, C)
+    r0, R0 = c0, C.copy()
+    out = np.empty(n_steps + 1, dtype=np.complex128)
+    out[0] = correlation(r0, R0, c0, C)
+    q0, Q, p0, P = c0.real, C.real.copy(), c0.imag, C.imag.copy()
+    for n in range(n_steps):
+        if integrator == "rk4":
+            c0, C = rk4_step(op, blocks, pulse, dt, n, c0, C)
+        else:
+            q0, Q, p0, P = sso_step(op, blocks, pulse, dt, n, q0, Q, p0, P)
+            c0, C = complex(q0, p0), Q + 1j * P
+        out[n + 1] = correlation(r0, R0, c0, C)
+    return out
+
+
 def sso_mode_matrix(a: float) -> np.ndarray:
     """The SSO step acting on one field-free eigenmode (q, p) of frequency w, a = w dt."""
     return np.array([[1.0 - a * a / 2.0, a], [-a * (1.0 - a * a / 4.0), 1.0 - a * a / 2.0]])

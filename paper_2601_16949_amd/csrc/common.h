@@ -27,6 +27,7 @@ struct DevState {
   long long pad;
   double *trace;       // trace row of step0 ([n_steps+1][nrhs]) or NULL; set per call, so a
   double *norms;       // captured step graph stays valid across calls with new output arrays
+  double *corr;        // time-correlation output ([n_steps+1][nrhs][2]) or NULL, likewise
 };
 
 // Per-RHS scalar slots (f64): g_re, g_im, E(t_stage), spare.
@@ -118,7 +119,11 @@ hipError_t launch_dv_diag(hipStream_t s, int b_dtype, int o, int v, int nq, cons
                           const void *Bvv, double cx, const double *D, double *diag);
 hipError_t launch_kick(hipStream_t s, int R, int ov, const DevPulse *pulses, const double *F, const double *sc,
                        double *c, double *c0);
-hipError_t launch_set_state(hipStream_t s, DevState *st, long long step0, double *trace, double *norms);
+hipError_t launch_set_state(hipStream_t s, DevState *st, long long step0, double *trace, double *norms,
+                            double *corr);
+// time-correlation sample <Xref_r | X_r> (both planes and the ground amplitude) at the current step
+hipError_t launch_corr(hipStream_t s, int R, size_t ov, const double *X, const double *X0, const double *xref,
+                       const double *xref0, const DevState *st);
 
 // Exchange: K partials P[split][slice][o][v] = scale * sum_{Q in split} B_oo^Q X_slice B_vv^Q.
 // Large-o split-BF16 path (two batched GEMMs per chunk of Q through a W scratch buffer): used

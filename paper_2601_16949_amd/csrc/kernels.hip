@@ -711,13 +711,47 @@ __global__ void k_kick(int R, int ov, const DevPulse *__restrict__ pulses, const
   }
 }
 
-__global__ void k_set_state(DevState *st, long long step0, double *trace, double *norms) {
+__global__ void k_set_state(DevState *st, long long step0, double *trace, double *norms, double *corr) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     st->step = step0;
     st->step0 = step0;
     st->bad_step = -1;
     st->trace = trace;
     st->norms = norms;
+    st->corr = corr;
+  }
+}
+
+// Time-correlation function (eq. time_correlation_function): corr[k][r] = <Xref_r | X_r>
+// = conj(x0ref) x0 + sum_ia conj(Xref_ia) X_ia at k = step - step0, one block per RHS (the two
+// planes of length ov and the ground amplitude), a fixed-order block reduction.
+__global__ __launch_bounds__(256) void k_corr(int R, size_t ov, const double *__restrict__ X,
+                                              const double *__restrict__ X0, const double *__restrict__ xref,
+                                              const double *__restrict__ xref0, const DevState *__restrict__ st) {
+  __shared__ double sh[2][4];
+  double *corr = st->corr;
+  if (corr == nullptr) return;
+  const int r = blockIdx.x;
+  const double *x = X + (size_t)r * 2 * ov, *y = xref + (size_t)r * 2 * ov;
+  double re = 0.0, im = 0.0;
+  for (size_t e = threadIdx.x; e < ov; e += 256) {
+    const double a0 = y[e], a1 = y[ov + e], b0 = x[e], b1 = x[ov + e];
+    re += a0 * b0 + a1 * b1;
+    im += a0 * b1 - a1 * b0;
+  }
+  re = wave_sum(re);
+  im = wave_sum(im);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    sh[0][wave] = re;
+    sh[1][wave] = im;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double g0 = xref0[2 * r], g1 = xref0[2 * r + 1], c0 = X0[2 * r], c1 = X0[2 * r + 1];
+    const long long k = st->step - st->step0;
+    corr[(k * R + r) * 2] = (g0 * c0 + g1 * c1) + ((sh[0][0] + sh[0][1]) + (sh[0][2] + sh[0][3]));
+    corr[(k * R + r) * 2 + 1] = (g0 * c1 - g1 * c0) + ((sh[1][0] + sh[1][1]) + (sh[1][2] + sh[1][3]));
   }
 }
 
@@ -897,8 +931,15 @@ hipError_t launch_kick(hipStream_t s, int R, int ov, const DevPulse *pulses, con
   return hipGetLastError();
 }
 
-hipError_t launch_set_state(hipStream_t s, DevState *st, long long step0, double *trace, double *norms) {
-  hipLaunchKernelGGL(k_set_state, dim3(1), dim3(64), 0, s, st, step0, trace, norms);
+hipError_t launch_set_state(hipStream_t s, DevState *st, long long step0, double *trace, double *norms,
+                            double *corr) {
+  hipLaunchKernelGGL(k_set_state, dim3(1), dim3(64), 0, s, st, step0, trace, norms, corr);
+  return hipGetLastError();
+}
+
+hipError_t launch_corr(hipStream_t s, int R, size_t ov, const double *X, const double *X0, const double *xref,
+                       const double *xref0, const DevState *st) {
+  hipLaunchKernelGGL(k_corr, dim3(R), dim3(256), 0, s, R, ov, X, X0, xref, xref0, st);
   return hipGetLastError();
 }
 

@@ -61,6 +61,7 @@ inline bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 
 
 struct Layout {
   size_t D, moo, mov, mvv, xs64, xs0, acc, acc0, F, part, sc, x32, xhi, xlo, dvec, P, pulses, state, normref;
+  size_t xref, xref0;  // reference state of the time-correlation output (state at the start of a call)
   size_t scratch, scratch_bytes;  // W hi/lo of the large-o exchange path (0 bytes when it does not apply)
   size_t lz, lzp;                 // Lanczos guard: three FP64 vectors of ov, block partial sums
   size_t total;
@@ -100,6 +101,8 @@ Layout make_layout(int o, int v, int nq, int R, int prec) {
   L.pulses = take((size_t)R * sizeof(DevPulse));
   L.state = take(sizeof(DevState));
   L.normref = take((size_t)R * 8);
+  L.xref = take(ns * ov * 8);
+  L.xref0 = take(ns * 8);
   L.scratch_bytes = 0;
   if (prec == RTTDA_PREC_MIXED_BF16 && nq > 0 && o >= XGEMM_O_MIN && o <= 256 && o % 8 == 0 && v % 8 == 0) {
     const size_t per_q = (size_t)v * ns * o * 4;  // W hi + lo for one Q at the largest RHS count
@@ -180,7 +183,7 @@ struct GraphEntry {
   int nrhs = 0, steps = 0, mode = 0, integ = 0;
   double dt = 0;
   const void *c0 = nullptr, *c = nullptr;
-  bool trace = false, norms = false;
+  bool trace = false, norms = false, corr = false;
   hipGraphExec_t exec = nullptr;
 };
 
@@ -225,6 +228,7 @@ struct rttda_ctx {
   int sk = 0, sj = 0;
   int use_graph = 1, steps_per_graph = 8;
   int qchunk = 0;  // Q per chunk of the GEMM exchange path, 0 = as many as the scratch holds
+  double *corr_next = nullptr;  // time-correlation output of the next propagate call
   // host staging for pulses (pinned)
   DevPulse *h_pulses = nullptr;
   hipEvent_t upload_ev = nullptr;
@@ -257,6 +261,8 @@ struct rttda_ctx {
   DevPulse *pulses() const { return at<DevPulse>(L.pulses); }
   DevState *state() const { return at<DevState>(L.state); }
   double *normref() const { return at<double>(L.normref); }
+  double *xref() const { return at<double>(L.xref); }
+  double *xref0() const { return at<double>(L.xref0); }
 };
 
 namespace {
@@ -407,7 +413,7 @@ rttda_status enqueue_two_electron(rttda_ctx *ctx, int ns) {
 int nslab(const rttda_ctx *ctx) { return ctx->nq > 0 ? ctx->sj + ctx->sk : 0; }
 
 // One RK4 step (4 stages) on the context's stream.
-rttda_status enqueue_step(rttda_ctx *ctx, int nrhs, double dt, bool has_field, double *c0, double *c) {
+rttda_status enqueue_step(rttda_ctx *ctx, int nrhs, double dt, bool has_field, bool corr, double *c0, double *c) {
   hipStream_t s = ctx->stream;
   const int o = ctx->o, v = ctx->v;
   for (int stage = 0; stage < 4; ++stage) {
@@ -429,6 +435,7 @@ rttda_status enqueue_step(rttda_ctx *ctx, int nrhs, double dt, bool has_field, d
     if (stage == 3) mode |= SM_INC;
     HIP_TRY(launch_scalar(s, nrhs, ctx->L.nbf, stage, mode, dt, ctx->pulses(), ctx->state(), ctx->part(), ctx->sc(),
                           c0, ctx->acc0(), ctx->xs0(), nullptr, ctx->normref(), nullptr));
+    if (corr && stage == 0) HIP_TRY(launch_corr(s, nrhs, ctx->ov, c, c0, ctx->xref(), ctx->xref0(), ctx->state()));
     HIP_TRY(launch_epilogue(s, ctx->prec, nrhs, o, v, nslab(ctx), stage, EP_RK4, has_field ? 1 : 0, dt, ctx->D(),
                             ctx->P(), ctx->F(), ctx->sc(), Xin, c, ctx->acc(), ctx->xs64(), ctx->x32(), ctx->xhi(),
                             ctx->xlo(), nullptr));
@@ -439,7 +446,8 @@ rttda_status enqueue_step(rttda_ctx *ctx, int nrhs, double dt, bool has_field, d
 
 // One symplectic split-operator step (k_sso_update): trace sample at the step start, drift with
 // H(t_n + dt/2) p_h, kick with H(t_n + dt) q_{n+1}.  Field products only when a pulse is on.
-rttda_status enqueue_sso_step(rttda_ctx *ctx, int nrhs, double dt, bool has_field, double *c0, double *c) {
+rttda_status enqueue_sso_step(rttda_ctx *ctx, int nrhs, double dt, bool has_field, bool corr, double *c0,
+                              double *c) {
   hipStream_t s = ctx->stream;
   const int o = ctx->o, v = ctx->v;
   const bool pr = ctx->prof.on;
@@ -449,6 +457,7 @@ rttda_status enqueue_sso_step(rttda_ctx *ctx, int nrhs, double dt, bool has_fiel
   HIP_TRY(launch_field(s, c, c0, ctx->moo(), ctx->mov(), ctx->mvv(), o, v, nrhs, ctx->F(), ctx->part()));
   HIP_TRY(launch_scalar(s, nrhs, ctx->L.nbf, 0, SM_TRACE, dt, ctx->pulses(), ctx->state(), ctx->part(), ctx->sc(), c0,
                         ctx->acc0(), ctx->xs0(), nullptr, ctx->normref(), nullptr));
+  if (corr) HIP_TRY(launch_corr(s, nrhs, ctx->ov, c, c0, ctx->xref(), ctx->xref0(), ctx->state()));
   if (pr) HIP_TRY(ctx->prof.end(PC_FIELD, s));
   for (int half = 0; half < 2; ++half) {  // 0: drift (stage node 1/2), 1: kick (node 1)
     if ((st = enqueue_two_electron(ctx, nrhs)) != RTTDA_OK) return st;
@@ -705,7 +714,7 @@ rttda_status rttda_create(const rttda_desc *desc, rttda_ctx **out) {
   if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->upload_ev, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventRecord(ctx->upload_ev, ctx->stream);
   if (e == hipSuccess) e = launch_gaps(ctx->stream, desc->e_occ, desc->e_virt, ctx->o, ctx->v, ctx->D());
-  if (e == hipSuccess) e = launch_set_state(ctx->stream, ctx->state(), 0, nullptr, nullptr);
+  if (e == hipSuccess) e = launch_set_state(ctx->stream, ctx->state(), 0, nullptr, nullptr, nullptr);
   if (e != hipSuccess) {
     if (ctx->h_pulses) (void)hipHostFree(ctx->h_pulses);
     if (ctx->upload_ev) (void)hipEventDestroy(ctx->upload_ev);
@@ -876,10 +885,13 @@ enum : int { INTEG_RK4 = 0, INTEG_SSO = 1 };
 rttda_status propagate_impl(rttda_ctx *ctx, int32_t nrhs, const rttda_pulse *pulses, double dt, int64_t step0,
                             int64_t n_steps, double *c0, double *c, double *trace, double *norms, int integ) {
   if (!ctx) return fail(RTTDA_E_INVAL, "ctx is NULL");
+  double *corr = ctx->corr_next;  // applies to this call only
+  ctx->corr_next = nullptr;
   rttda_status st = check_nrhs(ctx, nrhs);
   if (st != RTTDA_OK) return st;
   if (!pulses || !c0 || !c) return fail(RTTDA_E_INVAL, "NULL argument (pulses, c0 and c are required)");
-  if (!aligned16(c0) || !aligned16(c) || (trace && !aligned16(trace)) || (norms && !aligned16(norms)))
+  if (!aligned16(c0) || !aligned16(c) || (trace && !aligned16(trace)) || (norms && !aligned16(norms)) ||
+      (corr && !aligned16(corr)))
     return fail(RTTDA_E_INVAL, "device arrays must be 16-byte aligned");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(RTTDA_E_INVAL, "dt must be finite and > 0 (got %g)", dt);
   if (step0 < 0 || n_steps < 0) return fail(RTTDA_E_INVAL, "step0 and n_steps must be >= 0");
@@ -901,12 +913,16 @@ rttda_status propagate_impl(rttda_ctx *ctx, int32_t nrhs, const rttda_pulse *pul
   hipStream_t hs = ctx->stream;
   const int o = ctx->o, v = ctx->v;
   HIP_TRY(launch_mu_blocks(hs, ctx->d.mu, ctx->pulses(), o, v, nrhs, ctx->moo(), ctx->mov(), ctx->mvv()));
-  HIP_TRY(launch_set_state(hs, ctx->state(), step0, trace, norms));
+  HIP_TRY(launch_set_state(hs, ctx->state(), step0, trace, norms, corr));
   if (has_kick && step0 == 0) {
     HIP_TRY(launch_field(hs, c, c0, ctx->moo(), ctx->mov(), ctx->mvv(), o, v, nrhs, ctx->F(), ctx->part()));
     HIP_TRY(launch_scalar(hs, nrhs, ctx->L.nbf, 0, 0, dt, ctx->pulses(), ctx->state(), ctx->part(), ctx->sc(), c0,
                           ctx->acc0(), ctx->xs0(), nullptr, ctx->normref(), nullptr));
     HIP_TRY(launch_kick(hs, nrhs, (int)ctx->ov, ctx->pulses(), ctx->F(), ctx->sc(), c, c0));
+  }
+  if (corr) {  // reference state of the time-correlation function: the state after the kicks
+    HIP_TRY(hipMemcpyAsync(ctx->xref(), c, (size_t)2 * nrhs * ctx->ov * sizeof(double), hipMemcpyDeviceToDevice, hs));
+    HIP_TRY(hipMemcpyAsync(ctx->xref0(), c0, (size_t)2 * nrhs * sizeof(double), hipMemcpyDeviceToDevice, hs));
   }
   if (integ == INTEG_SSO)
     st = enqueue_sso_start(ctx, nrhs, dt, has_field, c0, c);
@@ -914,8 +930,8 @@ rttda_status propagate_impl(rttda_ctx *ctx, int32_t nrhs, const rttda_pulse *pul
     st = to_stage_copy(ctx, c, nrhs);
   if (st != RTTDA_OK) return st;
   auto step = [&]() {
-    return integ == INTEG_SSO ? enqueue_sso_step(ctx, nrhs, dt, has_field, c0, c)
-                              : enqueue_step(ctx, nrhs, dt, has_field, c0, c);
+    return integ == INTEG_SSO ? enqueue_sso_step(ctx, nrhs, dt, has_field, corr != nullptr, c0, c)
+                              : enqueue_step(ctx, nrhs, dt, has_field, corr != nullptr, c0, c);
   };
 
   const int spg = ctx->steps_per_graph;
@@ -926,7 +942,7 @@ rttda_status propagate_impl(rttda_ctx *ctx, int32_t nrhs, const rttda_pulse *pul
     GraphEntry &G = ctx->graph;
     const bool hit = G.valid && G.nrhs == nrhs && G.steps == spg && G.mode == mode && G.integ == integ &&
                      G.dt == dt && G.c0 == c0 && G.c == c && G.trace == (trace != nullptr) &&
-                     G.norms == (norms != nullptr);
+                     G.norms == (norms != nullptr) && G.corr == (corr != nullptr);
     if (!hit) {
       drop_graph(ctx);
       hipGraph_t graph = nullptr;
@@ -954,6 +970,7 @@ rttda_status propagate_impl(rttda_ctx *ctx, int32_t nrhs, const rttda_pulse *pul
       G.c = c;
       G.trace = trace != nullptr;
       G.norms = norms != nullptr;
+      G.corr = corr != nullptr;
     }
     const int64_t reps = n_steps / spg;
     for (int64_t k = 0; k < reps; ++k) HIP_TRY(hipGraphLaunch(G.exec, hs));
@@ -965,6 +982,7 @@ rttda_status propagate_impl(rttda_ctx *ctx, int32_t nrhs, const rttda_pulse *pul
   HIP_TRY(launch_field(hs, c, c0, ctx->moo(), ctx->mov(), ctx->mvv(), o, v, nrhs, ctx->F(), ctx->part()));
   HIP_TRY(launch_scalar(hs, nrhs, ctx->L.nbf, 0, SM_TRACE, dt, ctx->pulses(), ctx->state(), ctx->part(), ctx->sc(),
                         c0, ctx->acc0(), ctx->xs0(), nullptr, ctx->normref(), nullptr));
+  if (corr) HIP_TRY(launch_corr(hs, nrhs, ctx->ov, c, c0, ctx->xref(), ctx->xref0(), ctx->state()));
   return RTTDA_OK;
 }
 
@@ -975,6 +993,12 @@ extern "C" {
 rttda_status rttda_propagate(rttda_ctx *ctx, int32_t nrhs, const rttda_pulse *pulses, double dt, int64_t step0,
                              int64_t n_steps, double *c0, double *c, double *trace, double *norms) {
   return propagate_impl(ctx, nrhs, pulses, dt, step0, n_steps, c0, c, trace, norms, INTEG_RK4);
+}
+
+rttda_status rttda_set_correlation(rttda_ctx *ctx, double *corr) {
+  if (!ctx) return fail(RTTDA_E_INVAL, "ctx is NULL");
+  ctx->corr_next = corr;
+  return RTTDA_OK;
 }
 
 rttda_status rttda_propagate_sso(rttda_ctx *ctx, int32_t nrhs, const rttda_pulse *pulses, double dt, int64_t step0,

@@ -85,6 +85,7 @@ EXPORTS = {
     "rttda_propagate_sso": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(CPulse),
                                            ctypes.c_double, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "rttda_set_correlation": (ctypes.c_int, [_VP, _VP]),
     "rttda_dipole_trace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "rttda_guard": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
@@ -276,9 +277,10 @@ class Context:
         return s0, s
 
     def propagate(self, pulses, dt: float, n_steps: int, c0, c, step0: int = 0, trace=None, norms=None,
-                  want_trace: bool = True, want_norms: bool = False, integrator: str = "rk4"):
+                  want_trace: bool = True, want_norms: bool = False, integrator: str = "rk4", corr=None):
         """Advance in place with RK4 (rttda_propagate) or the symplectic split operator
-        (integrator="sso", rttda_propagate_sso)."""
+        (integrator="sso", rttda_propagate_sso).  corr: a device FP64 tensor [n_steps+1, nrhs, 2]
+        that receives the time-correlation function (rttda_set_correlation), or None."""
         import torch
 
         if integrator not in ("rk4", "sso"):
@@ -293,10 +295,16 @@ class Context:
         if want_norms and norms is None:
             norms = torch.empty((n_steps + 1, nrhs), dtype=torch.float64, device=self.device)
         cp = make_pulses(pulses)
+        if corr is not None:
+            _dev_check(corr, torch.float64, (n_steps + 1, nrhs, 2), "corr")
         self._enter()
-        _check(fn(self.handle, nrhs, cp, float(dt), int(step0), int(n_steps), _ptr(c0), _ptr(c),
-                  _ptr(trace) if trace is not None else None, _ptr(norms) if norms is not None else None))
-        self._leave()
+        try:
+            if corr is not None:
+                _check(self.lib.rttda_set_correlation(self.handle, _ptr(corr)))
+            _check(fn(self.handle, nrhs, cp, float(dt), int(step0), int(n_steps), _ptr(c0), _ptr(c),
+                      _ptr(trace) if trace is not None else None, _ptr(norms) if norms is not None else None))
+        finally:
+            self._leave()
         if want_norms:
             return trace, norms
         return trace

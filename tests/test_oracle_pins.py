@@ -543,3 +543,34 @@ def test_sso_second_order_and_bounded_norm():
         half = len(dev) // 2
         assert dev.max() < 0.2 * dt * dt  # bounded at O(dt^2)
         assert dev[half:].max() < 1.5 * dev[:half].max() + 1e-15  # no drift
+
+
+def test_correlation_closed_forms():
+    """Time-correlation function (eq. time_correlation_function) of the oracle's direct route
+    against closed forms on the eigenmodes after a kick: R(0) is the kicked norm; field-free RK4
+    gives R(t_n) = sum_I |y_I|^2 r(-i w_I dt)^n with r the RK4 polynomial; the split operator
+    moves each mode (q, p) by its 2x2 mode matrix."""
+    shape = I.Shape(3, 5, 4, b_scale=0.05, storage="f32")
+    op = O.Operator.from_problem(I.make_problem(shape, 77))
+    pulse = I.kick_pulses(axes=[(0.0, 0.6, 0.8)], kappa=0.05)[0]
+    dt, n = 0.2, 60
+    er = O.EigenRoute(op)
+    blocks = O.dipole_blocks(op, pulse.direction)
+    c0, C = O.kick(blocks, pulse.e0, 1.0 + 0j, np.zeros((3, 5), complex))
+    y = er.to_eig(c0, C)
+    # RK4
+    got = O.propagate_correlation(op, pulse, dt, n, "rk4")
+    assert abs(got[0] - O.norm2(c0, C)) < 1e-15
+    amp = O.rk4_amplification(-1j * er.w * dt)
+    ref = np.array([np.sum(np.abs(y) ** 2 * amp ** k) for k in range(n + 1)])
+    assert np.max(np.abs(got - ref)) < 1e-12
+    # split operator: per mode [q, p] <- M(w dt) [q, p]
+    got = O.propagate_correlation(op, pulse, dt, n, "sso")
+    ref = np.empty(n + 1, complex)
+    qp = np.stack([y.real, y.imag])
+    for k in range(n + 1):
+        ref[k] = np.sum(np.conj(y) * (qp[0] + 1j * qp[1]))
+        qp = np.stack([O.sso_mode_matrix(w * dt) @ qp[:, i] for i, w in enumerate(er.w)], axis=1)
+    assert np.max(np.abs(got - ref)) < 1e-12
+    # a mistake in the conjugation order would flip the sign of the imaginary part
+    assert np.max(np.abs(got.imag)) > 1e-6
