@@ -76,8 +76,11 @@ typedef enum {
   RTTDA_PULSE_DELTA = 1,  /* first-order kick X <- X + i e0 M_d X applied when step0 == 0   */
   RTTDA_PULSE_CW = 2,     /* E(t) = e0 sin(omega t + phase)                                  */
   RTTDA_PULSE_GAUSS = 3,  /* E(t) = e0 exp(-(t-t0)^2 / 2 s^2) sin(omega (t-t0) + phase)      */
-  RTTDA_PULSE_CHIRP = 4   /* E(t) = e0 exp(-(t-t0)^2 / 2 s^2)                                */
+  RTTDA_PULSE_CHIRP = 4,  /* E(t) = e0 exp(-(t-t0)^2 / 2 s^2)                                */
                           /*        sin((omega + beta (t-t0)/2)(t-t0) + phase)               */
+  RTTDA_PULSE_DELTA_EXACT = 5 /* unitary kick X <- exp(i e0 M_d) X applied when step0 == 0, */
+                          /* by a Taylor series whose length follows from a bound on        */
+                          /* e0 |M_d|; RTTDA_E_UNSUPPORTED if e0 |M_d| exceeds about 12      */
 } rttda_pulse_kind;       /* s = fwhm / 2.35482; phase = pi/2 turns sin into cos             */
 
 typedef struct rttda_pulse {

@@ -39,7 +39,7 @@ import numpy as np
 SQRT2 = math.sqrt(2.0)
 FWHM_TO_SIGMA = 2.35482
 
-PULSE_NONE, PULSE_DELTA, PULSE_CW, PULSE_GAUSS, PULSE_CHIRP = 0, 1, 2, 3, 4
+PULSE_NONE, PULSE_DELTA, PULSE_CW, PULSE_GAUSS, PULSE_CHIRP, PULSE_DELTA_EXACT = 0, 1, 2, 3, 4, 5
 
 
 class Operator:
@@ -196,7 +196,7 @@ def dense_A_blas(op: Operator) -> np.ndarray:
 def field_value(p, t: float) -> float:
     """E(t) of a continuous pulse; 0 for the delta pulse (it acts as a kick at t = 0)."""
     kind = p.kind
-    if kind in (PULSE_NONE, PULSE_DELTA):
+    if kind in (PULSE_NONE, PULSE_DELTA, PULSE_DELTA_EXACT):
         return 0.0
     if kind == PULSE_CW:
         return p.e0 * math.sin(p.omega * t + p.phase)
@@ -223,6 +223,26 @@ def kick(blocks, kappa: float, c0, C):
     """First-order delta kick X <- X + i kappa M X."""
     g, F = apply_dipole(blocks, c0, C)
     return c0 + 1j * kappa * g, C + 1j * kappa * F
+
+
+def kick_exact(op: "Operator", direction, kappa: float, c0, C):
+    """Unitary delta kick X <- exp(i kappa M) X: the exact propagator of a delta field of area
+    kappa, from the dense CSF dipole and the matrix exponential (small inputs)."""
+    import scipy.linalg
+
+    M = dense_dipole_csf_fast(op, direction)
+    x = np.concatenate([[complex(c0)], np.asarray(C, dtype=np.complex128).reshape(-1)])
+    y = scipy.linalg.expm(1j * kappa * M) @ x
+    return y[0], y[1:].reshape(op.o, op.v)
+
+
+def apply_kick(op: "Operator", blocks, pulse, c0, C):
+    """The kick of a delta pulse (first order or exact); other pulses leave the state alone."""
+    if pulse.kind == PULSE_DELTA:
+        return kick(blocks, pulse.e0, c0, C)
+    if pulse.kind == PULSE_DELTA_EXACT:
+        return kick_exact(op, pulse.direction, pulse.e0, c0, C)
+    return c0, C
 
 
 def dipole_expectation(blocks, c0, C) -> float:
@@ -274,8 +294,8 @@ def propagate(op: Operator, pulse, dt: float, n_steps: int, c0=1.0 + 0j, C=None,
     c0 = complex(c0)
     C = np.array(C, dtype=np.complex128)
     blocks = dipole_blocks(op, pulse.direction)
-    if pulse.kind == PULSE_DELTA and step0 == 0:
-        c0, C = kick(blocks, pulse.e0, c0, C)
+    if step0 == 0:
+        c0, C = apply_kick(op, blocks, pulse, c0, C)
     trace = np.empty(n_steps + 1)
     norms = np.empty(n_steps + 1)
     trace[0] = dipole_expectation(blocks, c0, C)
@@ -319,8 +339,8 @@ def propagate_sso(op: Operator, pulse, dt: float, n_steps: int, c0=1.0 + 0j, C=N
     c0 = complex(c0)
     C = np.array(C, dtype=np.complex128)
     blocks = dipole_blocks(op, pulse.direction)
-    if pulse.kind == PULSE_DELTA and step0 == 0:
-        c0, C = kick(blocks, pulse.e0, c0, C)
+    if step0 == 0:
+        c0, C = apply_kick(op, blocks, pulse, c0, C)
     q0, Q, p0, P = c0.real, C.real.copy(), c0.imag, C.imag.copy()
     trace = np.empty(n_steps + 1)
     norms = np.empty(n_steps + 1)
@@ -348,9 +368,7 @@ def propagate_correlation(op: Operator, pulse, dt: float, n_steps: int, integrat
     """R(t_n) = <X(0+) | X(t_n)> for n = 0..n_steps from the ground state, X(0+) being the state
     after the delta kick (direct route, RK4 or the split operator)."""
     blocks = dipole_blocks(op, pulse.direction)
-    c0, C = 1.0 + 0j, np.zeros((op.o, op.v), dtype=np.complex128)
-    if pulse.kind == PULSE_DELTA:
-        c0, C = kick(blocks, pulse.e0, c0, C)
+    c0, C = apply_kick(op, blocks, pulse, 1.0 + 0j, np.zeros((op.o, op.v), dtype=np.complex128))
     r0, R0 = c0, C.copy()
     out = np.empty(n_steps + 1, dtype=np.complex128)
     out[0] = correlation(r0, R0, c0, C)
@@ -427,8 +445,8 @@ class EigenRoute:
         if C is None:
             C = np.zeros((self.op.o, self.op.v), dtype=np.complex128)
         blocks = dipole_blocks(self.op, pulse.direction)
-        if pulse.kind == PULSE_DELTA:
-            c0, C = kick(blocks, pulse.e0, complex(c0), np.asarray(C, dtype=np.complex128))
+        if pulse.kind in (PULSE_DELTA, PULSE_DELTA_EXACT):
+            c0, C = apply_kick(self.op, blocks, pulse, complex(c0), np.asarray(C, dtype=np.complex128))
         elif pulse.kind != PULSE_NONE:
             raise ValueError("field-free route takes only delta or no pulse")
         y = self.to_eig(c0, C)
@@ -456,8 +474,7 @@ class EigenRoute:
             C = np.zeros((self.op.o, self.op.v), dtype=np.complex128)
         blocks = dipole_blocks(self.op, pulse.direction)
         c0, C = complex(c0), np.asarray(C, dtype=np.complex128)
-        if pulse.kind == PULSE_DELTA:
-            c0, C = kick(blocks, pulse.e0, c0, C)
+        c0, C = apply_kick(self.op, blocks, pulse, c0, C)
         y = self.to_eig(c0, C)
         Me = self.dipole_eig(pulse.direction)
         w = self.w

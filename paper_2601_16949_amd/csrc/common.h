@@ -119,6 +119,8 @@ hipError_t launch_dv_diag(hipStream_t s, int b_dtype, int o, int v, int nq, cons
                           const void *Bvv, double cx, const double *D, double *diag);
 hipError_t launch_kick(hipStream_t s, int R, int ov, const DevPulse *pulses, const double *F, const double *sc,
                        double *c, double *c0);
+hipError_t launch_kick_term(hipStream_t s, int R, int ov, const DevPulse *pulses, const double *F, const double *sc,
+                            double inv_j, double *T, double *T0, double *c, double *c0);
 hipError_t launch_set_state(hipStream_t s, DevState *st, long long step0, double *trace, double *norms,
                             double *corr);
 // time-correlation sample <Xref_r | X_r> (both planes and the ground amplitude) at the current step

@@ -711,6 +711,35 @@ __global__ void k_kick(int R, int ov, const DevPulse *__restrict__ pulses, const
   }
 }
 
+// One Taylor term of the unitary kick exp(i kappa M) X for the RHS with PULSE_DELTA_EXACT:
+// given F = (M T)_C and g = (M T)_0 of the previous term T, the next term is (i kappa / j) M T;
+// it replaces T and is added to the state (c, c0).
+__global__ void k_kick_term(int R, int ov, const DevPulse *__restrict__ pulses, const double *__restrict__ F,
+                            const double *__restrict__ sc, double inv_j, double *__restrict__ T,
+                            double *__restrict__ T0, double *__restrict__ c, double *__restrict__ c0) {
+  const size_t total = (size_t)R * ov;
+  const size_t gid = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  for (size_t e = gid; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const size_t r = e / ov, ia = e - r * ov;
+    if (pulses[r].kind != RTTDA_PULSE_DELTA_EXACT) continue;
+    const double s = pulses[r].e0 * inv_j;
+    const size_t i0 = r * 2 * ov + ia, i1 = i0 + ov;
+    const double t0 = -s * F[i1], t1 = s * F[i0];
+    T[i0] = t0;
+    T[i1] = t1;
+    c[i0] += t0;
+    c[i1] += t1;
+  }
+  if (gid < (size_t)R && pulses[gid].kind == RTTDA_PULSE_DELTA_EXACT) {
+    const double s = pulses[gid].e0 * inv_j;
+    const double t0 = -s * sc[gid * SC_STRIDE + SC_GIM], t1 = s * sc[gid * SC_STRIDE + SC_GRE];
+    T0[2 * gid] = t0;
+    T0[2 * gid + 1] = t1;
+    c0[2 * gid] += t0;
+    c0[2 * gid + 1] += t1;
+  }
+}
+
 __global__ void k_set_state(DevState *st, long long step0, double *trace, double *norms, double *corr) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     st->step = step0;
@@ -928,6 +957,13 @@ hipError_t launch_kick(hipStream_t s, int R, int ov, const DevPulse *pulses, con
                        double *c, double *c0) {
   const long long n = (long long)R * ov;
   hipLaunchKernelGGL(k_kick, dim3(grid_for(n)), dim3(256), 0, s, R, ov, pulses, F, sc, c, c0);
+  return hipGetLastError();
+}
+
+hipError_t launch_kick_term(hipStream_t s, int R, int ov, const DevPulse *pulses, const double *F, const double *sc,
+                            double inv_j, double *T, double *T0, double *c, double *c0) {
+  const long long n = (long long)R * ov;
+  hipLaunchKernelGGL(k_kick_term, dim3(grid_for(n)), dim3(256), 0, s, R, ov, pulses, F, sc, inv_j, T, T0, c, c0);
   return hipGetLastError();
 }
 

@@ -882,6 +882,54 @@ namespace {
 
 enum : int { INTEG_RK4 = 0, INTEG_SSO = 1 };
 
+// Unitary kick exp(i kappa M) X for the RHS with PULSE_DELTA_EXACT, as the Taylor series
+// sum_j (i kappa M)^j X / j!.  |M X| <= (|mu_oo|_F + |mu_vv|_F + 2 sqrt2 |mu_ov|_F) |X| = b |X|,
+// so J terms leave at most x^(J+1)/(J+1)! e^x of |X| with x = kappa b; J is the smallest with
+// that below 1e-17.  The terms live in the stage buffers (xs64, xs0).
+rttda_status exact_kick(rttda_ctx *ctx, int nrhs, const rttda_pulse *pulses, double *c0, double *c) {
+  hipStream_t hs = ctx->stream;
+  const int o = ctx->o, v = ctx->v;
+  const long long ov = (long long)ctx->ov;
+  double x = 0.0;
+  std::vector<double> hp;
+  for (int r = 0; r < nrhs; ++r) {
+    if (pulses[r].kind != RTTDA_PULSE_DELTA_EXACT) continue;
+    const double *blk[3] = {ctx->moo() + (size_t)r * o * o, ctx->mov() + (size_t)r * ov, ctx->mvv() + (size_t)r * v * v};
+    const long long len[3] = {(long long)o * o, ov, (long long)v * v};
+    double fro[3];
+    for (int b = 0; b < 3; ++b) {
+      HIP_TRY(launch_dv_norm2(hs, len[b], blk[b], ctx->lzp()));
+      const int nb = dv_blocks(len[b]);
+      hp.resize(nb);
+      HIP_TRY(hipMemcpyAsync(hp.data(), ctx->lzp(), nb * sizeof(double), hipMemcpyDeviceToHost, hs));
+      HIP_TRY(hipStreamSynchronize(hs));
+      double t = 0.0;
+      for (double y : hp) t += y;
+      fro[b] = std::sqrt(t);
+    }
+    x = std::max(x, std::fabs(pulses[r].e0) * (fro[0] + fro[2] + 2.0 * std::sqrt(2.0) * fro[1]));
+  }
+  int J = 0;
+  double term = std::exp(x);  // x^(J+1)/(J+1)! e^x, updated as J grows
+  for (J = 0; J < 200; ++J) {
+    term *= x / (J + 1);
+    if (term <= 1e-17) break;
+  }
+  if (J > 120)
+    return fail(RTTDA_E_UNSUPPORTED, "exact kick: kappa |M| bound %.3g too large for the series (use a smaller kick)",
+                x);
+  double *T = ctx->xs64(), *T0 = ctx->xs0();
+  HIP_TRY(hipMemcpyAsync(T, c, (size_t)2 * nrhs * ov * sizeof(double), hipMemcpyDeviceToDevice, hs));
+  HIP_TRY(hipMemcpyAsync(T0, c0, (size_t)2 * nrhs * sizeof(double), hipMemcpyDeviceToDevice, hs));
+  for (int j = 1; j <= J; ++j) {
+    HIP_TRY(launch_field(hs, T, T0, ctx->moo(), ctx->mov(), ctx->mvv(), o, v, nrhs, ctx->F(), ctx->part()));
+    HIP_TRY(launch_scalar(hs, nrhs, ctx->L.nbf, 0, 0, 0.0, ctx->pulses(), ctx->state(), ctx->part(), ctx->sc(), T0,
+                          ctx->acc0(), ctx->xs0(), nullptr, ctx->normref(), nullptr));
+    HIP_TRY(launch_kick_term(hs, nrhs, (int)ov, ctx->pulses(), ctx->F(), ctx->sc(), 1.0 / j, T, T0, c, c0));
+  }
+  return RTTDA_OK;
+}
+
 rttda_status propagate_impl(rttda_ctx *ctx, int32_t nrhs, const rttda_pulse *pulses, double dt, int64_t step0,
                             int64_t n_steps, double *c0, double *c, double *trace, double *norms, int integ) {
   if (!ctx) return fail(RTTDA_E_INVAL, "ctx is NULL");
@@ -895,10 +943,10 @@ rttda_status propagate_impl(rttda_ctx *ctx, int32_t nrhs, const rttda_pulse *pul
     return fail(RTTDA_E_INVAL, "device arrays must be 16-byte aligned");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(RTTDA_E_INVAL, "dt must be finite and > 0 (got %g)", dt);
   if (step0 < 0 || n_steps < 0) return fail(RTTDA_E_INVAL, "step0 and n_steps must be >= 0");
-  bool has_field = false, has_kick = false;
+  bool has_field = false, has_kick = false, has_exact = false;
   for (int r = 0; r < nrhs; ++r) {
     const rttda_pulse &p = pulses[r];
-    if (p.kind < RTTDA_PULSE_NONE || p.kind > RTTDA_PULSE_CHIRP) return fail(RTTDA_E_INVAL, "pulse %d: bad kind", r);
+    if (p.kind < RTTDA_PULSE_NONE || p.kind > RTTDA_PULSE_DELTA_EXACT) return fail(RTTDA_E_INVAL, "pulse %d: bad kind", r);
     if (p.reserved != 0) return fail(RTTDA_E_INVAL, "pulse %d: reserved field must be 0", r);
     const double vals[] = {p.e0, p.omega, p.t0, p.fwhm, p.beta, p.phase};
     for (double x : vals)
@@ -908,6 +956,7 @@ rttda_status propagate_impl(rttda_ctx *ctx, int32_t nrhs, const rttda_pulse *pul
     if ((st = check_dirs(p.dir, 1)) != RTTDA_OK) return fail(RTTDA_E_INVAL, "pulse %d: dir is not a unit vector", r);
     has_field |= (p.kind == RTTDA_PULSE_CW || p.kind == RTTDA_PULSE_GAUSS || p.kind == RTTDA_PULSE_CHIRP);
     has_kick |= (p.kind == RTTDA_PULSE_DELTA && p.e0 != 0.0);
+    has_exact |= (p.kind == RTTDA_PULSE_DELTA_EXACT && p.e0 != 0.0);
   }
   if ((st = upload_pulses(ctx, reinterpret_cast<const DevPulse *>(pulses), nrhs)) != RTTDA_OK) return st;
   hipStream_t hs = ctx->stream;
@@ -920,6 +969,7 @@ rttda_status propagate_impl(rttda_ctx *ctx, int32_t nrhs, const rttda_pulse *pul
                           ctx->acc0(), ctx->xs0(), nullptr, ctx->normref(), nullptr));
     HIP_TRY(launch_kick(hs, nrhs, (int)ctx->ov, ctx->pulses(), ctx->F(), ctx->sc(), c, c0));
   }
+  if (has_exact && step0 == 0 && (st = exact_kick(ctx, nrhs, pulses, c0, c)) != RTTDA_OK) return st;
   if (corr) {  // reference state of the time-correlation function: the state after the kicks
     HIP_TRY(hipMemcpyAsync(ctx->xref(), c, (size_t)2 * nrhs * ctx->ov * sizeof(double), hipMemcpyDeviceToDevice, hs));
     HIP_TRY(hipMemcpyAsync(ctx->xref0(), c0, (size_t)2 * nrhs * sizeof(double), hipMemcpyDeviceToDevice, hs));

@@ -35,14 +35,15 @@ SEED_BASE = 16949
 TENSOR_E_OCC, TENSOR_E_VIRT, TENSOR_B_OV, TENSOR_B_OO, TENSOR_B_VV, TENSOR_MU, TENSOR_PULSE = range(7)
 
 # Pulse kinds (the four pulses of the paper's pulse equations, plus none).
-PULSE_NONE, PULSE_DELTA, PULSE_CW, PULSE_GAUSS, PULSE_CHIRP = 0, 1, 2, 3, 4
+PULSE_NONE, PULSE_DELTA, PULSE_CW, PULSE_GAUSS, PULSE_CHIRP, PULSE_DELTA_EXACT = 0, 1, 2, 3, 4, 5
 
 
 @dataclass
 class Pulse:
     """One right-hand side's external field.
 
-    kind:  PULSE_* code.  For PULSE_DELTA, e0 is the kick strength kappa.
+    kind:  PULSE_* code.  For PULSE_DELTA (first-order kick) and PULSE_DELTA_EXACT (unitary
+           kick exp(i kappa M)), e0 is the kick strength kappa.
     e0:    peak field (au).  omega: carrier (Ha).  t0: envelope centre (au).
     fwhm:  envelope full width at half maximum (au), sigma = fwhm / 2.35482.
     beta:  chirp rate (Ha/au).  phase: carrier phase (rad; pi/2 turns sin into cos).
@@ -217,8 +218,8 @@ class Workload:
     precision: str = "fp32"  # "fp32" | "mixed"
 
 
-def kick_pulses(axes=AXES, kappa: float = KAPPA) -> List[Pulse]:
-    return [Pulse(kind=PULSE_DELTA, e0=kappa, direction=tuple(a)) for a in axes]
+def kick_pulses(axes=AXES, kappa: float = KAPPA, exact: bool = False) -> List[Pulse]:
+    return [Pulse(kind=PULSE_DELTA_EXACT if exact else PULSE_DELTA, e0=kappa, direction=tuple(a)) for a in axes]
 
 
 def gauss_cos_scan(omega_low: float, e0: float, n: int = 64, fwhm: float = 400.0, t0: float = 400.0,

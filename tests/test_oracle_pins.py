@@ -574,3 +574,29 @@ def test_correlation_closed_forms():
     assert np.max(np.abs(got - ref)) < 1e-12
     # a mistake in the conjugation order would flip the sign of the imaginary part
     assert np.max(np.abs(got.imag)) > 1e-6
+
+
+def test_exact_kick_unitary_second_order_and_group():
+    """Unitary kick exp(i kappa M) X: the norm is kept; against the first-order kick (a separate
+    route through the factorised dipole) the difference is -kappa^2/2 M^2 X up to O(kappa^3);
+    two kicks compose to one of the summed strength."""
+    shape = I.Shape(3, 5, 4, b_scale=0.05, storage="f32")
+    op = O.Operator.from_problem(I.make_problem(shape, 78))
+    d = (0.0, 0.6, 0.8)
+    blocks = O.dipole_blocks(op, d)
+    c0, C = I.random_state(3, 5, 1, seed=5)
+    c0, C = complex(c0[0]), np.asarray(C[0], complex)
+    n0 = O.norm2(c0, C)
+    a0, A = O.kick_exact(op, d, 0.3, c0, C)
+    assert abs(O.norm2(a0, A) - n0) < 1e-13 * n0
+    errs = []
+    for kap in (0.02, 0.01):
+        e0, E = O.kick_exact(op, d, kap, c0, C)
+        f0, F = O.kick(blocks, kap, c0, C)
+        g0, G = O.apply_dipole(blocks, c0, C)
+        h0, H = O.apply_dipole(blocks, g0, G)
+        r0, R = e0 - (f0 - 0.5 * kap ** 2 * h0), E - (F - 0.5 * kap ** 2 * H)
+        errs.append(np.sqrt(abs(r0) ** 2 + np.sum(np.abs(R) ** 2)))
+    assert 6.5 < errs[0] / errs[1] < 9.5  # third order
+    b0, B = O.kick_exact(op, d, 0.1, *O.kick_exact(op, d, 0.2, c0, C))
+    assert abs(b0 - a0) < 1e-13 and np.max(np.abs(B - A)) < 1e-13
