@@ -169,6 +169,13 @@ rttda_status rttda_propagate_sso(rttda_ctx *ctx, int32_t nrhs, const rttda_pulse
  * the ground amplitude and both planes. */
 rttda_status rttda_set_correlation(rttda_ctx *ctx, double *corr);
 
+/* Eigenstate populations as an output of the next rttda_propagate or rttda_propagate_sso call
+ * on ctx (that call only; pops NULL clears it): pops (device [n_steps+1][nrhs][k] FP64, 16-byte
+ * aligned) receives P_rI(t_n) = |<U_I, X_r(t_n)>|^2 (eq. populations) for the k real unit
+ * vectors evecs (device [k][o][v] FP64, e.g. from rttda_eigen_lowest; 1 <= k <= 64), at every
+ * step of the call, alongside the trace.  Both arrays must stay valid until the call's work ends. */
+rttda_status rttda_set_populations(rttda_ctx *ctx, int32_t k, const double *evecs, double *pops);
+
 /* out[r] = Re <X_r | M_dr | X_r> (f64 [nrhs]) for states c0, c and host unit
  * vectors dir ([nrhs][3]): the observable behind every trace sample. */
 rttda_status rttda_dipole_trace(rttda_ctx *ctx, int32_t nrhs, const double *dir, const double *c0,

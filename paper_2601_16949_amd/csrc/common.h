@@ -28,7 +28,11 @@ struct DevState {
   double *trace;       // trace row of step0 ([n_steps+1][nrhs]) or NULL; set per call, so a
   double *norms;       // captured step graph stays valid across calls with new output arrays
   double *corr;        // time-correlation output ([n_steps+1][nrhs][2]) or NULL, likewise
+  double *pops;        // eigenstate populations output ([n_steps+1][nrhs][popk]) or NULL, likewise
+  const double *popU;  // the popk unit vectors ([popk][o][v]) the states are projected on
+  long long popk;
 };
+constexpr int POP_MAX = 64;  // eigenstates per populations output
 
 // Per-RHS scalar slots (f64): g_re, g_im, E(t_stage), spare.
 constexpr int SC_STRIDE = 4;
@@ -122,7 +126,9 @@ hipError_t launch_kick(hipStream_t s, int R, int ov, const DevPulse *pulses, con
 hipError_t launch_kick_term(hipStream_t s, int R, int ov, const DevPulse *pulses, const double *F, const double *sc,
                             double inv_j, double *T, double *T0, double *c, double *c0);
 hipError_t launch_set_state(hipStream_t s, DevState *st, long long step0, double *trace, double *norms,
-                            double *corr);
+                            double *corr, double *pops, const double *popU, int popk);
+// eigenstate populations |<U_I | X_r>|^2 at the current step (no-op unless st->pops is set)
+hipError_t launch_pop(hipStream_t s, int R, size_t ov, const double *X, const DevState *st);
 // time-correlation sample <Xref_r | X_r> (both planes and the ground amplitude) at the current step
 hipError_t launch_corr(hipStream_t s, int R, size_t ov, const double *X, const double *X0, const double *xref,
                        const double *xref0, const DevState *st);

@@ -740,7 +740,8 @@ __global__ void k_kick_term(int R, int ov, const DevPulse *__restrict__ pulses, 
   }
 }
 
-__global__ void k_set_state(DevState *st, long long step0, double *trace, double *norms, double *corr) {
+__global__ void k_set_state(DevState *st, long long step0, double *trace, double *norms, double *corr, double *pops,
+                            const double *popU, int popk) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     st->step = step0;
     st->step0 = step0;
@@ -748,6 +749,39 @@ __global__ void k_set_state(DevState *st, long long step0, double *trace, double
     st->trace = trace;
     st->norms = norms;
     st->corr = corr;
+    st->pops = pops;
+    st->popU = popU;
+    st->popk = popk;
+  }
+}
+
+// Eigenstate populations (eq. populations) at k = step - step0: pops[k][r][I] = |<U_I, X_r>|^2
+// with real unit vectors U_I over the amplitudes c_ia (both planes); one block per (RHS, state),
+// blocks past the state count return at once, a fixed-order block reduction.
+__global__ __launch_bounds__(256) void k_pop(int R, size_t ov, const double *__restrict__ X,
+                                             const DevState *__restrict__ st) {
+  __shared__ double sh[2][4];
+  double *pops = st->pops;
+  const int K = (int)st->popk, r = blockIdx.x, I = blockIdx.y;
+  if (pops == nullptr || I >= K) return;
+  const double *u = st->popU + (size_t)I * ov, *x = X + (size_t)r * 2 * ov;
+  double re = 0.0, im = 0.0;
+  for (size_t e = threadIdx.x; e < ov; e += 256) {
+    re += u[e] * x[e];
+    im += u[e] * x[ov + e];
+  }
+  re = wave_sum(re);
+  im = wave_sum(im);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    sh[0][wave] = re;
+    sh[1][wave] = im;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double a = (sh[0][0] + sh[0][1]) + (sh[0][2] + sh[0][3]), b = (sh[1][0] + sh[1][1]) + (sh[1][2] + sh[1][3]);
+    const long long k = st->step - st->step0;
+    pops[(k * R + r) * K + I] = a * a + b * b;
   }
 }
 
@@ -968,8 +1002,13 @@ hipError_t launch_kick_term(hipStream_t s, int R, int ov, const DevPulse *pulses
 }
 
 hipError_t launch_set_state(hipStream_t s, DevState *st, long long step0, double *trace, double *norms,
-                            double *corr) {
-  hipLaunchKernelGGL(k_set_state, dim3(1), dim3(64), 0, s, st, step0, trace, norms, corr);
+                            double *corr, double *pops, const double *popU, int popk) {
+  hipLaunchKernelGGL(k_set_state, dim3(1), dim3(64), 0, s, st, step0, trace, norms, corr, pops, popU, popk);
+  return hipGetLastError();
+}
+
+hipError_t launch_pop(hipStream_t s, int R, size_t ov, const double *X, const DevState *st) {
+  hipLaunchKernelGGL(k_pop, dim3(R, POP_MAX), dim3(256), 0, s, R, ov, X, st);
   return hipGetLastError();
 }
 

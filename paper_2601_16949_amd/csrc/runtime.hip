@@ -183,7 +183,7 @@ struct GraphEntry {
   int nrhs = 0, steps = 0, mode = 0, integ = 0;
   double dt = 0;
   const void *c0 = nullptr, *c = nullptr;
-  bool trace = false, norms = false, corr = false;
+  bool trace = false, norms = false, corr = false, pops = false;
   hipGraphExec_t exec = nullptr;
 };
 
@@ -229,6 +229,9 @@ struct rttda_ctx {
   int use_graph = 1, steps_per_graph = 8;
   int qchunk = 0;  // Q per chunk of the GEMM exchange path, 0 = as many as the scratch holds
   double *corr_next = nullptr;  // time-correlation output of the next propagate call
+  double *pops_next = nullptr;  // populations output of the next propagate call, its vectors and count
+  const double *popU_next = nullptr;
+  int popk_next = 0;
   // host staging for pulses (pinned)
   DevPulse *h_pulses = nullptr;
   hipEvent_t upload_ev = nullptr;
@@ -413,7 +416,8 @@ rttda_status enqueue_two_electron(rttda_ctx *ctx, int ns) {
 int nslab(const rttda_ctx *ctx) { return ctx->nq > 0 ? ctx->sj + ctx->sk : 0; }
 
 // One RK4 step (4 stages) on the context's stream.
-rttda_status enqueue_step(rttda_ctx *ctx, int nrhs, double dt, bool has_field, bool corr, double *c0, double *c) {
+rttda_status enqueue_step(rttda_ctx *ctx, int nrhs, double dt, bool has_field, bool corr, bool pops, double *c0,
+                          double *c) {
   hipStream_t s = ctx->stream;
   const int o = ctx->o, v = ctx->v;
   for (int stage = 0; stage < 4; ++stage) {
@@ -436,6 +440,7 @@ rttda_status enqueue_step(rttda_ctx *ctx, int nrhs, double dt, bool has_field, b
     HIP_TRY(launch_scalar(s, nrhs, ctx->L.nbf, stage, mode, dt, ctx->pulses(), ctx->state(), ctx->part(), ctx->sc(),
                           c0, ctx->acc0(), ctx->xs0(), nullptr, ctx->normref(), nullptr));
     if (corr && stage == 0) HIP_TRY(launch_corr(s, nrhs, ctx->ov, c, c0, ctx->xref(), ctx->xref0(), ctx->state()));
+    if (pops && stage == 0) HIP_TRY(launch_pop(s, nrhs, ctx->ov, c, ctx->state()));
     HIP_TRY(launch_epilogue(s, ctx->prec, nrhs, o, v, nslab(ctx), stage, EP_RK4, has_field ? 1 : 0, dt, ctx->D(),
                             ctx->P(), ctx->F(), ctx->sc(), Xin, c, ctx->acc(), ctx->xs64(), ctx->x32(), ctx->xhi(),
                             ctx->xlo(), nullptr));
@@ -446,7 +451,7 @@ rttda_status enqueue_step(rttda_ctx *ctx, int nrhs, double dt, bool has_field, b
 
 // One symplectic split-operator step (k_sso_update): trace sample at the step start, drift with
 // H(t_n + dt/2) p_h, kick with H(t_n + dt) q_{n+1}.  Field products only when a pulse is on.
-rttda_status enqueue_sso_step(rttda_ctx *ctx, int nrhs, double dt, bool has_field, bool corr, double *c0,
+rttda_status enqueue_sso_step(rttda_ctx *ctx, int nrhs, double dt, bool has_field, bool corr, bool pops, double *c0,
                               double *c) {
   hipStream_t s = ctx->stream;
   const int o = ctx->o, v = ctx->v;
@@ -458,6 +463,7 @@ rttda_status enqueue_sso_step(rttda_ctx *ctx, int nrhs, double dt, bool has_fiel
   HIP_TRY(launch_scalar(s, nrhs, ctx->L.nbf, 0, SM_TRACE, dt, ctx->pulses(), ctx->state(), ctx->part(), ctx->sc(), c0,
                         ctx->acc0(), ctx->xs0(), nullptr, ctx->normref(), nullptr));
   if (corr) HIP_TRY(launch_corr(s, nrhs, ctx->ov, c, c0, ctx->xref(), ctx->xref0(), ctx->state()));
+  if (pops) HIP_TRY(launch_pop(s, nrhs, ctx->ov, c, ctx->state()));
   if (pr) HIP_TRY(ctx->prof.end(PC_FIELD, s));
   for (int half = 0; half < 2; ++half) {  // 0: drift (stage node 1/2), 1: kick (node 1)
     if ((st = enqueue_two_electron(ctx, nrhs)) != RTTDA_OK) return st;
@@ -714,7 +720,7 @@ rttda_status rttda_create(const rttda_desc *desc, rttda_ctx **out) {
   if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->upload_ev, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventRecord(ctx->upload_ev, ctx->stream);
   if (e == hipSuccess) e = launch_gaps(ctx->stream, desc->e_occ, desc->e_virt, ctx->o, ctx->v, ctx->D());
-  if (e == hipSuccess) e = launch_set_state(ctx->stream, ctx->state(), 0, nullptr, nullptr, nullptr);
+  if (e == hipSuccess) e = launch_set_state(ctx->stream, ctx->state(), 0, nullptr, nullptr, nullptr, nullptr, nullptr, 0);
   if (e != hipSuccess) {
     if (ctx->h_pulses) (void)hipHostFree(ctx->h_pulses);
     if (ctx->upload_ev) (void)hipEventDestroy(ctx->upload_ev);
@@ -935,11 +941,17 @@ rttda_status propagate_impl(rttda_ctx *ctx, int32_t nrhs, const rttda_pulse *pul
   if (!ctx) return fail(RTTDA_E_INVAL, "ctx is NULL");
   double *corr = ctx->corr_next;  // applies to this call only
   ctx->corr_next = nullptr;
+  double *pops = ctx->pops_next;
+  const double *popU = ctx->popU_next;
+  const int popk = ctx->popk_next;
+  ctx->pops_next = nullptr;
+  ctx->popU_next = nullptr;
+  ctx->popk_next = 0;
   rttda_status st = check_nrhs(ctx, nrhs);
   if (st != RTTDA_OK) return st;
   if (!pulses || !c0 || !c) return fail(RTTDA_E_INVAL, "NULL argument (pulses, c0 and c are required)");
   if (!aligned16(c0) || !aligned16(c) || (trace && !aligned16(trace)) || (norms && !aligned16(norms)) ||
-      (corr && !aligned16(corr)))
+      (corr && !aligned16(corr)) || (pops && !aligned16(pops)))
     return fail(RTTDA_E_INVAL, "device arrays must be 16-byte aligned");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(RTTDA_E_INVAL, "dt must be finite and > 0 (got %g)", dt);
   if (step0 < 0 || n_steps < 0) return fail(RTTDA_E_INVAL, "step0 and n_steps must be >= 0");
@@ -962,7 +974,7 @@ rttda_status propagate_impl(rttda_ctx *ctx, int32_t nrhs, const rttda_pulse *pul
   hipStream_t hs = ctx->stream;
   const int o = ctx->o, v = ctx->v;
   HIP_TRY(launch_mu_blocks(hs, ctx->d.mu, ctx->pulses(), o, v, nrhs, ctx->moo(), ctx->mov(), ctx->mvv()));
-  HIP_TRY(launch_set_state(hs, ctx->state(), step0, trace, norms, corr));
+  HIP_TRY(launch_set_state(hs, ctx->state(), step0, trace, norms, corr, pops, popU, popk));
   if (has_kick && step0 == 0) {
     HIP_TRY(launch_field(hs, c, c0, ctx->moo(), ctx->mov(), ctx->mvv(), o, v, nrhs, ctx->F(), ctx->part()));
     HIP_TRY(launch_scalar(hs, nrhs, ctx->L.nbf, 0, 0, dt, ctx->pulses(), ctx->state(), ctx->part(), ctx->sc(), c0,
@@ -980,8 +992,8 @@ rttda_status propagate_impl(rttda_ctx *ctx, int32_t nrhs, const rttda_pulse *pul
     st = to_stage_copy(ctx, c, nrhs);
   if (st != RTTDA_OK) return st;
   auto step = [&]() {
-    return integ == INTEG_SSO ? enqueue_sso_step(ctx, nrhs, dt, has_field, corr != nullptr, c0, c)
-                              : enqueue_step(ctx, nrhs, dt, has_field, corr != nullptr, c0, c);
+    return integ == INTEG_SSO ? enqueue_sso_step(ctx, nrhs, dt, has_field, corr != nullptr, pops != nullptr, c0, c)
+                              : enqueue_step(ctx, nrhs, dt, has_field, corr != nullptr, pops != nullptr, c0, c);
   };
 
   const int spg = ctx->steps_per_graph;
@@ -992,7 +1004,7 @@ rttda_status propagate_impl(rttda_ctx *ctx, int32_t nrhs, const rttda_pulse *pul
     GraphEntry &G = ctx->graph;
     const bool hit = G.valid && G.nrhs == nrhs && G.steps == spg && G.mode == mode && G.integ == integ &&
                      G.dt == dt && G.c0 == c0 && G.c == c && G.trace == (trace != nullptr) &&
-                     G.norms == (norms != nullptr) && G.corr == (corr != nullptr);
+                     G.norms == (norms != nullptr) && G.corr == (corr != nullptr) && G.pops == (pops != nullptr);
     if (!hit) {
       drop_graph(ctx);
       hipGraph_t graph = nullptr;
@@ -1021,6 +1033,7 @@ rttda_status propagate_impl(rttda_ctx *ctx, int32_t nrhs, const rttda_pulse *pul
       G.trace = trace != nullptr;
       G.norms = norms != nullptr;
       G.corr = corr != nullptr;
+      G.pops = pops != nullptr;
     }
     const int64_t reps = n_steps / spg;
     for (int64_t k = 0; k < reps; ++k) HIP_TRY(hipGraphLaunch(G.exec, hs));
@@ -1033,6 +1046,7 @@ rttda_status propagate_impl(rttda_ctx *ctx, int32_t nrhs, const rttda_pulse *pul
   HIP_TRY(launch_scalar(hs, nrhs, ctx->L.nbf, 0, SM_TRACE, dt, ctx->pulses(), ctx->state(), ctx->part(), ctx->sc(),
                         c0, ctx->acc0(), ctx->xs0(), nullptr, ctx->normref(), nullptr));
   if (corr) HIP_TRY(launch_corr(hs, nrhs, ctx->ov, c, c0, ctx->xref(), ctx->xref0(), ctx->state()));
+  if (pops) HIP_TRY(launch_pop(hs, nrhs, ctx->ov, c, ctx->state()));
   return RTTDA_OK;
 }
 
@@ -1048,6 +1062,16 @@ rttda_status rttda_propagate(rttda_ctx *ctx, int32_t nrhs, const rttda_pulse *pu
 rttda_status rttda_set_correlation(rttda_ctx *ctx, double *corr) {
   if (!ctx) return fail(RTTDA_E_INVAL, "ctx is NULL");
   ctx->corr_next = corr;
+  return RTTDA_OK;
+}
+
+rttda_status rttda_set_populations(rttda_ctx *ctx, int32_t k, const double *evecs, double *pops) {
+  if (!ctx) return fail(RTTDA_E_INVAL, "ctx is NULL");
+  if (pops && (k < 1 || k > POP_MAX || !evecs))
+    return fail(RTTDA_E_INVAL, "populations need 1 <= k <= %d and the vectors (k=%d)", POP_MAX, k);
+  ctx->pops_next = pops;
+  ctx->popU_next = pops ? evecs : nullptr;
+  ctx->popk_next = pops ? k : 0;
   return RTTDA_OK;
 }
 

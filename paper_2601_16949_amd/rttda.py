@@ -86,6 +86,7 @@ EXPORTS = {
                                            ctypes.c_double, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "rttda_set_correlation": (ctypes.c_int, [_VP, _VP]),
+    "rttda_set_populations": (ctypes.c_int, [_VP, _I32, _VP, _VP]),
     "rttda_dipole_trace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "rttda_guard": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
@@ -277,10 +278,13 @@ class Context:
         return s0, s
 
     def propagate(self, pulses, dt: float, n_steps: int, c0, c, step0: int = 0, trace=None, norms=None,
-                  want_trace: bool = True, want_norms: bool = False, integrator: str = "rk4", corr=None):
+                  want_trace: bool = True, want_norms: bool = False, integrator: str = "rk4", corr=None,
+                  pops=None, pop_vectors=None):
         """Advance in place with RK4 (rttda_propagate) or the symplectic split operator
         (integrator="sso", rttda_propagate_sso).  corr: a device FP64 tensor [n_steps+1, nrhs, 2]
-        that receives the time-correlation function (rttda_set_correlation), or None."""
+        that receives the time-correlation function (rttda_set_correlation), or None.  pops: a
+        device FP64 tensor [n_steps+1, nrhs, k] that receives the populations of the k unit vectors
+        pop_vectors [k, o, v] at every step (rttda_set_populations), or None."""
         import torch
 
         if integrator not in ("rk4", "sso"):
@@ -297,10 +301,16 @@ class Context:
         cp = make_pulses(pulses)
         if corr is not None:
             _dev_check(corr, torch.float64, (n_steps + 1, nrhs, 2), "corr")
+        if pops is not None:
+            k = int(pop_vectors.shape[0])
+            _dev_check(pop_vectors, torch.float64, (k, self.o, self.v), "pop_vectors")
+            _dev_check(pops, torch.float64, (n_steps + 1, nrhs, k), "pops")
         self._enter()
         try:
             if corr is not None:
                 _check(self.lib.rttda_set_correlation(self.handle, _ptr(corr)))
+            if pops is not None:
+                _check(self.lib.rttda_set_populations(self.handle, k, _ptr(pop_vectors), _ptr(pops)))
             _check(fn(self.handle, nrhs, cp, float(dt), int(step0), int(n_steps), _ptr(c0), _ptr(c),
                       _ptr(trace) if trace is not None else None, _ptr(norms) if norms is not None else None))
         finally:

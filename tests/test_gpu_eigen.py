@@ -95,3 +95,42 @@ def test_populations_match_oracle(gpu_lib, prec):
         e2 = np.abs(got[r] - own)
         say(f"[populations] {prec} rhs {r}: projection on the GPU vectors, max error {e2.max():.2e}")
         assert np.all(e2 <= 1e-12 + (1e-6 if prec == "fp32" else 1e-4) * np.max(own))
+
+
+@pytest.mark.parametrize("integrator", ["rk4", "sso"])
+def test_populations_output_of_propagation(gpu_lib, integrator):
+    """Populations as a per-step output of the propagation (rttda_set_populations): every sample
+    against the oracle trajectory projected on the same (GPU) eigenvectors, and the last sample
+    against the separate projection call."""
+    import torch
+
+    o, v, nq, n, k = 12, 48, 60, 60, 6
+    op, ctx = _setup(o, v, nq, "fp32", 4321, max_rhs=2)
+    _, _, U, _ = ctx.eigen_lowest(k, tol=1e-6, max_iter=300)
+    pulses = I.kick_pulses(axes=[(0.0, 0.0, 1.0), (0.0, 1.0, 0.0)], kappa=1e-2)
+    c0d, cd = gpu_lib.ground_state(2, o, v)
+    pops = torch.full((n + 1, 2, k), float("nan"), dtype=torch.float64, device="cuda")
+    ctx.propagate(pulses, 0.05, n, c0d, cd, want_trace=False, integrator=integrator, pops=pops, pop_vectors=U)
+    torch.cuda.synchronize()
+    got = pops.cpu().numpy()
+    assert np.isfinite(got).all()
+    last = ctx.populations(U, cd)
+    assert np.max(np.abs(got[-1] - last)) <= 1e-14 * np.max(last)
+    Ug = U.cpu().numpy().reshape(k, -1)
+    for r, p in enumerate(pulses):
+        blocks = O.dipole_blocks(op, p.direction)
+        c0, C = O.kick(blocks, p.e0, 1.0 + 0j, np.zeros((o, v), complex))
+        q0, Q, p0, P = c0.real, C.real.copy(), c0.imag, C.imag.copy()
+        worst = 0.0
+        for step in range(n + 1):
+            ref = np.abs(Ug @ C.reshape(-1)) ** 2
+            err = np.max(np.abs(got[step, r] - ref))
+            worst = max(worst, err / (1e-12 + 1e-6 * np.max(ref)))
+            assert err <= 1e-12 + 1e-6 * np.max(ref), (step, r, err)
+            if step < n:
+                if integrator == "rk4":
+                    c0, C = O.rk4_step(op, blocks, p, 0.05, step, c0, C)
+                else:
+                    q0, Q, p0, P = O.sso_step(op, blocks, p, 0.05, step, q0, Q, p0, P)
+                    c0, C = complex(q0, p0), Q + 1j * P
+        say(f"[populations output] {integrator} rhs {r}: worst error / bound {worst:.3f}")
