@@ -176,6 +176,17 @@ rttda_status rttda_set_correlation(rttda_ctx *ctx, double *corr);
  * step of the call, alongside the trace.  Both arrays must stay valid until the call's work ends. */
 rttda_status rttda_set_populations(rttda_ctx *ctx, int32_t k, const double *evecs, double *pops);
 
+/* Spectra on the frequency grid omega_j = omega0 + j domega (j < n_omega, Ha), from device signals
+ * of n_t samples spaced dt (eq. fourier_transform; the paper's Hann window with mirroring is the
+ * half-Hann window h_n = (1 + cos(pi n / (n_t-1))) / 2 on the record):
+ *   kind 0, signal = dipole traces [n_t][nsig]:  S_s = omega sum_n h_n (mu_n - mu_0) sin(omega t_n) dt / kappa
+ *   kind 1, signal = time correlations [n_t][nsig][2]:  S_s = omega Re sum_n h_n R_n exp(i omega t_n) dt
+ * out (device): [nsig][n_omega], or with average != 0 the mean over the signals [n_omega] (the
+ * x/y/z average, eq. spectrum_average).  Asynchronous on stream (hipStream_t, NULL = default). */
+rttda_status rttda_spectrum(void *stream, int32_t kind, const double *signal, int32_t n_t, int32_t nsig, double dt,
+                            double kappa, int32_t n_omega, double omega0, double domega, int32_t average,
+                            double *out);
+
 /* out[r] = Re <X_r | M_dr | X_r> (f64 [nrhs]) for states c0, c and host unit
  * vectors dir ([nrhs][3]): the observable behind every trace sample. */
 rttda_status rttda_dipole_trace(rttda_ctx *ctx, int32_t nrhs, const double *dir, const double *c0,

@@ -129,6 +129,8 @@ hipError_t launch_set_state(hipStream_t s, DevState *st, long long step0, double
                             double *corr, double *pops, const double *popU, int popk);
 // eigenstate populations |<U_I | X_r>|^2 at the current step (no-op unless st->pops is set)
 hipError_t launch_pop(hipStream_t s, int R, size_t ov, const double *X, const DevState *st);
+hipError_t launch_spectrum(hipStream_t s, int kind, const double *sig, int n_t, int nsig, double dt, double kappa,
+                           int n_w, double w0, double dw, int average, double *out);
 // time-correlation sample <Xref_r | X_r> (both planes and the ground amplitude) at the current step
 hipError_t launch_corr(hipStream_t s, int R, size_t ov, const double *X, const double *X0, const double *xref,
                        const double *xref0, const DevState *st);

@@ -1007,6 +1007,49 @@ hipError_t launch_set_state(hipStream_t s, DevState *st, long long step0, double
   return hipGetLastError();
 }
 
+// Kick spectra on a frequency grid (eq. fourier_transform, with the half-Hann window that
+// equals a full Hann window on the mirrored record): for a dipole trace (kind 0)
+//   S_s(w) = w sum_n h_n (mu_n - mu_0) sin(w t_n) dt / kappa,
+// for the time-correlation function (kind 1)
+//   S_s(w) = w Re sum_n h_n R_n exp(i w t_n) dt,
+// with h_n = (1 + cos(pi n / N)) / 2, t_n = n dt, n = 0..N.  One thread per (frequency, signal);
+// average: out[w] = the mean over the signals (eq. spectrum_average) instead of out[s][w].
+__global__ __launch_bounds__(256) void k_spectrum(int kind, const double *__restrict__ sig, int n_t, int nsig, double dt,
+                                                  double kappa, int n_w, double w0, double dw, int average,
+                                                  double *__restrict__ out) {
+  const int w_idx = blockIdx.x * 256 + threadIdx.x;
+  if (w_idx >= n_w) return;
+  const double w = w0 + dw * w_idx;
+  const int N = n_t - 1;
+  double mean = 0.0;
+  for (int s = 0; s < nsig; ++s) {
+    double acc = 0.0;
+    const double base = kind == 0 ? sig[s] : 0.0;
+    for (int n = 0; n < n_t; ++n) {
+      const double h = N > 0 ? 0.5 * (1.0 + cos(M_PI * (double)n / N)) : 1.0;
+      double sn, cs;
+      sincos(w * (n * dt), &sn, &cs);
+      if (kind == 0)
+        acc += h * (sig[(size_t)n * nsig + s] - base) * sn;
+      else
+        acc += h * (sig[((size_t)n * nsig + s) * 2] * cs - sig[((size_t)n * nsig + s) * 2 + 1] * sn);
+    }
+    const double val = kind == 0 ? w * acc * dt / kappa : w * acc * dt;
+    if (average)
+      mean += val;
+    else
+      out[(size_t)s * n_w + w_idx] = val;
+  }
+  if (average) out[w_idx] = mean / nsig;
+}
+
+hipError_t launch_spectrum(hipStream_t s, int kind, const double *sig, int n_t, int nsig, double dt, double kappa,
+                           int n_w, double w0, double dw, int average, double *out) {
+  hipLaunchKernelGGL(k_spectrum, dim3((n_w + 255) / 256), dim3(256), 0, s, kind, sig, n_t, nsig, dt, kappa, n_w, w0, dw,
+                     average, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_pop(hipStream_t s, int R, size_t ov, const double *X, const DevState *st) {
   hipLaunchKernelGGL(k_pop, dim3(R, POP_MAX), dim3(256), 0, s, R, ov, X, st);
   return hipGetLastError();

@@ -1065,6 +1065,20 @@ rttda_status rttda_set_correlation(rttda_ctx *ctx, double *corr) {
   return RTTDA_OK;
 }
 
+rttda_status rttda_spectrum(void *stream, int32_t kind, const double *signal, int32_t n_t, int32_t nsig, double dt,
+                            double kappa, int32_t n_omega, double omega0, double domega, int32_t average,
+                            double *out) {
+  if (!signal || !out) return fail(RTTDA_E_INVAL, "NULL argument");
+  if (kind != 0 && kind != 1) return fail(RTTDA_E_INVAL, "kind %d: 0 (dipole trace) or 1 (time correlation)", kind);
+  if (n_t < 1 || nsig < 1 || n_omega < 1) return fail(RTTDA_E_INVAL, "need n_t, nsig, n_omega >= 1");
+  if (!(dt > 0.0) || !std::isfinite(dt) || !std::isfinite(omega0) || !std::isfinite(domega) ||
+      (kind == 0 && (!(kappa != 0.0) || !std::isfinite(kappa))))
+    return fail(RTTDA_E_INVAL, "dt > 0, finite frequencies and a nonzero kappa (dipole trace) are required");
+  HIP_TRY(launch_spectrum(static_cast<hipStream_t>(stream), kind, signal, n_t, nsig, dt, kappa, n_omega, omega0, domega,
+                          average ? 1 : 0, out));
+  return RTTDA_OK;
+}
+
 rttda_status rttda_set_populations(rttda_ctx *ctx, int32_t k, const double *evecs, double *pops) {
   if (!ctx) return fail(RTTDA_E_INVAL, "ctx is NULL");
   if (pops && (k < 1 || k > POP_MAX || !evecs))

@@ -87,6 +87,7 @@ EXPORTS = {
                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "rttda_set_correlation": (ctypes.c_int, [_VP, _VP]),
     "rttda_set_populations": (ctypes.c_int, [_VP, _I32, _VP, _VP]),
+    "rttda_spectrum": (ctypes.c_int, [_VP, _I32, _VP, _I32, _I32, _D, _D, _I32, _D, _D, _I32, _VP]),
     "rttda_dipole_trace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "rttda_guard": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
@@ -448,6 +449,25 @@ def ground_state(nrhs: int, o: int, v: int, device="cuda:0"):
     c0[:, 0] = 1.0
     c = torch.zeros((nrhs, 2, o, v), dtype=torch.float64, device=device)
     return c0, c
+
+
+def spectrum(signal, dt: float, omega, kappa: float = 1.0, average: bool = False, stream=None):
+    """Spectra of device signals on the uniform grid omega (rttda_spectrum): a dipole trace
+    [n_t, nsig] (kind 0, divided by kappa) or a time correlation [n_t, nsig, 2] (kind 1).  Returns
+    a device tensor [nsig, n_omega], or [n_omega] averaged over the signals."""
+    import torch
+
+    lib = load()
+    omega = np.asarray(omega, dtype=np.float64)
+    kind = 0 if signal.dim() == 2 else 1
+    n_t, nsig = int(signal.shape[0]), int(signal.shape[1])
+    _dev_check(signal, torch.float64, tuple(signal.shape), "signal")
+    dw = float(omega[1] - omega[0]) if omega.size > 1 else 0.0
+    out = torch.empty((omega.size,) if average else (nsig, omega.size), dtype=torch.float64, device=signal.device)
+    st = stream if stream is not None else torch.cuda.current_stream(signal.device)
+    _check(lib.rttda_spectrum(st.cuda_stream, kind, _ptr(signal), n_t, nsig, float(dt), float(kappa), int(omega.size),
+                              float(omega[0]), dw, 1 if average else 0, _ptr(out)))
+    return out
 
 
 def to_planes(c0: np.ndarray, c: np.ndarray, device="cuda:0"):

@@ -1,0 +1,63 @@
+"""Device spectra (rttda_spectrum, eq. fourier_transform and eq. spectrum_average) of GPU dipole
+traces and time correlations against the test harness's transform of the same signals (FP64 on
+both sides).  (The signals themselves are checked against the oracle elsewhere: traces in the
+parity tests, correlations in test_gpu_corr.)"""
+import numpy as np
+import pytest
+
+from conftest import say
+from oracle import spectrum as SP
+from paper_2601_16949_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(gpu_lib, n):
+    import torch
+    from paper_2601_16949_amd import rttda
+
+    o, v, nq = 10, 40, 120
+    prob = I.make_problem(I.Shape(o, v, nq, b_scale=0.05, storage="f32"), 16949)
+    ctx = rttda.Context(rttda.DeviceProblem(prob, "fp32"), max_rhs=3)
+    pulses = I.kick_pulses(kappa=1e-3)
+    c0d, cd = gpu_lib.ground_state(3, o, v)
+    corr = torch.empty((n + 1, 3, 2), dtype=torch.float64, device="cuda")
+    tr = ctx.propagate(pulses, 0.05, n, c0d, cd, corr=corr)
+    torch.cuda.synchronize()
+    return tr, corr
+
+
+def test_spectra_match_the_transform_definition(gpu_lib):
+    import torch
+
+    n, kappa, dt = 1500, 1e-3, 0.05
+    tr, corr = _run(gpu_lib, n)
+    omega = np.linspace(0.2, 1.6, 701)
+    S = gpu_lib.spectrum(tr, dt, omega, kappa=kappa).cpu().numpy()
+    Sa = gpu_lib.spectrum(tr, dt, omega, kappa=kappa, average=True).cpu().numpy()
+    C = gpu_lib.spectrum(corr, dt, omega).cpu().numpy()
+    torch.cuda.synchronize()
+    trh, ch = tr.cpu().numpy(), corr.cpu().numpy()
+    h = SP.window(n + 1)
+    t = np.arange(n + 1) * dt
+    worst = 0.0
+    for s in range(3):
+        for j in range(0, omega.size, 50):
+            ref = SP.dtft(trh[:, s], dt, kappa, omega[j])
+            worst = max(worst, abs(S[s, j] - ref) / np.max(np.abs(S[s])))
+            z = np.sum(h * (ch[:, s, 0] + 1j * ch[:, s, 1]) * np.exp(1j * omega[j] * t)) * dt
+            refc = omega[j] * z.real
+            worst = max(worst, abs(C[s, j] - refc) / np.max(np.abs(C[s])))
+    say(f"[spectrum] worst relative deviation from the transform definition {worst:.2e}")
+    assert worst < 1e-10
+    assert np.max(np.abs(Sa - S.mean(axis=0))) <= 1e-12 * np.max(np.abs(Sa))
+
+
+def test_spectrum_argument_errors(gpu_lib):
+    import torch
+
+    sig = torch.zeros((10, 2), dtype=torch.float64, device="cuda")
+    with pytest.raises(gpu_lib.RttdaError):
+        gpu_lib.spectrum(sig, 0.05, np.linspace(0.1, 1.0, 5), kappa=0.0)
+    with pytest.raises(gpu_lib.RttdaError):
+        gpu_lib.spectrum(sig, -0.05, np.linspace(0.1, 1.0, 5), kappa=1.0)
