@@ -41,7 +41,7 @@ constexpr int SC_GRE = 0, SC_GIM = 1, SC_E = 2;
 constexpr int PART_STRIDE = 4;
 
 // Field-kernel tile (i x a) and its grid per RHS.
-constexpr int FT_I = 16, FT_A = 64;
+constexpr int FT_I = 16, FT_A = 16;
 inline int field_blocks_a(int v) { return (v + FT_A - 1) / FT_A; }
 inline int field_blocks_i(int o) { return (o + FT_I - 1) / FT_I; }
 

@@ -232,119 +232,104 @@ __global__ __launch_bounds__(256) void k_gemv2(const TB *__restrict__ B, const f
 }
 
 // ------------------------------------------------------------------------------------------------
-// Field product (FP64), eqs. sc2-sc5 in factorised form, both planes of one RHS per block:
-//   F_p = X_p mu_vv - mu_oo X_p + sqrt2 mu_ov c0_p
+// Field product (FP64), eqs. sc2-sc5 in factorised form, on the FP64 matrix cores:
+//   F_p = X_p mu_vv - mu_oo X_p + sqrt2 mu_ov c0_p      (p = 0, 1: the real and imaginary planes)
 // plus per-block partial sums g_p = sqrt2 <mu_ov, X_p>, <X, F> and |X|^2.
-// Tile FT_I x FT_A = 16 x 64; 256 threads, 4 columns x 2 planes per thread.
+// One block per (RHS, 16 x 16 tile of (i, a)); 8 waves: waves 0-3 form plane 0, waves 4-7 plane 1,
+// each over a quarter of the contraction index (b for X mu_vv, j for mu_oo X) with
+// v_mfma_f64_16x16x4 (operands read straight from memory, four K steps' loads issued before their
+// MFMAs); the quarters are added in a fixed order through LDS.
+// f64 16x16x4 operand layout: lane l holds A[l % 16][l / 16] and B[l / 16][l % 16]; the result
+// element t of lane l is D[4 t + l / 16][l % 16].
 // ------------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_field(const double *__restrict__ X, const double *__restrict__ X0,
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(512) void k_field(const double *__restrict__ X, const double *__restrict__ X0,
                                                const double *__restrict__ moo, const double *__restrict__ mov,
                                                const double *__restrict__ mvv, int o, int v,
                                                double *__restrict__ F, double *__restrict__ part) {
-  __shared__ double sh[2 * 32 * 65 + 16 * 33];
+  __shared__ double red[8][4][64];
+  __shared__ double sums[2][4];
   const int at = blockIdx.x, it = blockIdx.y, r = blockIdx.z;
   const int nbf = gridDim.x * gridDim.y, blk = it * gridDim.x + at;
   const int i0 = it * FT_I, a0 = at * FT_A;
-  const int tid = threadIdx.x, ti = tid >> 4, ta = (tid & 15) * 4;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int p = wave >> 2, q = wave & 3;
+  const int m = lane & 15, g = lane >> 4;
   const size_t ov = (size_t)o * v;
-  const double *Xr = X + (size_t)r * 2 * ov;
+  const double *Xp = X + ((size_t)r * 2 + p) * ov;
   const double *moo_r = moo + (size_t)r * o * o;
   const double *mov_r = mov + (size_t)r * ov;
   const double *mvv_r = mvv + (size_t)r * v * v;
-  double acc[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+  const int i = i0 + m, a = a0 + m;  // this lane's operand row (A) and column (B)
+  d4v acc = {0.0, 0.0, 0.0, 0.0};
 
-  // X_p mu_vv
+  // X_p mu_vv over b in this wave's quarter [bq, be)
   {
-    double(*Xs)[16][33] = reinterpret_cast<double(*)[16][33]>(sh);        // [2][16][33]
-    double(*Ms)[65] = reinterpret_cast<double(*)[65]>(sh + 2 * 16 * 33);  // [32][65]
-    for (int b0 = 0; b0 < v; b0 += 32) {
-      __syncthreads();
-      for (int k = tid; k < 2 * 16 * 32; k += 256) {
-        const int p = k >> 9, rr = (k >> 5) & 15, bb = k & 31, i = i0 + rr, b = b0 + bb;
-        Xs[p][rr][bb] = (i < o && b < v) ? Xr[p * ov + (size_t)i * v + b] : 0.0;
-      }
-      for (int k = tid; k < 32 * 64; k += 256) {
-        const int bb = k >> 6, aa = k & 63, b = b0 + bb, a = a0 + aa;
-        Ms[bb][aa] = (b < v && a < v) ? mvv_r[(size_t)b * v + a] : 0.0;
-      }
-      __syncthreads();
-#pragma unroll 8
-      for (int bb = 0; bb < 32; ++bb) {
-        const double x0 = Xs[0][ti][bb], x1 = Xs[1][ti][bb];
+    const int kq = (((v + 3) / 4) + 3) / 4 * 4;
+    const int bq = q * kq, be = min(v, bq + kq);
+    for (int b0 = bq; b0 < be; b0 += 16) {
+      double xa[4], mb[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const double m = Ms[bb][ta + k];
-          acc[0][k] += x0 * m;
-          acc[1][k] += x1 * m;
-        }
+      for (int u = 0; u < 4; ++u) {
+        const int b = b0 + 4 * u + g;
+        xa[u] = (i < o && b < be) ? Xp[(size_t)i * v + b] : 0.0;
+        mb[u] = (b < be && a < v) ? mvv_r[(size_t)b * v + a] : 0.0;
       }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[u], mb[u], acc, 0, 0, 0);
     }
   }
-  // - mu_oo X_p
+  // - mu_oo X_p over j in this wave's quarter [jq, je)
   {
-    double(*Os)[33] = reinterpret_cast<double(*)[33]>(sh);                // [16][33]
-    double(*XJ)[32][65] = reinterpret_cast<double(*)[32][65]>(sh + 16 * 33);  // [2][32][65]
-    for (int j0 = 0; j0 < o; j0 += 32) {
-      __syncthreads();
-      for (int k = tid; k < 16 * 32; k += 256) {
-        const int rr = k >> 5, jj = k & 31, i = i0 + rr, j = j0 + jj;
-        Os[rr][jj] = (i < o && j < o) ? moo_r[(size_t)i * o + j] : 0.0;
-      }
-      for (int k = tid; k < 2 * 32 * 64; k += 256) {
-        const int p = k >> 11, jj = (k >> 6) & 31, aa = k & 63, j = j0 + jj, a = a0 + aa;
-        XJ[p][jj][aa] = (j < o && a < v) ? Xr[p * ov + (size_t)j * v + a] : 0.0;
-      }
-      __syncthreads();
-#pragma unroll 8
-      for (int jj = 0; jj < 32; ++jj) {
-        const double m = Os[ti][jj];
+    const int kq = (((o + 3) / 4) + 3) / 4 * 4;
+    const int jq = q * kq, je = min(o, jq + kq);
+    for (int j0 = jq; j0 < je; j0 += 16) {
+      double ma[4], xb[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          acc[0][k] -= m * XJ[0][jj][ta + k];
-          acc[1][k] -= m * XJ[1][jj][ta + k];
-        }
+      for (int u = 0; u < 4; ++u) {
+        const int j = j0 + 4 * u + g;
+        ma[u] = (i < o && j < je) ? -moo_r[(size_t)i * o + j] : 0.0;
+        xb[u] = (j < je && a < v) ? Xp[(size_t)j * v + a] : 0.0;
       }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ma[u], xb[u], acc, 0, 0, 0);
     }
   }
-  // + sqrt2 mu_ov c0, outputs and partial sums
-  const double c0r = X0[2 * r], c0i = X0[2 * r + 1];
-  const int i = i0 + ti;
-  double pg0 = 0, pg1 = 0, ptr = 0, pnr = 0;
-  double *Fr = F + (size_t)r * 2 * ov;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int a = a0 + ta + k;
-    if (i < o && a < v) {
-      const size_t ia = (size_t)i * v + a;
-      const double m = mov_r[ia];
-      const double x0 = Xr[ia], x1 = Xr[ov + ia];
-      const double f0 = acc[0][k] + SQRT2 * m * c0r;
-      const double f1 = acc[1][k] + SQRT2 * m * c0i;
-      Fr[ia] = f0;
-      Fr[ov + ia] = f1;
-      pg0 += SQRT2 * m * x0;
-      pg1 += SQRT2 * m * x1;
-      ptr += x0 * f0 + x1 * f1;
-      pnr += x0 * x0 + x1 * x1;
+  for (int t = 0; t < 4; ++t) red[wave][t][lane] = acc[t];
+  __syncthreads();
+  // plane leaders (waves 0 and 4): add the quarters, + sqrt2 mu_ov c0_p, outputs, partial sums
+  if (q == 0) {
+    const double c0p = X0[2 * r + p];
+    double pg = 0.0, ptr = 0.0, pnr = 0.0;
+    double *Fp = F + ((size_t)r * 2 + p) * ov;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int ii = i0 + 4 * t + g, aa = a0 + m;
+      if (ii < o && aa < v) {
+        const size_t ia = (size_t)ii * v + aa;
+        const double mo = mov_r[ia], x = Xp[ia];
+        const double f = ((red[wave][t][lane] + red[wave + 1][t][lane]) + (red[wave + 2][t][lane] + red[wave + 3][t][lane])) +
+                         SQRT2 * mo * c0p;
+        Fp[ia] = f;
+        pg += SQRT2 * mo * x;
+        ptr += x * f;
+        pnr += x * x;
+      }
+    }
+    pg = wave_sum(pg);
+    ptr = wave_sum(ptr);
+    pnr = wave_sum(pnr);
+    if (lane == 0) {
+      sums[p][0] = p == 0 ? pg : 0.0;
+      sums[p][1] = p == 1 ? pg : 0.0;
+      sums[p][2] = ptr;
+      sums[p][3] = pnr;
     }
   }
   __syncthreads();
-  double *red = sh;  // [4 waves][4]
-  pg0 = wave_sum(pg0);
-  pg1 = wave_sum(pg1);
-  ptr = wave_sum(ptr);
-  pnr = wave_sum(pnr);
-  const int lane = tid & 63, wave = tid >> 6;
-  if (lane == 0) {
-    red[wave * 4 + 0] = pg0;
-    red[wave * 4 + 1] = pg1;
-    red[wave * 4 + 2] = ptr;
-    red[wave * 4 + 3] = pnr;
-  }
-  __syncthreads();
-  if (tid < 4) {
-    part[((size_t)r * nbf + blk) * PART_STRIDE + tid] = (red[tid] + red[4 + tid]) + (red[8 + tid] + red[12 + tid]);
-  }
+  if (tid < 4) part[((size_t)r * nbf + blk) * PART_STRIDE + tid] = sums[0][tid] + sums[1][tid];
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -365,70 +350,91 @@ __global__ __launch_bounds__(256) void k_scalar(int R, int nbf, int stage, int m
   double *trace = st->trace;
   double *norms = st->norms;
   const double node = (stage == 0) ? 0.0 : (stage == 3 ? 1.0 : 0.5);
-  for (int r = threadIdx.x; r < R; r += blockDim.x) {
-    double g0 = 0.0, g1 = 0.0, tr = 0.0, nr = 0.0;
-    for (int b = 0; b < nbf; ++b) {
-      const double *pp = part + ((size_t)r * nbf + b) * PART_STRIDE;
-      g0 += pp[0];
-      g1 += pp[1];
-      tr += pp[2];
-      nr += pp[3];
+  // the field kernel's per-block partial sums of each RHS, 64 RHS at a time: wave w adds those of
+  // RHS r0 + w, r0 + w + 4, ... (lanes over blocks, then a fixed shuffle tree)
+  __shared__ double tot[64][PART_STRIDE];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int r0 = 0; r0 < R; r0 += 64) {
+    const int nr0 = min(64, R - r0);
+    for (int rr = wave; rr < nr0; rr += (int)(blockDim.x >> 6)) {
+      const double *pp = part + (size_t)(r0 + rr) * nbf * PART_STRIDE;
+      double s_0 = 0.0, s_1 = 0.0, s_2 = 0.0, s_3 = 0.0;
+      for (int b = lane; b < nbf; b += 64) {
+        s_0 += pp[(size_t)b * PART_STRIDE + 0];
+        s_1 += pp[(size_t)b * PART_STRIDE + 1];
+        s_2 += pp[(size_t)b * PART_STRIDE + 2];
+        s_3 += pp[(size_t)b * PART_STRIDE + 3];
+      }
+      s_0 = wave_sum(s_0);
+      s_1 = wave_sum(s_1);
+      s_2 = wave_sum(s_2);
+      s_3 = wave_sum(s_3);
+      if (lane == 0) {
+        tot[rr][0] = s_0;
+        tot[rr][1] = s_1;
+        tot[rr][2] = s_2;
+        tot[rr][3] = s_3;
+      }
     }
-    double E = 0.0;
-    if (mode & SM_EFIELD)
-      E = pulse_field(pulses[r], ((double)step + node) * dt);
-    else if (mode & SM_KEEP_E)
-      E = sc[r * SC_STRIDE + SC_E];
-    sc[r * SC_STRIDE + SC_GRE] = g0;
-    sc[r * SC_STRIDE + SC_GIM] = g1;
-    sc[r * SC_STRIDE + SC_E] = E;
-    // X0 of this stage (c0 at stage 0, else the stage value)
-    const double x0r = (stage == 0) ? c0[2 * r] : xs0[2 * r];
-    const double x0i = (stage == 0) ? c0[2 * r + 1] : xs0[2 * r + 1];
-    if (mode & (SM_TRACE | SM_OUT)) {
-      const double t = tr + (x0r * g0 + x0i * g1);
-      const double n2 = nr + (x0r * x0r + x0i * x0i);
-      if (mode & SM_OUT) out[r] = t;
-      if (mode & SM_TRACE) {
-        if (trace) trace[k * R + r] = t;
-        if (norms) norms[k * R + r] = n2;
-        if (k == 0) {
-          normref[r] = n2;
-        } else if (!(n2 <= 2.0 * normref[r])) {  // also catches NaN
-          bad = 1;
+    __syncthreads();
+    for (int r = r0 + (int)threadIdx.x; r < r0 + nr0; r += blockDim.x) {
+      const double g0 = tot[r - r0][0], g1 = tot[r - r0][1], tr = tot[r - r0][2], nr = tot[r - r0][3];
+      double E = 0.0;
+      if (mode & SM_EFIELD)
+        E = pulse_field(pulses[r], ((double)step + node) * dt);
+      else if (mode & SM_KEEP_E)
+        E = sc[r * SC_STRIDE + SC_E];
+      sc[r * SC_STRIDE + SC_GRE] = g0;
+      sc[r * SC_STRIDE + SC_GIM] = g1;
+      sc[r * SC_STRIDE + SC_E] = E;
+      // X0 of this stage (c0 at stage 0, else the stage value)
+      const double x0r = (stage == 0) ? c0[2 * r] : xs0[2 * r];
+      const double x0i = (stage == 0) ? c0[2 * r + 1] : xs0[2 * r + 1];
+      if (mode & (SM_TRACE | SM_OUT)) {
+        const double t = tr + (x0r * g0 + x0i * g1);
+        const double n2 = nr + (x0r * x0r + x0i * x0i);
+        if (mode & SM_OUT) out[r] = t;
+        if (mode & SM_TRACE) {
+          if (trace) trace[k * R + r] = t;
+          if (norms) norms[k * R + r] = n2;
+          if (k == 0) {
+            normref[r] = n2;
+          } else if (!(n2 <= 2.0 * normref[r])) {  // also catches NaN
+            bad = 1;
+          }
+        }
+      }
+      if (mode & SM_SIGMA0) {
+        s0[2 * r] = -E * g0;
+        s0[2 * r + 1] = -E * g1;
+      }
+      if (mode & SM_C0) {
+        // k0 = -i * (H X)_0 = -i * (-E g) = i E g
+        const double kr = -E * g1, ki = E * g0;
+        const double cr = c0[2 * r], ci = c0[2 * r + 1];
+        if (stage == 0) {
+          acc0[2 * r] = cr + dt / 6.0 * kr;
+          acc0[2 * r + 1] = ci + dt / 6.0 * ki;
+          xs0[2 * r] = cr + 0.5 * dt * kr;
+          xs0[2 * r + 1] = ci + 0.5 * dt * ki;
+        } else if (stage == 1) {
+          acc0[2 * r] += dt / 3.0 * kr;
+          acc0[2 * r + 1] += dt / 3.0 * ki;
+          xs0[2 * r] = cr + 0.5 * dt * kr;
+          xs0[2 * r + 1] = ci + 0.5 * dt * ki;
+        } else if (stage == 2) {
+          acc0[2 * r] += dt / 3.0 * kr;
+          acc0[2 * r + 1] += dt / 3.0 * ki;
+          xs0[2 * r] = cr + dt * kr;
+          xs0[2 * r + 1] = ci + dt * ki;
+        } else {
+          c0[2 * r] = acc0[2 * r] + dt / 6.0 * kr;
+          c0[2 * r + 1] = acc0[2 * r + 1] + dt / 6.0 * ki;
         }
       }
     }
-    if (mode & SM_SIGMA0) {
-      s0[2 * r] = -E * g0;
-      s0[2 * r + 1] = -E * g1;
-    }
-    if (mode & SM_C0) {
-      // k0 = -i * (H X)_0 = -i * (-E g) = i E g
-      const double kr = -E * g1, ki = E * g0;
-      const double cr = c0[2 * r], ci = c0[2 * r + 1];
-      if (stage == 0) {
-        acc0[2 * r] = cr + dt / 6.0 * kr;
-        acc0[2 * r + 1] = ci + dt / 6.0 * ki;
-        xs0[2 * r] = cr + 0.5 * dt * kr;
-        xs0[2 * r + 1] = ci + 0.5 * dt * ki;
-      } else if (stage == 1) {
-        acc0[2 * r] += dt / 3.0 * kr;
-        acc0[2 * r + 1] += dt / 3.0 * ki;
-        xs0[2 * r] = cr + 0.5 * dt * kr;
-        xs0[2 * r + 1] = ci + 0.5 * dt * ki;
-      } else if (stage == 2) {
-        acc0[2 * r] += dt / 3.0 * kr;
-        acc0[2 * r + 1] += dt / 3.0 * ki;
-        xs0[2 * r] = cr + dt * kr;
-        xs0[2 * r + 1] = ci + dt * ki;
-      } else {
-        c0[2 * r] = acc0[2 * r] + dt / 6.0 * kr;
-        c0[2 * r + 1] = acc0[2 * r + 1] + dt / 6.0 * ki;
-      }
-    }
+    __syncthreads();
   }
-  __syncthreads();
   if (threadIdx.x == 0) {
     if (bad && st->bad_step < 0) st->bad_step = step;
     if (mode & SM_INC) st->step = step + 1;
@@ -908,7 +914,7 @@ hipError_t launch_gemv2(hipStream_t s, int b_dtype, const void *B, const float *
 hipError_t launch_field(hipStream_t s, const double *X, const double *X0, const double *moo, const double *mov,
                         const double *mvv, int o, int v, int R, double *F, double *part) {
   dim3 grid(field_blocks_a(v), field_blocks_i(o), R);
-  hipLaunchKernelGGL(k_field, grid, dim3(256), 0, s, X, X0, moo, mov, mvv, o, v, F, part);
+  hipLaunchKernelGGL(k_field, grid, dim3(512), 0, s, X, X0, moo, mov, mvv, o, v, F, part);
   return hipGetLastError();
 }
 
