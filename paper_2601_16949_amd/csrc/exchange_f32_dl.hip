@@ -61,7 +61,7 @@ __device__ __forceinline__ void lds_barrier() {
   asm volatile("s_barrier" ::: "memory");
 }
 
-template <int O16, int WS, int WC>
+template <int O16, int WS, int WC, int NB = 3>
 struct CfgD {
   static constexpr int KS = 2 * WS, NT = 32 * WC, JB = O16 / 16;
   static constexpr int XROWS = KS * O16;
@@ -71,25 +71,28 @@ struct CfgD {
   static constexpr int NOW = (OCH + 255) / 256;             // B_oo load instructions per wave
   static constexpr int XS = XROWS * KC, BS = NT * KC;       // floats per buffer
   static constexpr int OS = NOW * 256 * 4;                  // floats (padded to whole instructions)
-  static constexpr size_t LDS = (size_t)(3 * (XS + BS) + OS) * sizeof(float);
+  static constexpr size_t LDS = (size_t)(NB * (XS + BS) + OS) * sizeof(float);  // NB chunk buffers
   static_assert(XROWS % 64 == 0 && NT % 64 == 0, "tile must split into whole load instructions");
 };
 
-// PIPE: half-chunk software pipeline (described at the loop) instead of reading each chunk's
-// fragments after its barrier and waiting for them before its MFMAs.
+// PIPE: 0 reads each chunk's fragments after its barrier and waits for them before its MFMAs;
+// 1 is the half-chunk software pipeline (described at the loop) over three chunk buffers, loads
+// issued two chunks ahead; 2 the same over two buffers, loads one chunk ahead (less LDS, so four
+// workgroups fit a CU).
 // OCC: workgroups per CU the register budget is sized for (2, or 3 where three fit the LDS).
-template <int O16, int WS, int WC, bool PIPE, int OCC>
+template <int O16, int WS, int WC, int PIPE, int OCC>
 __global__ __launch_bounds__(256, OCC) void k_exchange_f32_dl(const float *__restrict__ Boo,
                                                          const float *__restrict__ Bvv,
                                                          const float *__restrict__ X, int o, int v, int nq, int ns,
                                                          int n_sg, int n_ct, int nsplit, float scale,
                                                          float *__restrict__ P) {
-  using C = CfgD<O16, WS, WC>;
+  constexpr int NB = PIPE == 2 ? 2 : 3;
+  using C = CfgD<O16, WS, WC, NB>;
   constexpr int JB = C::JB, NXW = C::NXW, NBW = C::NBW, NOW = C::NOW, NXB = NXW + NBW;
   extern __shared__ __attribute__((aligned(16))) float ldsd[];
-  float *Xs0 = ldsd;                 // [3][XROWS][16]
-  float *Bs0 = Xs0 + 3 * C::XS;      // [3][NT][16]
-  float *Os = Bs0 + 3 * C::BS;       // [O16][O16] (+ padding)
+  float *Xs0 = ldsd;                 // [NB][XROWS][16]
+  float *Bs0 = Xs0 + NB * C::XS;     // [NB][NT][16]
+  float *Os = Bs0 + NB * C::BS;      // [O16][O16] (+ padding)
 
   const int total = n_sg * n_ct * nsplit;
   const int per_xcd = (int)gridDim.x / 8;
@@ -101,7 +104,8 @@ __global__ __launch_bounds__(256, OCC) void k_exchange_f32_dl(const float *__res
   const int qa = (int)((long long)sp * nq / nsplit), qb = (int)((long long)(sp + 1) * nq / nsplit);
   const int s_base = sg * C::KS, c_base = ct * C::NT;
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // (the two-buffer form holds the wave index in a scalar register, and with it the LDS destinations)
+  const int tid = threadIdx.x, lane = tid & 63, wave = PIPE == 2 ? __builtin_amdgcn_readfirstlane(tid >> 6) : tid >> 6;
   const int g = lane >> 4, n = lane & 15;
   const int ws = wave >> 1, wc = wave & 1;
   const int nkc = (v + KC - 1) / KC;
@@ -145,9 +149,13 @@ __global__ __launch_bounds__(256, OCC) void k_exchange_f32_dl(const float *__res
   auto issue = [&](int c) { issue_at(qa + c / nkc, c % nkc, c % 3, true); };
   auto issue_os = [&](int q) {
     const float *Oq = Boo + (size_t)q * o * o;
+    // (once per Q: with two buffers the per-lane addresses are recomputed here rather than held in
+    // registers through the loop)
+    int ln = lane;
+    if constexpr (PIPE == 2) asm volatile("" : "+v"(ln));
 #pragma unroll
     for (int k = 0; k < NOW; ++k) {
-      const int e0 = (wave * NOW + k) * 64, e = e0 + lane;  // 16-byte chunk index in the tile
+      const int e0 = (wave * NOW + k) * 64, e = e0 + ln;  // 16-byte chunk index in the tile
       const int i = e / (O16 / 4), p = e % (O16 / 4);
       const int jc = 4 * (p ^ swz_o<O16>(i));
       const float *src = (e < C::OCH && i < o && jc < o) ? Oq + (size_t)i * o + jc : zp;
@@ -349,22 +357,19 @@ __global__ __launch_bounds__(256, OCC) void k_exchange_f32_dl(const float *__res
       FragA A0, A1;
       issue_os(qa);
       issue_at(qa, 0, 0, true);
-      // chunk c+2's (Q, K chunk, buffer), advanced one chunk per iteration
-      int q2 = qa, kc2 = 1, b2 = 1;
-      if (kc2 == nkc) { kc2 = 0; ++q2; }
-      issue_at(q2, kc2, b2, NC > 1);
-      auto adv2 = [&]() __attribute__((always_inline)) {
-        if (++kc2 == nkc) { kc2 = 0; ++q2; }
-        b2 = b2 == 2 ? 0 : b2 + 1;
-      };
-      adv2();
+      if constexpr (NB == 3) issue_at(qa, 1, 1, true);  // NC >= nkc >= 3
+      // the chunk NB-1 ahead of chunk c: (Q index, K chunk, buffer), advanced one chunk per iteration
+      int q2 = qa, kc2 = NB - 1, b2 = NB - 1;
       int kcc = 0, qc = qa, buf = 0;  // chunk c's K chunk, Q index and LDS buffer
       auto step = [&](int c, FragB &Bc, const FragB &Bp) __attribute__((always_inline)) {
-        wait_vm<NXB>();  // chunk c (and a B_oo^Q tile issued before it) has landed
+        // chunk c (and a B_oo^Q tile issued before it) has landed; with three buffers chunk c+1
+        // may still be in flight
+        if constexpr (NB == 3) wait_vm<NXB>(); else wait_vm<0>();
         lds_barrier();   // publishes chunk c; every wave has read chunk c-1 and run the last K product
         if (kcc == 1 && c > 1) issue_os(qc);  // chunk c-1 opened Q qc; the K product before it is done
-        issue_at(q2, kc2, b2, c + 2 < NC);
-        adv2();
+        issue_at(q2, kc2, b2, c + NB - 1 < NC);  // into chunk c-1's buffer
+        if (++kc2 == nkc) { kc2 = 0; ++q2; }
+        b2 = b2 == NB - 1 ? 0 : b2 + 1;
         __builtin_amdgcn_sched_barrier(0);
         read_b(ncb_tag, buf, Bc);
         read_a(ncb_tag, H0{}, buf, A0);
@@ -382,7 +387,7 @@ __global__ __launch_bounds__(256, OCC) void k_exchange_f32_dl(const float *__res
         __builtin_amdgcn_sched_barrier(0);
         mfma_half(ncb_tag, H0{}, Bc, A0, T2{}, T4{});
         if (++kcc == nkc) { kcc = 0; ++qc; }
-        buf = buf == 2 ? 0 : buf + 1;
+        buf = buf == NB - 1 ? 0 : buf + 1;
       };
       for (int c = 0; c < NC; c += 2) {
         step(c, B0, B1);
@@ -456,10 +461,10 @@ __global__ __launch_bounds__(256, OCC) void k_exchange_f32_dl(const float *__res
   }
 }
 
-template <int O16, int WS, int WC, bool PIPE, int OCC>
+template <int O16, int WS, int WC, int PIPE, int OCC>
 hipError_t launch_xf32dl(hipStream_t s, const void *Boo, const void *Bvv, const void *X, const void *, int o, int v,
                          int nq, int ns, int nsplit, float scale, float *P, void *, size_t) {
-  using C = CfgD<O16, WS, WC>;
+  using C = CfgD<O16, WS, WC, PIPE == 2 ? 2 : 3>;
   if (o > O16 || (v & 3) != 0 || (o & 3) != 0 || v < 3 * KC) return hipErrorInvalidValue;
   const int n_sg = (ns + C::KS - 1) / C::KS, n_ct = (v + C::NT - 1) / C::NT;
   const int total = n_sg * n_ct * nsplit;
@@ -470,25 +475,27 @@ hipError_t launch_xf32dl(hipStream_t s, const void *Boo, const void *Bvv, const 
   return hipGetLastError();
 }
 
-template <int O16, int WS, int WC, bool PIPE, int OCC>
+template <int O16, int WS, int WC, int PIPE, int OCC>
 hipError_t prepare_xf32dl() {
   return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_exchange_f32_dl<O16, WS, WC, PIPE, OCC>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)CfgD<O16, WS, WC>::LDS);
+                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)CfgD<O16, WS, WC, PIPE == 2 ? 2 : 3>::LDS);
 }
 
 #define XDL(O16, WS, WC, PIPE, OCC, NAME)                                                                \
   ExchangeVariant {                                                                                      \
     RTTDA_PREC_FP32, O16, CfgD<O16, WS, WC>::KS, CfgD<O16, WS, WC>::NT, NAME,                            \
-        &launch_xf32dl<O16, WS, WC, PIPE, OCC>, CfgD<O16, WS, WC>::LDS,                                  \
+        &launch_xf32dl<O16, WS, WC, PIPE, OCC>, CfgD<O16, WS, WC, PIPE == 2 ? 2 : 3>::LDS,                \
         &prepare_xf32dl<O16, WS, WC, PIPE, OCC>, 3 * KC, 4, 4, 1, false, PIPE ? 2 : 1                    \
   }
 #define XDL2(O16, WS, WC)                                                                                \
-  XDL(O16, WS, WC, false, 2, "f32dl_o" #O16 "_ws" #WS "_wc" #WC),                                        \
-      XDL(O16, WS, WC, true, 2, "f32dlp_o" #O16 "_ws" #WS "_wc" #WC)
+  XDL(O16, WS, WC, 0, 2, "f32dl_o" #O16 "_ws" #WS "_wc" #WC),                                            \
+      XDL(O16, WS, WC, 1, 2, "f32dlp_o" #O16 "_ws" #WS "_wc" #WC)
 
 // (o64 ws1 wc2 fits three workgroups per CU in both forms: at most 152 registers, 52 KiB of LDS)
 const ExchangeVariant kF32DlVariants[] = {
     XDL2(32, 1, 2), XDL2(32, 2, 2), XDL2(48, 2, 2), XDL2(64, 1, 2), XDL2(64, 2, 2), XDL2(64, 1, 4), XDL2(96, 1, 2),
+    XDL(64, 1, 2, 2, 4, "f32dlq_o64_ws1_wc2"),
 };
 
 }  // namespace
