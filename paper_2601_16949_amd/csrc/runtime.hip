@@ -228,6 +228,11 @@ struct rttda_ctx {
   int sk = 0, sj = 0;
   int use_graph = 1, steps_per_graph = 8;
   int qchunk = 0;  // Q per chunk of the GEMM exchange path, 0 = as many as the scratch holds
+  // second stream for the Coulomb pair, which then runs alongside the exchange (HBM-bound next to
+  // MFMA-bound work); fork and join through two events, also inside a captured graph
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  int overlap = 1;  // 1: Coulomb pair on the second stream, 2: in order on the context's stream
   double *corr_next = nullptr;  // time-correlation output of the next propagate call
   double *pops_next = nullptr;  // populations output of the next propagate call, its vectors and count
   const double *popU_next = nullptr;
@@ -397,11 +402,19 @@ rttda_status enqueue_two_electron(rttda_ctx *ctx, int ns) {
   const int ov = (int)ctx->ov;
   hipStream_t s = ctx->stream;
   const bool pr = ctx->prof.on;
-  if (pr) HIP_TRY(ctx->prof.begin(PC_COULOMB, s));
+  // the Coulomb pair and the exchange read the same stage copy and write disjoint partial slabs
+  const bool fork = ctx->aux != nullptr && ctx->overlap == 1;
+  hipStream_t sc = fork ? ctx->aux : s;
+  if (fork) {
+    HIP_TRY(hipEventRecord(ctx->ev_fork, s));
+    HIP_TRY(hipStreamWaitEvent(ctx->aux, ctx->ev_fork, 0));
+  }
+  if (pr) HIP_TRY(ctx->prof.begin(PC_COULOMB, sc));
   const int nes = gemv1_chunks(ctx->nq, ov);
-  HIP_TRY(launch_gemv1(s, ctx->d.b_dtype, ctx->d.b_ov, ctx->x32(), ctx->nq, ov, ns, nes, ctx->dvec()));
-  HIP_TRY(launch_gemv2(s, ctx->d.b_dtype, ctx->d.b_ov, ctx->dvec(), ctx->nq, ov, ns, ctx->sj, ctx->P()));
-  if (pr) HIP_TRY(ctx->prof.end(PC_COULOMB, s));
+  HIP_TRY(launch_gemv1(sc, ctx->d.b_dtype, ctx->d.b_ov, ctx->x32(), ctx->nq, ov, ns, nes, ctx->dvec()));
+  HIP_TRY(launch_gemv2(sc, ctx->d.b_dtype, ctx->d.b_ov, ctx->dvec(), ctx->nq, ov, ns, ctx->sj, ctx->P()));
+  if (pr) HIP_TRY(ctx->prof.end(PC_COULOMB, sc));
+  if (fork) HIP_TRY(hipEventRecord(ctx->ev_join, ctx->aux));
   const ExchangeVariant *x = variant_of(ctx->prec, ctx->xvar);
   float *Pk = ctx->P() + (size_t)ctx->sj * ns * ctx->ov;
   const void *X = ctx->prec == RTTDA_PREC_FP32 ? (const void *)ctx->x32() : (const void *)ctx->xhi();
@@ -410,6 +423,7 @@ rttda_status enqueue_two_electron(rttda_ctx *ctx, int ns) {
   HIP_TRY(x->launch(s, ctx->d.b_oo, ctx->d.b_vv, X, Xlo, ctx->o, ctx->v, ctx->nq, ns, ctx->sk, (float)(-ctx->d.cx),
                     Pk, ctx->scratch(), scratch_for(ctx, ns)));
   if (pr) HIP_TRY(ctx->prof.end(PC_EXCHANGE, s));
+  if (fork) HIP_TRY(hipStreamWaitEvent(s, ctx->ev_join, 0));  // join before any reader of the slabs
   return RTTDA_OK;
 }
 
@@ -718,12 +732,18 @@ rttda_status rttda_create(const rttda_desc *desc, rttda_ctx **out) {
   }
   hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&ctx->h_pulses), sizeof(DevPulse) * ctx->R);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->upload_ev, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventRecord(ctx->upload_ev, ctx->stream);
   if (e == hipSuccess) e = launch_gaps(ctx->stream, desc->e_occ, desc->e_virt, ctx->o, ctx->v, ctx->D());
   if (e == hipSuccess) e = launch_set_state(ctx->stream, ctx->state(), 0, nullptr, nullptr, nullptr, nullptr, nullptr, 0);
   if (e != hipSuccess) {
     if (ctx->h_pulses) (void)hipHostFree(ctx->h_pulses);
     if (ctx->upload_ev) (void)hipEventDestroy(ctx->upload_ev);
+    if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+    if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+    if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
     delete ctx;
     return fail(RTTDA_E_DEVICE, "create: %s", hipGetErrorString(e));
   }
@@ -734,9 +754,13 @@ rttda_status rttda_create(const rttda_desc *desc, rttda_ctx **out) {
 rttda_status rttda_destroy(rttda_ctx *ctx) {
   if (!ctx) return fail(RTTDA_E_INVAL, "ctx is NULL");
   (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->aux) (void)hipStreamSynchronize(ctx->aux);
   drop_graph(ctx);
   ctx->prof.destroy();
   if (ctx->upload_ev) (void)hipEventDestroy(ctx->upload_ev);
+  if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+  if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+  if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
   if (ctx->h_pulses) (void)hipHostFree(ctx->h_pulses);
   delete ctx;
   return RTTDA_OK;
@@ -799,6 +823,10 @@ rttda_status rttda_set_tuning(rttda_ctx *ctx, const rttda_tuning *t) {
   }
   if (t->exchange_chunk) ctx->qchunk = t->exchange_chunk < 0 ? 0 : t->exchange_chunk;
   if (t->use_graph) ctx->use_graph = t->use_graph;
+  if (t->overlap) {
+    if (t->overlap != 1 && t->overlap != 2) return fail(RTTDA_E_INVAL, "overlap must be 0, 1 or 2");
+    ctx->overlap = t->overlap;
+  }
   if (t->steps_per_graph) ctx->steps_per_graph = t->steps_per_graph;
   drop_graph(ctx);
   return RTTDA_OK;
@@ -812,6 +840,7 @@ rttda_status rttda_get_tuning(const rttda_ctx *ctx, rttda_tuning *t) {
   t->use_graph = ctx->use_graph;
   t->steps_per_graph = ctx->steps_per_graph;
   t->exchange_chunk = ctx->qchunk;
+  t->overlap = ctx->overlap;
   return RTTDA_OK;
 }
 

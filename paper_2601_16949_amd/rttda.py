@@ -49,7 +49,8 @@ class CDesc(ctypes.Structure):
 class CTuning(ctypes.Structure):
     _fields_ = [("exchange_variant", ctypes.c_int32), ("exchange_splits", ctypes.c_int32),
                 ("coulomb_splits", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("steps_per_graph", ctypes.c_int32), ("exchange_chunk", ctypes.c_int32)]
+                ("steps_per_graph", ctypes.c_int32), ("exchange_chunk", ctypes.c_int32),
+                ("overlap", ctypes.c_int32)]
 
 
 class CProfile(ctypes.Structure):
@@ -395,8 +396,9 @@ class Context:
         return int(bad.value)
 
     def set_tuning(self, exchange_variant=0, exchange_splits=0, coulomb_splits=0, use_graph=0, steps_per_graph=0,
-                   exchange_chunk=0):
-        t = CTuning(exchange_variant, exchange_splits, coulomb_splits, use_graph, steps_per_graph, exchange_chunk)
+                   exchange_chunk=0, overlap=0):
+        t = CTuning(exchange_variant, exchange_splits, coulomb_splits, use_graph, steps_per_graph, exchange_chunk,
+                    overlap)
         _check(self.lib.rttda_set_tuning(self.handle, ctypes.byref(t)))
 
     def get_tuning(self) -> dict:
