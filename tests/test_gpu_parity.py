@@ -190,6 +190,25 @@ def test_graph_and_direct_paths_agree(gpu_lib):
     assert np.array_equal(g, d)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "mixed"])
+def test_coulomb_overlap_is_bitwise_neutral(gpu_lib, prec):
+    """The Coulomb pair on its own stream alongside the exchange (the default) and in order on the
+    context's stream give bitwise the same traces and states, for both integrators."""
+    o, v, nq = 24, 96, 64
+    say(f"[overlap] {prec}")
+    prob, op, ctx = setup(I.Shape(o, v, nq, b_scale=0.05, storage="f32" if prec == "fp32" else "bf16"), 771, 2,
+                          prec)
+    pulses = I.kick_pulses(axes=[(0.0, 0.0, 1.0), (1.0, 0.0, 0.0)], kappa=1e-3)
+    for integ in ("rk4", "sso"):
+        out = []
+        for ov in (1, 2):
+            ctx.set_tuning(overlap=ov)
+            c0d, cd = gpu_lib.ground_state(2, o, v)
+            tr = ctx.propagate(pulses, 0.05, 40, c0d, cd, integrator=integ)
+            out.append((tr.cpu().numpy(), cd.cpu().numpy()))
+        assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1]), integ
+
+
 def test_zero_steps_returns_initial_sample(gpu_lib):
     o, v, nq = 8, 20, 10
     prob, op, ctx = setup(I.Shape(o, v, nq), 31, 1)
