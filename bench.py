@@ -38,11 +38,11 @@ TRAFFIC = {
     # scaled by what the same counters read for a plain device copy (2.0 and 1.0), keyed by
     # (variant, workload, Q splits) and tied to the kernel source they were taken on
     ("f32dlp_o64_ws1_wc2", "o60_v400_nq1500_kick_xyz", 238):
-        {"file": "exchange_f32_dl.hip", "src": "70b37e9d80dc794f",
-         "fetch_bytes": 660293.44140625 * 1024 * 2.0, "write_bytes": 139420.484375 * 1024 * 1.0},
+        {"file": "exchange_f32_dl.hip", "src": "d35e655cbb08e573",
+         "fetch_bytes": 662749.1328125 * 1024 * 2.0, "write_bytes": 139445.4609375 * 1024 * 1.0},
     ("bf16x2dlp_o64_ws1_wc2", "o60_v400_nq1500_kick_xyz", 220):
         {"file": "exchange_bf16_dl.hip", "src": "5f96b613372590ac",
-         "fetch_bytes": 251953.77734375 * 1024 * 2.0, "write_bytes": 128934.875 * 1024 * 1.0},
+         "fetch_bytes": 252255.046875 * 1024 * 2.0, "write_bytes": 128937.59765625 * 1024 * 1.0},
     # the GEMM path: one exchange stage is 200 chunks of 25 Q, each a k_xgemm_w + k_boo_w pair
     ("bf16x2gemm_a256x256w8_b256x128w8", "o240_v1800_nq5000_kick_xyz_mixed", 2):
         {"file": "exchange_bf16_gemm.hip", "src": "7dc7d8bb3f4ee411",

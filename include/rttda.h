@@ -277,8 +277,9 @@ typedef struct rttda_tuning {
                                scratch holds W hi/lo for one chunk, so at most what fits);
                                -1 = as many as fit (the default)                           */
   int32_t overlap;          /* 1 = the Coulomb pair runs on a second stream alongside the
-                               exchange (the default), 2 = both in order on the context's
-                               stream                                                       */
+                               exchange, 2 = both in order on the context's stream; the
+                               default is 1 when the exchange has at least 5e10 flops per
+                               stage at max_rhs, else 2                                     */
 } rttda_tuning;
 rttda_status rttda_set_tuning(rttda_ctx *ctx, const rttda_tuning *t);
 rttda_status rttda_get_tuning(const rttda_ctx *ctx, rttda_tuning *t);

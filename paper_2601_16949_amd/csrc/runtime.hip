@@ -52,6 +52,8 @@ rttda_status fail(rttda_status st, const char *fmt, ...) {
 constexpr int MAX_RHS = 4096;
 constexpr int SJ_MAX = 8;    // Coulomb second-product Q splits
 constexpr int SK_MAX = 768;  // exchange Q splits
+// exchange flops per stage (at the largest RHS count) from which the Coulomb pair gets its own stream
+constexpr double OVERLAP_MIN_FLOPS = 5e10;
 // the exchange's partial K slabs (one per split) take at most this much workspace, or 32 slabs
 constexpr size_t SK_SLAB_BYTES = (size_t)256 << 20;
 constexpr size_t ALIGN = 256;
@@ -232,7 +234,7 @@ struct rttda_ctx {
   // MFMA-bound work); fork and join through two events, also inside a captured graph
   hipStream_t aux = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-  int overlap = 1;  // 1: Coulomb pair on the second stream, 2: in order on the context's stream
+  int overlap = 2;  // 1: Coulomb pair on the second stream, 2: in order on the context's stream
   double *corr_next = nullptr;  // time-correlation output of the next propagate call
   double *pops_next = nullptr;  // populations output of the next propagate call, its vectors and count
   const double *popU_next = nullptr;
@@ -729,6 +731,9 @@ rttda_status rttda_create(const rttda_desc *desc, rttda_ctx **out) {
   if (desc->n_aux > 0) {
     ctx->sk = auto_splits(variant_of(ctx->prec, xv), ctx->o, ns_max, ctx->v, ctx->nq, L.sk_max, L);
     ctx->sj = L.sj_max;
+    // the Coulomb pair runs alongside the exchange only where the exchange is long enough to
+    // cover the cost of the fork and join (small problems and many concurrent contexts lose)
+    ctx->overlap = 4.0 * ctx->nq * (double)ctx->ov * (ctx->o + ctx->v) * ctx->R >= OVERLAP_MIN_FLOPS ? 1 : 2;
   }
   hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&ctx->h_pulses), sizeof(DevPulse) * ctx->R);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->upload_ev, hipEventDisableTiming);
