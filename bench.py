@@ -40,9 +40,9 @@ TRAFFIC = {
     ("f32dlp_o64_ws1_wc2", "o60_v400_nq1500_kick_xyz", 238):
         {"file": "exchange_f32_dl.hip", "src": "d35e655cbb08e573",
          "fetch_bytes": 662749.1328125 * 1024 * 2.0, "write_bytes": 139445.4609375 * 1024 * 1.0},
-    ("bf16x2dlp_o64_ws1_wc2", "o60_v400_nq1500_kick_xyz", 220):
-        {"file": "exchange_bf16_dl.hip", "src": "5f96b613372590ac",
-         "fetch_bytes": 252255.046875 * 1024 * 2.0, "write_bytes": 128937.59765625 * 1024 * 1.0},
+    ("bf16x2dlp_o64_ws1_wc2_w8", "o60_v400_nq1500_kick_xyz", 220):
+        {"file": "exchange_bf16_dl.hip", "src": "6c90bb1c00b4e6d1",
+         "fetch_bytes": 259862.15625 * 1024 * 2.0, "write_bytes": 126415.99609375 * 1024 * 1.0},
     # the GEMM path: one exchange stage is 200 chunks of 25 Q, each a k_xgemm_w + k_boo_w pair
     ("bf16x2gemm_a256x256w8_b256x128w8", "o240_v1800_nq5000_kick_xyz_mixed", 2):
         {"file": "exchange_bf16_gemm.hip", "src": "7dc7d8bb3f4ee411",

@@ -57,38 +57,44 @@ __device__ __forceinline__ f16v zero16() {
   return z;
 }
 
-template <int O32, int WS, int WC>
+// NW waves per workgroup: two rows of waves over the slices, NW/2 columns of waves over the
+// B_vv columns; NB LDS buffers (chunks c+1 .. c+NB-2 are in flight while chunk c is multiplied)
+template <int O32, int WS, int WC, int NW = 4, int NB = 3>
 struct CfgBD {
-  static constexpr int KS = 2 * WS, NT = 64 * WC, JB = O32 / 32;
+  static constexpr int NWC = NW / 2, NTH = 64 * NW;
+  static constexpr int KS = 2 * WS, NT = 32 * WC * NWC, JB = O32 / 32;
   static constexpr int XROWS = KS * O32;
-  static constexpr int NXW = XROWS / 64;  // per plane: 16-byte load instructions per wave
-  static constexpr int NBW = NT / 64;
+  static constexpr int NXW = XROWS / (16 * NW);  // per plane: 16-byte load instructions per wave
+  static constexpr int NBW = NT / (16 * NW);
   static constexpr int ODW = O32 * O32 / 2;            // dwords of the B_oo tile
-  static constexpr int NOW = (ODW + 255) / 256;        // 4-byte load instructions per wave
+  static constexpr int NOW = (ODW + NTH - 1) / NTH;    // 4-byte load instructions per wave
   static constexpr int XS = XROWS * KC, BS = NT * KC;  // bf16 per buffer and plane
-  static constexpr int OS = NOW * 256 * 2;             // bf16 (padded to whole instructions)
-  static constexpr size_t LDS = (size_t)(3 * (2 * XS + BS) + OS) * 2;
-  static_assert(XROWS % 64 == 0 && NT % 64 == 0, "tile must split into whole load instructions");
+  static constexpr int OS = NOW * NTH * 2;             // bf16 (padded to whole instructions)
+  static constexpr size_t LDS = (size_t)(NB * (2 * XS + BS) + OS) * 2;
+  static_assert(NW == 4 || NW == 8, "four or eight waves");
+  static_assert(NB == 3 || NB == 4, "three or four LDS buffers");
+  static_assert(XROWS % (16 * NW) == 0 && NT % (16 * NW) == 0, "tile must split into whole load instructions");
 };
 
 // PIPE: half-chunk software pipeline.  The fragments of one 16-wide K step are read from LDS
 // while the matrix cores work on the other step, and the barrier that publishes chunk c+1 sits
 // between the two steps of chunk c, so every LDS read has a batch of MFMAs to hide behind; the
 // loop is specialised once on the number of valid column blocks (no branches on it inside).
-template <int O32, int WS, int WC, bool PIPE>
-__global__ __launch_bounds__(256, 2) void k_exchange_bf16_dl(const __bf16 *__restrict__ Boo,
+template <int O32, int WS, int WC, bool PIPE, int NW, int NB>
+__global__ __launch_bounds__(64 * NW, 8 / NW) void k_exchange_bf16_dl(const __bf16 *__restrict__ Boo,
                                                              const __bf16 *__restrict__ Bvv,
                                                              const __bf16 *__restrict__ Xh,
                                                              const __bf16 *__restrict__ Xl, int o, int v, int nq,
                                                              int ns, int n_sg, int n_ct, int nsplit, float scale,
                                                              float *__restrict__ P) {
-  using C = CfgBD<O32, WS, WC>;
+  using C = CfgBD<O32, WS, WC, NW, NB>;
   constexpr int JB = C::JB, NXW = C::NXW, NBW = C::NBW, NOW = C::NOW, NXB = 2 * NXW + NBW;
+  static_assert(PIPE || (NW == 4 && NB == 3), "the plain loop has four waves and three buffers");
   extern __shared__ __attribute__((aligned(16))) __bf16 ldsbd[];
-  __bf16 *Xh0 = ldsbd;               // [3][XROWS][32]
-  __bf16 *Xl0 = Xh0 + 3 * C::XS;     // [3][XROWS][32]
-  __bf16 *Bs0 = Xl0 + 3 * C::XS;     // [3][NT][32]
-  __bf16 *Os = Bs0 + 3 * C::BS;      // [O32][O32] (+ padding)
+  __bf16 *Xh0 = ldsbd;               // [NB][XROWS][32]
+  __bf16 *Xl0 = Xh0 + NB * C::XS;    // [NB][XROWS][32]
+  __bf16 *Bs0 = Xl0 + NB * C::XS;    // [NB][NT][32]
+  __bf16 *Os = Bs0 + NB * C::BS;     // [O32][O32] (+ padding)
 
   const int total = n_sg * n_ct * nsplit;
   const int per_xcd = (int)gridDim.x / 8;
@@ -104,7 +110,7 @@ __global__ __launch_bounds__(256, 2) void k_exchange_bf16_dl(const __bf16 *__res
   // of the loads; in the plain loop that moves more values into vector registers than fit)
   const int tid = threadIdx.x, lane = tid & 63, wave = PIPE ? __builtin_amdgcn_readfirstlane(tid >> 6) : tid >> 6;
   const int h = lane >> 5, m = lane & 31;
-  const int ws = wave >> 1, wc = wave & 1;
+  const int ws = wave / C::NWC, wc = wave % C::NWC;
   const int nkc = (v + KC - 1) / KC;
   const int NC = (qb - qa) * nkc;
   int nvalid = 0;
@@ -328,7 +334,7 @@ __global__ __launch_bounds__(256, 2) void k_exchange_bf16_dl(const __bf16 *__res
             Wacc[si][jb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(part ? F.l[si][jb] : F.h[si][jb], F.b[cb],
                                                                        Wacc[si][jb][cb], 0, 0, 0);
     };
-    // Per chunk c, after the barrier that publishes it: issue the loads of chunk c+2 (into chunk
+    // Per chunk c, after the barrier that publishes it: issue the loads of chunk c+NB-1 (into chunk
     // c-1's buffer), read K step 0's fragments (F0), run K step 1 of chunk c-1 (F1, read before the
     // barrier) and, at the end of a Q, its K product while they arrive, then the X_hi half of K
     // step 0, then read K step 1's fragments into F1 while the X_lo half runs.  Every LDS wait is
@@ -347,17 +353,18 @@ __global__ __launch_bounds__(256, 2) void k_exchange_bf16_dl(const __bf16 *__res
         for (int jb = 0; jb < JB; ++jb) F1.h[si][jb] = F1.l[si][jb] = bf8{};
       if (NC == 0) return;
       issue_os(qa);
-      issue_at(qa, 0, 0, true);
-      issue_at(qa, 1, 1, true);  // NC >= nkc >= 3
+#pragma unroll
+      for (int b = 0; b < NB - 1; ++b) issue_at(qa, b, b, true);  // NC >= nkc >= 3 >= NB - 1
       const bool tail1 = 16 < v - (nkc - 1) * KC;  // K step 1 of a Q's last chunk lies inside [0, v)
       int kcc = 0, qc = qa, buf = 0;               // chunk c's K chunk, Q index and LDS buffer
       for (int c = 0; c < NC; ++c) {
-        wait_vm<NXB>();  // chunk c (and a B_oo^Q tile issued before it) has landed
+        wait_vm<(NB - 2) * NXB>();  // chunk c (and a B_oo^Q tile issued before it) has landed
         lds_barrier();   // publishes chunk c; every wave has read chunk c-1 and run the last K product
         if (kcc == 1 && c > 1) issue_os(qc);  // chunk c-1 opened Q qc; the K product before it is done
         {
-          const bool wrap = kcc + 2 >= nkc;  // chunk c+2 (nkc >= 3: at most one Q ahead)
-          issue_at(wrap ? qc + 1 : qc, wrap ? kcc + 2 - nkc : kcc + 2, buf == 0 ? 2 : buf - 1, c + 2 < NC);
+          const bool wrap = kcc + NB - 1 >= nkc;  // chunk c+NB-1 (nkc >= 3: at most one Q ahead)
+          issue_at(wrap ? qc + 1 : qc, wrap ? kcc + NB - 1 - nkc : kcc + NB - 1, buf == 0 ? NB - 1 : buf - 1,
+                   c + NB - 1 < NC);
         }
         __builtin_amdgcn_sched_barrier(0);
         read_frag(ncb_tag, buf, 0, F0);
@@ -376,7 +383,7 @@ __global__ __launch_bounds__(256, 2) void k_exchange_bf16_dl(const __bf16 *__res
         __builtin_amdgcn_sched_barrier(0);
         mfma_w(ncb_tag, F0, 1);
         if (++kcc == nkc) { kcc = 0; ++qc; }
-        buf = buf == 2 ? 0 : buf + 1;
+        buf = buf == NB - 1 ? 0 : buf + 1;
       }
       if (tail1) {
         mfma_w(ncb_tag, F1, 0);
@@ -445,38 +452,43 @@ __global__ __launch_bounds__(256, 2) void k_exchange_bf16_dl(const __bf16 *__res
   }
 }
 
-template <int O32, int WS, int WC, bool PIPE>
+template <int O32, int WS, int WC, bool PIPE, int NW, int NB>
 hipError_t launch_xbf16dl(hipStream_t s, const void *Boo, const void *Bvv, const void *X, const void *Xlo, int o,
                           int v, int nq, int ns, int nsplit, float scale, float *P, void *, size_t) {
-  using C = CfgBD<O32, WS, WC>;
+  using C = CfgBD<O32, WS, WC, NW, NB>;
   if (o > O32 || (v & 7) != 0 || (o & 1) != 0 || v < 3 * KC) return hipErrorInvalidValue;
   const int n_sg = (ns + C::KS - 1) / C::KS, n_ct = (v + C::NT - 1) / C::NT;
   const int total = n_sg * n_ct * nsplit;
   dim3 grid((total + 7) / 8 * 8);
-  hipLaunchKernelGGL((k_exchange_bf16_dl<O32, WS, WC, PIPE>), grid, dim3(256), C::LDS, s, static_cast<const __bf16 *>(Boo),
-                     static_cast<const __bf16 *>(Bvv), static_cast<const __bf16 *>(X),
-                     static_cast<const __bf16 *>(Xlo), o, v, nq, ns, n_sg, n_ct, nsplit, scale, P);
+  hipLaunchKernelGGL((k_exchange_bf16_dl<O32, WS, WC, PIPE, NW, NB>), grid, dim3(C::NTH), C::LDS, s,
+                     static_cast<const __bf16 *>(Boo), static_cast<const __bf16 *>(Bvv),
+                     static_cast<const __bf16 *>(X), static_cast<const __bf16 *>(Xlo), o, v, nq, ns, n_sg, n_ct,
+                     nsplit, scale, P);
   return hipGetLastError();
 }
 
-template <int O32, int WS, int WC, bool PIPE>
+template <int O32, int WS, int WC, bool PIPE, int NW, int NB>
 hipError_t prepare_xbf16dl() {
-  return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_exchange_bf16_dl<O32, WS, WC, PIPE>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)CfgBD<O32, WS, WC>::LDS);
+  return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_exchange_bf16_dl<O32, WS, WC, PIPE, NW, NB>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)CfgBD<O32, WS, WC, NW, NB>::LDS);
 }
 
-#define XBD(O32, WS, WC, PIPE, NAME)                                                                        \
+#define XBD(O32, WS, WC, PIPE, NW, NB, NAME)                                                                \
   ExchangeVariant {                                                                                         \
-    RTTDA_PREC_MIXED_BF16, O32, CfgBD<O32, WS, WC>::KS, CfgBD<O32, WS, WC>::NT, NAME,                       \
-        &launch_xbf16dl<O32, WS, WC, PIPE>, CfgBD<O32, WS, WC>::LDS, &prepare_xbf16dl<O32, WS, WC, PIPE>,    \
-        3 * KC, 8, 2, 1, false, PIPE ? 2 : 1                                                                \
+    RTTDA_PREC_MIXED_BF16, O32, CfgBD<O32, WS, WC, NW, NB>::KS, CfgBD<O32, WS, WC, NW, NB>::NT, NAME,       \
+        &launch_xbf16dl<O32, WS, WC, PIPE, NW, NB>, CfgBD<O32, WS, WC, NW, NB>::LDS,                        \
+        &prepare_xbf16dl<O32, WS, WC, PIPE, NW, NB>, 3 * KC, 8, 2, 1, false, PIPE ? 2 : 1                   \
   }
 #define XBD2(O32, WS, WC)                                                                                   \
-  XBD(O32, WS, WC, false, "bf16x2dl_o" #O32 "_ws" #WS "_wc" #WC),                                           \
-      XBD(O32, WS, WC, true, "bf16x2dlp_o" #O32 "_ws" #WS "_wc" #WC)
+  XBD(O32, WS, WC, false, 4, 3, "bf16x2dl_o" #O32 "_ws" #WS "_wc" #WC),                                     \
+      XBD(O32, WS, WC, true, 4, 3, "bf16x2dlp_o" #O32 "_ws" #WS "_wc" #WC)
 
 const ExchangeVariant kBf16DlVariants[] = {
     XBD2(32, 1, 1), XBD2(32, 2, 1), XBD2(64, 1, 1), XBD2(64, 1, 2), XBD2(64, 2, 1),
+    // eight waves (2 x 4) per workgroup, one workgroup per CU: the X tile of a chunk serves twice
+    // the columns, and with four buffers three chunks are in flight
+    XBD(64, 1, 2, true, 8, 3, "bf16x2dlp_o64_ws1_wc2_w8"), XBD(64, 1, 2, true, 8, 4, "bf16x2dlp_o64_ws1_wc2_w8b4"),
+    XBD(32, 2, 2, true, 8, 4, "bf16x2dlp_o32_ws2_wc2_w8b4"),
 };
 
 }  // namespace
