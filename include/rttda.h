@@ -188,7 +188,8 @@ rttda_status rttda_spectrum(void *stream, int32_t kind, const double *signal, in
                             double *out);
 
 /* out[r] = Re <X_r | M_dr | X_r> (f64 [nrhs]) for states c0, c and host unit
- * vectors dir ([nrhs][3]): the observable behind every trace sample. */
+ * vectors dir ([nrhs][3]): the expectation value of the field-coupling operator of
+ * eq. e_field (built by eqs. sc1-sc6), the observable behind every trace sample. */
 rttda_status rttda_dipole_trace(rttda_ctx *ctx, int32_t nrhs, const double *dir, const double *c0,
                                 const double *c, double *out);
 
@@ -199,7 +200,9 @@ rttda_status rttda_dipole_trace(rttda_ctx *ctx, int32_t nrhs, const double *dir,
 rttda_status rttda_guard(rttda_ctx *ctx, int64_t *first_bad_step);
 
 /* ---------------------------------------------------------------------------------------
- * Serving pool: continuous batching of propagation requests on one GPU.
+ * Serving pool: continuous batching of propagation requests on one GPU (the paper runs
+ * each polarisation as a job of its own, Absorption spectrum subsection; here many
+ * molecules and pulses share the device).
  *
  * A request is a context (its operator, workspace and stream) plus states, pulses, dt and
  * a step count.  The pool admits a request when its declared HBM footprint fits the
@@ -232,7 +235,8 @@ rttda_status rttda_pool_release(rttda_pool *pool, int32_t slot);
 /* Budget in use and number of admitted (unreleased) requests. */
 rttda_status rttda_pool_usage(const rttda_pool *pool, size_t *used_bytes, int32_t *active);
 
-/* Estimate the spectral radius of A (Lanczos on the sigma product with a fixed start
+/* Time-step guard for the integrators of the Propagation Algorithm subsection.
+ * Estimate the spectral radius of A (Lanczos on the sigma product with a fixed start
  * vector, n_iter steps, 2 <= n_iter <= 500): *rho is the largest |Ritz value| and
  * *rho_bound adds the Ritz residual of the extreme pairs, so that rho(A) <= rho_bound up
  * to the rounding of the sigma product.  Classic RK4 is stable for rho(A) dt up to about

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "librttda.so")
 OK, E_INVAL, E_NOMEM, E_DEVICE, E_STATE, E_UNSTABLE, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 F64, F32, BF16 = 0, 1, 2
 PREC_FP32, PREC_MIXED_BF16 = 1, 2
-PULSE_NONE, PULSE_DELTA, PULSE_CW, PULSE_GAUSS, PULSE_CHIRP = 0, 1, 2, 3, 4
+PULSE_NONE, PULSE_DELTA, PULSE_CW, PULSE_GAUSS, PULSE_CHIRP, PULSE_DELTA_EXACT = 0, 1, 2, 3, 4, 5
 
 _lib = None
 
@@ -275,8 +275,10 @@ class Context:
         dd = dd / np.linalg.norm(dd, axis=1, keepdims=True)
         dptr = dd.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         self._enter()
-        _check(self.lib.rttda_sigma(self.handle, nrhs, f, dptr, _ptr(c0), _ptr(c), _ptr(s0), _ptr(s)))
-        self._leave()
+        try:
+            _check(self.lib.rttda_sigma(self.handle, nrhs, f, dptr, _ptr(c0), _ptr(c), _ptr(s0), _ptr(s)))
+        finally:
+            self._leave()
         return s0, s
 
     def propagate(self, pulses, dt: float, n_steps: int, c0, c, step0: int = 0, trace=None, norms=None,
@@ -309,10 +311,16 @@ class Context:
             _dev_check(pops, torch.float64, (n_steps + 1, nrhs, k), "pops")
         self._enter()
         try:
-            if corr is not None:
-                _check(self.lib.rttda_set_correlation(self.handle, _ptr(corr)))
-            if pops is not None:
-                _check(self.lib.rttda_set_populations(self.handle, k, _ptr(pop_vectors), _ptr(pops)))
+            try:
+                if corr is not None:
+                    _check(self.lib.rttda_set_correlation(self.handle, _ptr(corr)))
+                if pops is not None:
+                    _check(self.lib.rttda_set_populations(self.handle, k, _ptr(pop_vectors), _ptr(pops)))
+            except RttdaError:
+                # the outputs apply to the next propagate call: none may stay pending for a later one
+                self.lib.rttda_set_correlation(self.handle, None)
+                self.lib.rttda_set_populations(self.handle, 0, None, None)
+                raise
             _check(fn(self.handle, nrhs, cp, float(dt), int(step0), int(n_steps), _ptr(c0), _ptr(c),
                       _ptr(trace) if trace is not None else None, _ptr(norms) if norms is not None else None))
         finally:
@@ -325,8 +333,10 @@ class Context:
         """(rho, rho_bound) of A from n_iter Lanczos steps on the device (rttda_spectral_radius)."""
         rho, bound = ctypes.c_double(), ctypes.c_double()
         self._enter()
-        _check(self.lib.rttda_spectral_radius(self.handle, int(n_iter), ctypes.byref(rho), ctypes.byref(bound)))
-        self._leave()
+        try:
+            _check(self.lib.rttda_spectral_radius(self.handle, int(n_iter), ctypes.byref(rho), ctypes.byref(bound)))
+        finally:
+            self._leave()
         return rho.value, bound.value
 
     def eigen_lowest(self, k: int, m_max: int = 0, max_iter: int = 200, tol: float = 1e-5, want_vectors: bool = True):
@@ -383,9 +393,11 @@ class Context:
         dd = np.ascontiguousarray(np.asarray(dirs, dtype=np.float64).reshape(nrhs, 3))
         dd = dd / np.linalg.norm(dd, axis=1, keepdims=True)
         self._enter()
-        _check(self.lib.rttda_dipole_trace(self.handle, nrhs, dd.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                                           _ptr(c0), _ptr(c), _ptr(out)))
-        self._leave()
+        try:
+            _check(self.lib.rttda_dipole_trace(self.handle, nrhs, dd.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                               _ptr(c0), _ptr(c), _ptr(out)))
+        finally:
+            self._leave()
         return out
 
     def guard(self) -> int:
@@ -460,11 +472,17 @@ def spectrum(signal, dt: float, omega, kappa: float = 1.0, average: bool = False
     import torch
 
     lib = load()
-    omega = np.asarray(omega, dtype=np.float64)
+    omega = np.asarray(omega, dtype=np.float64).reshape(-1)
+    if signal.dim() not in (2, 3) or (signal.dim() == 3 and signal.shape[2] != 2):
+        raise ValueError(f"signal must be [n_t, nsig] or [n_t, nsig, 2], got {tuple(signal.shape)}")
     kind = 0 if signal.dim() == 2 else 1
     n_t, nsig = int(signal.shape[0]), int(signal.shape[1])
     _dev_check(signal, torch.float64, tuple(signal.shape), "signal")
+    if omega.size == 0:
+        raise ValueError("omega must hold at least one frequency")
     dw = float(omega[1] - omega[0]) if omega.size > 1 else 0.0
+    if omega.size > 2 and not np.allclose(np.diff(omega), dw, rtol=1e-9, atol=1e-12 * max(1.0, abs(dw))):
+        raise ValueError("omega must be a uniform grid")
     out = torch.empty((omega.size,) if average else (nsig, omega.size), dtype=torch.float64, device=signal.device)
     st = stream if stream is not None else torch.cuda.current_stream(signal.device)
     _check(lib.rttda_spectrum(st.cuda_stream, kind, _ptr(signal), n_t, nsig, float(dt), float(kappa), int(omega.size),

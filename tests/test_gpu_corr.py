@@ -65,3 +65,15 @@ def test_correlation_applies_to_one_call(gpu_lib):
     torch.cuda.synchronize()
     assert torch.equal(first, corr)
     assert torch.equal(ta, tb) and torch.equal(ca, cb)
+    # a call refused by the binding (65 population vectors, above the limit of 64) leaves no
+    # correlation output pending for the call after it
+    bad_u = torch.zeros((65, o, v), dtype=torch.float64, device="cuda")
+    bad_p = torch.zeros((n + 1, 1, 65), dtype=torch.float64, device="cuda")
+    c0c, cc = gpu_lib.ground_state(1, o, v)
+    with pytest.raises(gpu_lib.RttdaError):
+        ctx.propagate(pulses, 0.05, n, c0c, cc, corr=corr, pops=bad_p, pop_vectors=bad_u)
+    c0d, cd = gpu_lib.ground_state(1, o, v)
+    ctx.propagate(pulses, 0.05, n, c0d, cd)
+    torch.cuda.synchronize()
+    assert torch.equal(first, corr)
+    assert torch.equal(c0c, gpu_lib.ground_state(1, o, v)[0]) and torch.equal(cd, cb)

@@ -61,3 +61,9 @@ def test_spectrum_argument_errors(gpu_lib):
         gpu_lib.spectrum(sig, 0.05, np.linspace(0.1, 1.0, 5), kappa=0.0)
     with pytest.raises(gpu_lib.RttdaError):
         gpu_lib.spectrum(sig, -0.05, np.linspace(0.1, 1.0, 5), kappa=1.0)
+    # the binding refuses what the library cannot check: a correlation without its (re, im)
+    # pair and a frequency grid that is not uniform
+    with pytest.raises(ValueError):
+        gpu_lib.spectrum(torch.zeros((10, 2, 1), dtype=torch.float64, device="cuda"), 0.05, np.linspace(0.1, 1.0, 5))
+    with pytest.raises(ValueError):
+        gpu_lib.spectrum(sig, 0.05, np.array([0.1, 0.2, 0.4]), kappa=1.0)
