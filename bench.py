@@ -36,15 +36,16 @@ AU_FS = 0.02418884326585747
 TRAFFIC = {
     # HBM bytes per exchange launch from rocprofv3 FETCH_SIZE / WRITE_SIZE (KiB per dispatch),
     # scaled by what the same counters read for a plain device copy (2.0 and 1.0), keyed by
-    # (variant, workload, Q splits) and tied to the kernel source they were taken on
-    ("f32dlp_o64_ws1_wc2", "o60_v400_nq1500_kick_xyz", 238):
+    # (variant, workload, Q splits, real slices per launch: 2 per RHS for RK4, 1 for the split
+    # operator) and tied to the kernel source they were taken on
+    ("f32dlp_o64_ws1_wc2", "o60_v400_nq1500_kick_xyz", 238, 6):
         {"file": "exchange_f32_dl.hip", "src": "d35e655cbb08e573",
          "fetch_bytes": 662749.1328125 * 1024 * 2.0, "write_bytes": 139445.4609375 * 1024 * 1.0},
-    ("bf16x2dlp_o64_ws1_wc2_w8", "o60_v400_nq1500_kick_xyz", 220):
+    ("bf16x2dlp_o64_ws1_wc2_w8", "o60_v400_nq1500_kick_xyz", 220, 6):
         {"file": "exchange_bf16_dl.hip", "src": "6c90bb1c00b4e6d1",
          "fetch_bytes": 259862.15625 * 1024 * 2.0, "write_bytes": 126415.99609375 * 1024 * 1.0},
     # the GEMM path: one exchange stage is 200 chunks of 25 Q, each a k_xgemm_w + k_boo_w pair
-    ("bf16x2gemm_a256x256w8_b256x128w8", "o240_v1800_nq5000_kick_xyz_mixed", 2):
+    ("bf16x2gemm_a256x256w8_b256x128w8", "o240_v1800_nq5000_kick_xyz_mixed", 2, 6):
         {"file": "exchange_bf16_gemm.hip", "src": "7dc7d8bb3f4ee411",
          "fetch_bytes": 200 * (631754.39 + 163649.59) * 1024 * 2.0,
          "write_bytes": 200 * (271632.23 + 20838.12) * 1024 * 1.0},
@@ -75,10 +76,10 @@ def make_workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def traffic_for(variant: str, workload: str, splits: int, precision: str):
+def traffic_for(variant: str, workload: str, splits: int, slices: int):
     import hashlib
 
-    e = TRAFFIC.get((variant, workload, splits))
+    e = TRAFFIC.get((variant, workload, splits, slices))
     if not e:
         return None
     src = os.path.join(ROOT, "paper_2601_16949_amd", "csrc", e["file"])
@@ -266,7 +267,7 @@ def main():
         "roofline": {"bound": "mfma", "kernel": "exchange", "achieved": round(achieved, 3), "peak": peak,
                      "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                      "traffic": traffic_for(ctx.variant_name(tun["exchange_variant"]), wl.name,
-                                            tun["exchange_splits"], wl.precision),
+                                            tun["exchange_splits"], 2 * R if args.integrator == "rk4" else R),
                      "avg_launch_us": round(ex_avg_ms * 1e3, 2), "algorithmic_flops_per_launch": ex_flops},
         "kernels": breakdown,
         "guard_bad_step": bad,
