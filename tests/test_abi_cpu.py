@@ -34,6 +34,9 @@ def test_version_and_variants():
     names = [lib.rttda_exchange_variant_name(rttda.PREC_FP32, k).decode() for k in range(1, n + 1)]
     assert all(nm.startswith("f32") for nm in names) and len(set(names)) == len(names)
     assert lib.rttda_exchange_variant_name(rttda.PREC_FP32, n + 1).decode() == ""
+    m = lib.rttda_exchange_variants(rttda.PREC_MIXED_BF16)
+    mixed = [lib.rttda_exchange_variant_name(rttda.PREC_MIXED_BF16, k).decode() for k in range(1, m + 1)]
+    assert m >= 4 and all(nm.startswith("bf16") for nm in mixed) and len(set(mixed)) == m
     assert lib.rttda_exchange_variants(7) == 0
 
 
@@ -71,3 +74,19 @@ def test_create_rejects_null_pointers_before_any_device_work():
     assert st == rttda.E_INVAL
     assert "NULL" in rttda.load().rttda_last_error().decode()
     assert rttda.load().rttda_destroy(None) == rttda.E_INVAL
+
+
+def test_packaged_autotune_choices_name_variants_of_this_build():
+    """Every packaged autotune entry (key p<precision>_o.._v.._nq.._r<nrhs>) names an exchange
+    variant the library has for that precision, with a positive split count."""
+    from paper_2601_16949_amd import autotune
+
+    lib = rttda.load()
+    cache = autotune.load_cache()
+    assert cache
+    for key, e in cache.items():
+        prec = int(key.split("_")[0][1:])
+        names = [lib.rttda_exchange_variant_name(prec, k).decode()
+                 for k in range(1, lib.rttda_exchange_variants(prec) + 1)]
+        assert e["name"] in names, (key, e["name"])
+        assert int(e["splits"]) >= 1
