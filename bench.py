@@ -243,6 +243,8 @@ def main():
     peak = PEAK[wl.precision]
     breakdown = {k: {"launches": d["launches"], "avg_us": round(1e3 * d["ms"] / max(d["launches"], 1), 2),
                      "share": round(d["ms"] / (elapsed * 1e3), 4)} for k, d in prof.items()}
+    traffic = traffic_for(ctx.variant_name(tun["exchange_variant"]), wl.name, tun["exchange_splits"],
+                          2 * R if args.integrator == "rk4" else R)
     out = {
         "metric": "sigma GFLOP/s (% MFMA peak) + fs/hour",
         "value": round(value, 2),
@@ -265,9 +267,9 @@ def main():
         "fs_per_hour": round(fs_h, 3),
         "mfma_frac_step": round(value / 1e3 / peak, 4),
         "roofline": {"bound": "mfma", "kernel": "exchange", "achieved": round(achieved, 3), "peak": peak,
-                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-                     "traffic": traffic_for(ctx.variant_name(tun["exchange_variant"]), wl.name,
-                                            tun["exchange_splits"], 2 * R if args.integrator == "rk4" else R),
+                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": traffic,
+                     # counter bytes over the same launch time, against the 8 TB/s of HBM
+                     "traffic_gbs": round(traffic / (ex_avg_ms * 1e-3) / 1e9, 1) if traffic else None,
                      "avg_launch_us": round(ex_avg_ms * 1e3, 2), "algorithmic_flops_per_launch": ex_flops},
         "kernels": breakdown,
         "guard_bad_step": bad,
