@@ -39,8 +39,8 @@ TRAFFIC = {
     # (variant, workload, Q splits, real slices per launch: 2 per RHS for RK4, 1 for the split
     # operator) and tied to the kernel source they were taken on
     ("f32dlp_o64_ws1_wc2", "o60_v400_nq1500_kick_xyz", 238, 6):
-        {"file": "exchange_f32_dl.hip", "src": "d35e655cbb08e573",
-         "fetch_bytes": 662749.1328125 * 1024 * 2.0, "write_bytes": 139445.4609375 * 1024 * 1.0},
+        {"file": "exchange_f32_dl.hip", "src": "a06a6601420a34af",
+         "fetch_bytes": 662518.34765625 * 1024 * 2.0, "write_bytes": 139470.60546875 * 1024 * 1.0},
     ("bf16x2dlp_o64_ws1_wc2_w8", "o60_v400_nq1500_kick_xyz", 220, 6):
         {"file": "exchange_bf16_dl.hip", "src": "6c90bb1c00b4e6d1",
          "fetch_bytes": 259862.15625 * 1024 * 2.0, "write_bytes": 126415.99609375 * 1024 * 1.0},
@@ -208,7 +208,7 @@ def main():
     if args.variant or args.splits:
         ctx.set_tuning(exchange_variant=args.variant, exchange_splits=args.splits)
     else:
-        tuned = ctx.use_tuned(R)
+        tuned = ctx.use_tuned(R, args.integrator)
     tun = ctx.get_tuning()
     c0, c = rttda.ground_state(R, dev.o, dev.v)
     ctx.propagate(wl.pulses, wl.dt, args.warmup, c0, c, integrator=args.integrator)

@@ -3,7 +3,9 @@
 For a context (one operator, a fixed RHS count), each candidate (variant, splits) runs a few
 propagation steps with the library's per-kernel-class event profiling on, and the candidate
 with the smallest average exchange launch time wins.  Results are cached in a JSON file keyed
-by (precision, o, v, N_Q, nrhs) so later contexts of the same shape reuse the choice.
+by (precision, o, v, N_Q, nrhs, integrator) so later contexts of the same shape reuse the choice:
+the split operator launches the exchange on R real slices instead of RK4's 2R, which favours
+other tiles.
 
     from paper_2601_16949_amd import autotune
     best = autotune.tune(ctx, pulses, dt, nrhs)      # applies the best setting to ctx
@@ -18,9 +20,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_CACHE = os.path.join(HERE, "autotune_cache.json")
 
 
-def _key(ctx, nrhs: int) -> str:
+def _key(ctx, nrhs: int, integrator: str = "rk4") -> str:
     d = ctx.desc
-    return f"p{d.precision}_o{d.n_occ}_v{d.n_virt}_nq{d.n_aux}_r{nrhs}"
+    return f"p{d.precision}_o{d.n_occ}_v{d.n_virt}_nq{d.n_aux}_r{nrhs}" + ("_sso" if integrator == "sso" else "")
 
 
 def load_cache(path: str = DEFAULT_CACHE) -> Dict[str, dict]:
@@ -56,8 +58,8 @@ def apply(ctx, entry: dict) -> bool:
     return True
 
 
-def lookup(ctx, nrhs: int, cache_path: str = DEFAULT_CACHE) -> Optional[dict]:
-    return load_cache(cache_path).get(_key(ctx, nrhs))
+def lookup(ctx, nrhs: int, cache_path: str = DEFAULT_CACHE, integrator: str = "rk4") -> Optional[dict]:
+    return load_cache(cache_path).get(_key(ctx, nrhs, integrator))
 
 
 GEMM_CHUNKS = (0, 6, 12)  # Q per chunk tried for the large-o GEMM path (0 = as many as fit)
@@ -87,13 +89,13 @@ def candidates(ctx, max_per_variant: int = 5) -> List[tuple]:
     return out
 
 
-def measure(ctx, pulses, dt: float, c0, c, steps: int = 3) -> float:
-    """Average time (ms) per RK4 stage of the exchange launch plus the stage epilogue (which
-    reads one partial slab per Q split, so more splits cost there) over `steps` RK4 steps."""
+def measure(ctx, pulses, dt: float, c0, c, steps: int = 3, integrator: str = "rk4") -> float:
+    """Average time (ms) per exchange launch of the exchange plus the epilogue after it (which
+    reads one partial slab per Q split, so more splits cost there) over `steps` steps."""
     import torch
 
     ctx.set_profiling(True)
-    ctx.propagate(pulses, dt, steps, c0, c, want_trace=False)
+    ctx.propagate(pulses, dt, steps, c0, c, want_trace=False, integrator=integrator)
     torch.cuda.synchronize()
     prof = ctx.get_profile()
     ctx.set_profiling(False)
@@ -102,11 +104,11 @@ def measure(ctx, pulses, dt: float, c0, c, steps: int = 3) -> float:
 
 
 def tune(ctx, pulses, dt: float, nrhs: Optional[int] = None, steps: int = 3, cache_path: str = DEFAULT_CACHE,
-         use_cache: bool = True, verbose: bool = False) -> dict:
+         use_cache: bool = True, verbose: bool = False, integrator: str = "rk4") -> dict:
     from . import rttda
 
     nrhs = nrhs or len(pulses)
-    key = _key(ctx, nrhs)
+    key = _key(ctx, nrhs, integrator)
     cache = load_cache(cache_path) if use_cache else {}
     if key in cache:
         best = cache[key]
@@ -119,8 +121,8 @@ def tune(ctx, pulses, dt: float, nrhs: Optional[int] = None, steps: int = 3, cac
             ctx.set_tuning(exchange_variant=k, exchange_splits=s, exchange_chunk=ch or -1)
         except rttda.RttdaError:
             continue
-        measure(ctx, pulses, dt, c0, c, steps=1)  # warm
-        ms = measure(ctx, pulses, dt, c0, c, steps=steps)
+        measure(ctx, pulses, dt, c0, c, steps=1, integrator=integrator)  # warm
+        ms = measure(ctx, pulses, dt, c0, c, steps=steps, integrator=integrator)
         results.append({"variant": k, "name": ctx.variant_name(k), "splits": s, "chunk": ch, "ms": ms})
         if verbose:
             print(f"  {ctx.variant_name(k):34s} splits {s:3d} chunk {ch:3d}: {ms * 1e3:10.1f} us", flush=True)

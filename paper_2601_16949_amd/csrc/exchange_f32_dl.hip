@@ -61,9 +61,12 @@ __device__ __forceinline__ void lds_barrier() {
   asm volatile("s_barrier" ::: "memory");
 }
 
-template <int O16, int WS, int WC, int NB = 3>
+// NWS rows of waves over the slices (2, or 1 for odd slice counts such as the split operator's
+// R real slices), 4 / NWS columns of waves over the B_vv columns
+template <int O16, int WS, int WC, int NB = 3, int NWS = 2>
 struct CfgD {
-  static constexpr int KS = 2 * WS, NT = 32 * WC, JB = O16 / 16;
+  static constexpr int NWC = 4 / NWS;
+  static constexpr int KS = NWS * WS, NT = 16 * WC * NWC, JB = O16 / 16;
   static constexpr int XROWS = KS * O16;
   static constexpr int NXW = XROWS / 64;  // X load instructions per wave (16 rows each, 4 waves)
   static constexpr int NBW = NT / 64;     // B_vv load instructions per wave
@@ -80,14 +83,14 @@ struct CfgD {
 // issued two chunks ahead; 2 the same over two buffers, loads one chunk ahead (less LDS, so four
 // workgroups fit a CU).
 // OCC: workgroups per CU the register budget is sized for (2, or 3 where three fit the LDS).
-template <int O16, int WS, int WC, int PIPE, int OCC>
+template <int O16, int WS, int WC, int PIPE, int OCC, int NWS>
 __global__ __launch_bounds__(256, OCC) void k_exchange_f32_dl(const float *__restrict__ Boo,
                                                          const float *__restrict__ Bvv,
                                                          const float *__restrict__ X, int o, int v, int nq, int ns,
                                                          int n_sg, int n_ct, int nsplit, float scale,
                                                          float *__restrict__ P) {
   constexpr int NB = PIPE == 2 ? 2 : 3;
-  using C = CfgD<O16, WS, WC, NB>;
+  using C = CfgD<O16, WS, WC, NB, NWS>;
   constexpr int JB = C::JB, NXW = C::NXW, NBW = C::NBW, NOW = C::NOW, NXB = NXW + NBW;
   extern __shared__ __attribute__((aligned(16))) float ldsd[];
   float *Xs0 = ldsd;                 // [NB][XROWS][16]
@@ -107,7 +110,7 @@ __global__ __launch_bounds__(256, OCC) void k_exchange_f32_dl(const float *__res
   // (the two-buffer form holds the wave index in a scalar register, and with it the LDS destinations)
   const int tid = threadIdx.x, lane = tid & 63, wave = PIPE == 2 ? __builtin_amdgcn_readfirstlane(tid >> 6) : tid >> 6;
   const int g = lane >> 4, n = lane & 15;
-  const int ws = wave >> 1, wc = wave & 1;
+  const int ws = wave / C::NWC, wc = wave % C::NWC;
   const int nkc = (v + KC - 1) / KC;
   const int NC = (qb - qa) * nkc;
   int nvalid = 0;  // column blocks of this wave inside [0, v): WC, or fewer in the last tile
@@ -461,33 +464,34 @@ __global__ __launch_bounds__(256, OCC) void k_exchange_f32_dl(const float *__res
   }
 }
 
-template <int O16, int WS, int WC, int PIPE, int OCC>
+template <int O16, int WS, int WC, int PIPE, int OCC, int NWS>
 hipError_t launch_xf32dl(hipStream_t s, const void *Boo, const void *Bvv, const void *X, const void *, int o, int v,
                          int nq, int ns, int nsplit, float scale, float *P, void *, size_t) {
-  using C = CfgD<O16, WS, WC, PIPE == 2 ? 2 : 3>;
+  using C = CfgD<O16, WS, WC, PIPE == 2 ? 2 : 3, NWS>;
   if (o > O16 || (v & 3) != 0 || (o & 3) != 0 || v < 3 * KC) return hipErrorInvalidValue;
   const int n_sg = (ns + C::KS - 1) / C::KS, n_ct = (v + C::NT - 1) / C::NT;
   const int total = n_sg * n_ct * nsplit;
   dim3 grid((total + 7) / 8 * 8);
-  hipLaunchKernelGGL((k_exchange_f32_dl<O16, WS, WC, PIPE, OCC>), grid, dim3(256), C::LDS, s, static_cast<const float *>(Boo),
-                     static_cast<const float *>(Bvv), static_cast<const float *>(X), o, v, nq, ns, n_sg, n_ct, nsplit,
-                     scale, P);
+  hipLaunchKernelGGL((k_exchange_f32_dl<O16, WS, WC, PIPE, OCC, NWS>), grid, dim3(256), C::LDS, s,
+                     static_cast<const float *>(Boo), static_cast<const float *>(Bvv), static_cast<const float *>(X), o,
+                     v, nq, ns, n_sg, n_ct, nsplit, scale, P);
   return hipGetLastError();
 }
 
-template <int O16, int WS, int WC, int PIPE, int OCC>
+template <int O16, int WS, int WC, int PIPE, int OCC, int NWS>
 hipError_t prepare_xf32dl() {
-  return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_exchange_f32_dl<O16, WS, WC, PIPE, OCC>),
+  return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_exchange_f32_dl<O16, WS, WC, PIPE, OCC, NWS>),
                              hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)CfgD<O16, WS, WC, PIPE == 2 ? 2 : 3>::LDS);
+                             (int)CfgD<O16, WS, WC, PIPE == 2 ? 2 : 3, NWS>::LDS);
 }
 
-#define XDL(O16, WS, WC, PIPE, OCC, NAME)                                                                \
+#define XDLS(O16, WS, WC, PIPE, OCC, NWS, NAME)                                                          \
   ExchangeVariant {                                                                                      \
-    RTTDA_PREC_FP32, O16, CfgD<O16, WS, WC>::KS, CfgD<O16, WS, WC>::NT, NAME,                            \
-        &launch_xf32dl<O16, WS, WC, PIPE, OCC>, CfgD<O16, WS, WC, PIPE == 2 ? 2 : 3>::LDS,                \
-        &prepare_xf32dl<O16, WS, WC, PIPE, OCC>, 3 * KC, 4, 4, 1, false, PIPE ? 2 : 1                    \
+    RTTDA_PREC_FP32, O16, CfgD<O16, WS, WC, 3, NWS>::KS, CfgD<O16, WS, WC, 3, NWS>::NT, NAME,            \
+        &launch_xf32dl<O16, WS, WC, PIPE, OCC, NWS>, CfgD<O16, WS, WC, PIPE == 2 ? 2 : 3, NWS>::LDS,      \
+        &prepare_xf32dl<O16, WS, WC, PIPE, OCC, NWS>, 3 * KC, 4, 4, 1, false, PIPE ? 2 : 1              \
   }
+#define XDL(O16, WS, WC, PIPE, OCC, NAME) XDLS(O16, WS, WC, PIPE, OCC, 2, NAME)
 #define XDL2(O16, WS, WC)                                                                                \
   XDL(O16, WS, WC, 0, 2, "f32dl_o" #O16 "_ws" #WS "_wc" #WC),                                            \
       XDL(O16, WS, WC, 1, 2, "f32dlp_o" #O16 "_ws" #WS "_wc" #WC)
@@ -496,6 +500,8 @@ hipError_t prepare_xf32dl() {
 const ExchangeVariant kF32DlVariants[] = {
     XDL2(32, 1, 2), XDL2(32, 2, 2), XDL2(48, 2, 2), XDL2(64, 1, 2), XDL2(64, 2, 2), XDL2(64, 1, 4), XDL2(96, 1, 2),
     XDL(64, 1, 2, 2, 4, "f32dlq_o64_ws1_wc2"),
+    // one slice per workgroup, four columns of waves (odd slice counts: no idle slice row)
+    XDLS(64, 1, 2, 1, 2, 1, "f32dlp_o64_ws1_wc2_s1"), XDLS(64, 1, 1, 1, 2, 1, "f32dlp_o64_ws1_wc1_s1"),
 };
 
 }  // namespace

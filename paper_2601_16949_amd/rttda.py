@@ -424,11 +424,11 @@ class Context:
         _check(self.lib.rttda_exchange_splits_max(self.handle, ctypes.byref(n)))
         return max(1, int(n.value))
 
-    def use_tuned(self, nrhs: int) -> bool:
-        """Apply the packaged autotune choice for (shape, nrhs) if there is one."""
+    def use_tuned(self, nrhs: int, integrator: str = "rk4") -> bool:
+        """Apply the packaged autotune choice for (shape, nrhs, integrator) if there is one."""
         from . import autotune
 
-        e = autotune.lookup(self, nrhs)
+        e = autotune.lookup(self, nrhs, integrator=integrator)
         return bool(e) and autotune.apply(self, e)
 
     def set_profiling(self, on: bool):

@@ -132,3 +132,29 @@ def test_sso_isolated_kick_peaks_at_modified_eigenvalues(gpu_lib):
             d = min(abs(q - w) for q, _ in pk)
             say(f"   modified eig {w:.8f}: nearest GPU peak {d:.2e} Ha away")
             assert d < 1e-5
+
+
+@pytest.mark.parametrize("prec", ["fp32", "mixed"])
+def test_sso_every_exchange_variant_odd_slices(gpu_lib, prec):
+    """The split operator launches the exchange on R real slices (here 3, odd): every tile
+    variant that holds o, at one and at three Q splits, gives the oracle's split-operator trace."""
+    o, v, nq, n = 40, 104, 9, 20
+    shape = I.Shape(o, v, nq, storage="f32" if prec == "fp32" else "bf16")
+    op, ctx = setup(shape, 777, 3, prec)
+    pulses = I.kick_pulses(kappa=1e-2)
+    refs = [O.propagate_sso(op, p, 0.05, n)[0] for p in pulses]
+    tol = 1e-5 if prec == "fp32" else 1e-4
+    tried = 0
+    for k in range(1, ctx.lib.rttda_exchange_variants(ctx.desc.precision) + 1):
+        for splits in (1, 3):
+            try:
+                ctx.set_tuning(exchange_variant=k, exchange_splits=splits)
+            except gpu_lib.RttdaError:
+                continue
+            say(f"[sso variant] {ctx.variant_name(k)} splits {splits} {prec}")
+            got, _, _ = run(gpu_lib, ctx, pulses, 0.05, n, o, v)
+            for r in range(3):
+                err = rel(got[:, r], refs[r])
+                assert err < tol, (ctx.variant_name(k), splits, r, err)
+            tried += 1
+    assert tried >= 4
