@@ -42,8 +42,8 @@ TRAFFIC = {
         {"file": "exchange_f32_dl.hip", "src": "a06a6601420a34af",
          "fetch_bytes": 662518.34765625 * 1024 * 2.0, "write_bytes": 139470.60546875 * 1024 * 1.0},
     ("bf16x2dlp_o64_ws1_wc2_w8", "o60_v400_nq1500_kick_xyz", 220, 6):
-        {"file": "exchange_bf16_dl.hip", "src": "6c90bb1c00b4e6d1",
-         "fetch_bytes": 259862.15625 * 1024 * 2.0, "write_bytes": 126415.99609375 * 1024 * 1.0},
+        {"file": "exchange_bf16_dl.hip", "src": "c660feeaed33f7d9",
+         "fetch_bytes": 260366.92578125 * 1024 * 2.0, "write_bytes": 126374.82421875 * 1024 * 1.0},
     # the GEMM path: one exchange stage is 200 chunks of 25 Q, each a k_xgemm_w + k_boo_w pair
     ("bf16x2gemm_a256x256w8_b256x128w8", "o240_v1800_nq5000_kick_xyz_mixed", 2, 6):
         {"file": "exchange_bf16_gemm.hip", "src": "7dc7d8bb3f4ee411",

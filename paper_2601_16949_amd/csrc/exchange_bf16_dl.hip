@@ -57,12 +57,13 @@ __device__ __forceinline__ f16v zero16() {
   return z;
 }
 
-// NW waves per workgroup: two rows of waves over the slices, NW/2 columns of waves over the
-// B_vv columns; NB LDS buffers (chunks c+1 .. c+NB-2 are in flight while chunk c is multiplied)
-template <int O32, int WS, int WC, int NW = 4, int NB = 3>
+// NW waves per workgroup: NWS rows of waves over the slices (2, or 1 for odd slice counts such
+// as the split operator's R real slices), NW/NWS columns of waves over the B_vv columns; NB LDS
+// buffers (chunks c+1 .. c+NB-2 are in flight while chunk c is multiplied)
+template <int O32, int WS, int WC, int NW = 4, int NB = 3, int NWS = 2>
 struct CfgBD {
-  static constexpr int NWC = NW / 2, NTH = 64 * NW;
-  static constexpr int KS = 2 * WS, NT = 32 * WC * NWC, JB = O32 / 32;
+  static constexpr int NWC = NW / NWS, NTH = 64 * NW;
+  static constexpr int KS = NWS * WS, NT = 32 * WC * NWC, JB = O32 / 32;
   static constexpr int XROWS = KS * O32;
   static constexpr int NXW = XROWS / (16 * NW);  // per plane: 16-byte load instructions per wave
   static constexpr int NBW = NT / (16 * NW);
@@ -80,14 +81,14 @@ struct CfgBD {
 // while the matrix cores work on the other step, and the barrier that publishes chunk c+1 sits
 // between the two steps of chunk c, so every LDS read has a batch of MFMAs to hide behind; the
 // loop is specialised once on the number of valid column blocks (no branches on it inside).
-template <int O32, int WS, int WC, bool PIPE, int NW, int NB>
+template <int O32, int WS, int WC, bool PIPE, int NW, int NB, int NWS>
 __global__ __launch_bounds__(64 * NW, 8 / NW) void k_exchange_bf16_dl(const __bf16 *__restrict__ Boo,
                                                              const __bf16 *__restrict__ Bvv,
                                                              const __bf16 *__restrict__ Xh,
                                                              const __bf16 *__restrict__ Xl, int o, int v, int nq,
                                                              int ns, int n_sg, int n_ct, int nsplit, float scale,
                                                              float *__restrict__ P) {
-  using C = CfgBD<O32, WS, WC, NW, NB>;
+  using C = CfgBD<O32, WS, WC, NW, NB, NWS>;
   constexpr int JB = C::JB, NXW = C::NXW, NBW = C::NBW, NOW = C::NOW, NXB = 2 * NXW + NBW;
   static_assert(PIPE || (NW == 4 && NB == 3), "the plain loop has four waves and three buffers");
   extern __shared__ __attribute__((aligned(16))) __bf16 ldsbd[];
@@ -452,33 +453,34 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void k_exchange_bf16_dl(const __bf
   }
 }
 
-template <int O32, int WS, int WC, bool PIPE, int NW, int NB>
+template <int O32, int WS, int WC, bool PIPE, int NW, int NB, int NWS>
 hipError_t launch_xbf16dl(hipStream_t s, const void *Boo, const void *Bvv, const void *X, const void *Xlo, int o,
                           int v, int nq, int ns, int nsplit, float scale, float *P, void *, size_t) {
-  using C = CfgBD<O32, WS, WC, NW, NB>;
+  using C = CfgBD<O32, WS, WC, NW, NB, NWS>;
   if (o > O32 || (v & 7) != 0 || (o & 1) != 0 || v < 3 * KC) return hipErrorInvalidValue;
   const int n_sg = (ns + C::KS - 1) / C::KS, n_ct = (v + C::NT - 1) / C::NT;
   const int total = n_sg * n_ct * nsplit;
   dim3 grid((total + 7) / 8 * 8);
-  hipLaunchKernelGGL((k_exchange_bf16_dl<O32, WS, WC, PIPE, NW, NB>), grid, dim3(C::NTH), C::LDS, s,
+  hipLaunchKernelGGL((k_exchange_bf16_dl<O32, WS, WC, PIPE, NW, NB, NWS>), grid, dim3(C::NTH), C::LDS, s,
                      static_cast<const __bf16 *>(Boo), static_cast<const __bf16 *>(Bvv),
                      static_cast<const __bf16 *>(X), static_cast<const __bf16 *>(Xlo), o, v, nq, ns, n_sg, n_ct,
                      nsplit, scale, P);
   return hipGetLastError();
 }
 
-template <int O32, int WS, int WC, bool PIPE, int NW, int NB>
+template <int O32, int WS, int WC, bool PIPE, int NW, int NB, int NWS>
 hipError_t prepare_xbf16dl() {
-  return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_exchange_bf16_dl<O32, WS, WC, PIPE, NW, NB>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)CfgBD<O32, WS, WC, NW, NB>::LDS);
+  return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_exchange_bf16_dl<O32, WS, WC, PIPE, NW, NB, NWS>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)CfgBD<O32, WS, WC, NW, NB, NWS>::LDS);
 }
 
-#define XBD(O32, WS, WC, PIPE, NW, NB, NAME)                                                                \
+#define XBDS(O32, WS, WC, PIPE, NW, NB, NWS, NAME)                                                          \
   ExchangeVariant {                                                                                         \
-    RTTDA_PREC_MIXED_BF16, O32, CfgBD<O32, WS, WC, NW, NB>::KS, CfgBD<O32, WS, WC, NW, NB>::NT, NAME,       \
-        &launch_xbf16dl<O32, WS, WC, PIPE, NW, NB>, CfgBD<O32, WS, WC, NW, NB>::LDS,                        \
-        &prepare_xbf16dl<O32, WS, WC, PIPE, NW, NB>, 3 * KC, 8, 2, 1, false, PIPE ? 2 : 1                   \
+    RTTDA_PREC_MIXED_BF16, O32, CfgBD<O32, WS, WC, NW, NB, NWS>::KS, CfgBD<O32, WS, WC, NW, NB, NWS>::NT,    \
+        NAME, &launch_xbf16dl<O32, WS, WC, PIPE, NW, NB, NWS>, CfgBD<O32, WS, WC, NW, NB, NWS>::LDS,        \
+        &prepare_xbf16dl<O32, WS, WC, PIPE, NW, NB, NWS>, 3 * KC, 8, 2, 1, false, PIPE ? 2 : 1              \
   }
+#define XBD(O32, WS, WC, PIPE, NW, NB, NAME) XBDS(O32, WS, WC, PIPE, NW, NB, 2, NAME)
 #define XBD2(O32, WS, WC)                                                                                   \
   XBD(O32, WS, WC, false, 4, 3, "bf16x2dl_o" #O32 "_ws" #WS "_wc" #WC),                                     \
       XBD(O32, WS, WC, true, 4, 3, "bf16x2dlp_o" #O32 "_ws" #WS "_wc" #WC)
@@ -489,6 +491,8 @@ const ExchangeVariant kBf16DlVariants[] = {
     // the columns, and with four buffers three chunks are in flight
     XBD(64, 1, 2, true, 8, 3, "bf16x2dlp_o64_ws1_wc2_w8"), XBD(64, 1, 2, true, 8, 4, "bf16x2dlp_o64_ws1_wc2_w8b4"),
     XBD(32, 2, 2, true, 8, 4, "bf16x2dlp_o32_ws2_wc2_w8b4"),
+    // one slice per workgroup, four columns of waves (odd slice counts: no idle slice row)
+    XBDS(64, 1, 2, true, 4, 3, 1, "bf16x2dlp_o64_ws1_wc2_s1"), XBDS(64, 1, 1, true, 4, 3, 1, "bf16x2dlp_o64_ws1_wc1_s1"),
 };
 
 }  // namespace
