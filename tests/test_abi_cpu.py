@@ -90,3 +90,19 @@ def test_packaged_autotune_choices_name_variants_of_this_build():
                  for k in range(1, lib.rttda_exchange_variants(prec) + 1)]
         assert e["name"] in names, (key, e["name"])
         assert int(e["splits"]) >= 1
+
+
+def test_autotune_keys_carry_the_integrator():
+    """RK4 and the split operator launch the exchange on 2R and R slices, so their tuned choices
+    are kept apart; the packaged split-operator entries name the same shapes as RK4 ones."""
+    from types import SimpleNamespace
+
+    from paper_2601_16949_amd import autotune
+
+    ctx = SimpleNamespace(desc=SimpleNamespace(precision=1, n_occ=60, n_virt=400, n_aux=1500))
+    assert autotune._key(ctx, 3) == "p1_o60_v400_nq1500_r3"
+    assert autotune._key(ctx, 3, "sso") == "p1_o60_v400_nq1500_r3_sso"
+    cache = autotune.load_cache()
+    for key in cache:
+        if key.endswith("_sso"):
+            assert key[: -len("_sso")] in cache, key
