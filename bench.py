@@ -169,7 +169,7 @@ def main():
                     help="only run a plain device copy of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is a design "
+        print(json.dumps({"error": "bench.py runs on one GPU; --gpus must be 1 (multi-GPU sharding is a design "
                                    "note only)"}))
         sys.exit(2)
 

@@ -59,7 +59,7 @@ typedef enum {
   RTTDA_E_DEVICE = -3,      /* a HIP runtime call failed                                    */
   RTTDA_E_STATE = -4,       /* context in the wrong state (e.g. destroyed, no kernel)      */
   RTTDA_E_UNSTABLE = -5,    /* norm guard tripped: non-finite or growing amplitudes        */
-  RTTDA_E_UNSUPPORTED = -6  /* shape or option not supported by this build                 */
+  RTTDA_E_UNSUPPORTED = -6  /* shape or option this library does not support             */
 } rttda_status;
 
 typedef enum { RTTDA_F64 = 0, RTTDA_F32 = 1, RTTDA_BF16 = 2 } rttda_dtype;
@@ -269,7 +269,7 @@ rttda_status rttda_populations(rttda_ctx *ctx, int32_t k, const double *evecs, i
                                void *work, size_t work_bytes, double *out);
 
 /* Launch configuration knobs (for the autotuner).  Zero fields keep the
- * library's choice.  Returns RTTDA_E_UNSUPPORTED for a tile variant this build
+ * library's choice.  Returns RTTDA_E_UNSUPPORTED for a tile variant the library
  * does not have, RTTDA_E_NOMEM when the splits do not fit the workspace. */
 typedef struct rttda_tuning {
   int32_t exchange_variant; /* index into the exchange tile table (1-based), 0 = auto      */

@@ -40,7 +40,7 @@ def save_cache(cache: Dict[str, dict], path: str = DEFAULT_CACHE):
 
 
 def variant_index(ctx, name: str) -> int:
-    """1-based index of the exchange variant called `name` in this build (0 if absent)."""
+    """1-based index of the exchange variant called `name` in the loaded library (0 if absent)."""
     n = ctx.lib.rttda_exchange_variants(ctx.desc.precision)
     for k in range(1, n + 1):
         if ctx.variant_name(k) == name:
@@ -49,7 +49,7 @@ def variant_index(ctx, name: str) -> int:
 
 
 def apply(ctx, entry: dict) -> bool:
-    """Apply a cached (variant name, splits[, Q chunk]) choice; False if this build lacks the variant."""
+    """Apply a cached (variant name, splits[, Q chunk]) choice; False if the loaded library lacks the variant."""
     k = variant_index(ctx, entry["name"])
     if not k:
         return False
