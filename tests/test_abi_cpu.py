@@ -106,3 +106,34 @@ def test_autotune_keys_carry_the_integrator():
     for key in cache:
         if key.endswith("_sso"):
             assert key[: -len("_sso")] in cache, key
+
+
+def test_serving_stream_and_footprint_host_logic():
+    """The serving workload stream (o ~ U{10..48} here, v = floor(7.5 o), N_Q = 20 o, Poisson
+    arrivals) and the footprint used for admission: increasing arrival times, the stated size
+    rules, and a footprint that covers the factors, the library's own workspace and the state."""
+    import math
+
+    import numpy as np
+
+    from paper_2601_16949_amd import inputs as I
+    from paper_2601_16949_amd import serve
+
+    reqs = I.serving_requests(400, rate=20.0, o_min=10, o_max=48)
+    t = np.array([r.arrival for r in reqs])
+    assert np.all(np.diff(t) > 0)
+    gaps = np.diff(np.concatenate([[0.0], t]))
+    assert abs(gaps.mean() - 1 / 20.0) < 0.2 / 20.0  # exponential gaps of mean 1/rate
+    for r in reqs:
+        o = r.shape.o
+        assert 10 <= o <= 48 and r.shape.v == math.floor(7.5 * o) and r.shape.nq == 20 * o
+        assert 500 <= r.n_steps <= 8000 and r.shape.storage == "bf16"
+        assert r.pulse.kind in (I.PULSE_DELTA, I.PULSE_GAUSS)
+    kinds = [r.pulse.kind for r in reqs]
+    assert 0.4 < kinds.count(I.PULSE_DELTA) / len(kinds) < 0.6
+    sh = reqs[0].shape
+    fp = serve.footprint(sh, 1000, "mixed")
+    ws = rttda.workspace_bytes(sh.o, sh.v, sh.nq, "mixed", 1)
+    factors = sh.nq * (sh.o * sh.v + sh.o ** 2 + sh.v ** 2) * 2
+    assert fp >= ws + factors + 2 * sh.o * sh.v * 8 + 1001 * 8
+    assert serve.footprint(sh, 2000, "mixed") - fp == 1000 * 8
