@@ -44,6 +44,12 @@ TRAFFIC = {
     ("bf16x2dlp_o64_ws1_wc2_w8", "o60_v400_nq1500_kick_xyz", 220, 6):
         {"file": "exchange_bf16_dl.hip", "src": "c660feeaed33f7d9",
          "fetch_bytes": 260366.92578125 * 1024 * 2.0, "write_bytes": 126374.82421875 * 1024 * 1.0},
+    ("f32dlp_o64_ws1_wc1_s1", "o60_v400_nq1500_kick_xyz", 466, 3):
+        {"file": "exchange_f32_dl.hip", "src": "a06a6601420a34af",
+         "fetch_bytes": 507411.29375 * 1024 * 2.0, "write_bytes": 139592.9125 * 1024 * 1.0},
+    ("f32dlp_o48_ws2_wc2", "o40_v300_nq1000_gauss_cos_scan64", 40, 128):
+        {"file": "exchange_f32_dl.hip", "src": "a06a6601420a34af",
+         "fetch_bytes": 10195717.9765625 * 1024 * 2.0, "write_bytes": 264620.1328125 * 1024 * 1.0},
     # the GEMM path: one exchange stage is 200 chunks of 25 Q, each a k_xgemm_w + k_boo_w pair
     ("bf16x2gemm_a256x256w8_b256x128w8", "o240_v1800_nq5000_kick_xyz_mixed", 2, 6):
         {"file": "exchange_bf16_gemm.hip", "src": "7dc7d8bb3f4ee411",
