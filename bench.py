@@ -38,6 +38,9 @@ TRAFFIC = {
     # scaled by what the same counters read for a plain device copy (2.0 and 1.0), keyed by
     # (variant, workload, Q splits, real slices per launch: 2 per RHS for RK4, 1 for the split
     # operator) and tied to the kernel source they were taken on
+    ("f32dlq_o64_ws1_wc2", "o60_v400_nq1500_kick_xyz", 357, 6):
+        {"file": "exchange_f32_dl.hip", "src": "a06a6601420a34af",
+         "fetch_bytes": 666769.640625 * 1024 * 2.0, "write_bytes": 210734.49609375 * 1024 * 1.0},
     ("f32dlp_o64_ws1_wc2", "o60_v400_nq1500_kick_xyz", 238, 6):
         {"file": "exchange_f32_dl.hip", "src": "a06a6601420a34af",
          "fetch_bytes": 662518.34765625 * 1024 * 2.0, "write_bytes": 139470.60546875 * 1024 * 1.0},
