@@ -137,3 +137,26 @@ def test_serving_stream_and_footprint_host_logic():
     factors = sh.nq * (sh.o * sh.v + sh.o ** 2 + sh.v ** 2) * 2
     assert fp >= ws + factors + 2 * sh.o * sh.v * 8 + 1001 * 8
     assert serve.footprint(sh, 2000, "mixed") - fp == 1000 * 8
+
+
+def test_pool_host_logic_without_device_work():
+    """The serving pool's bookkeeping needs no device: an empty pool reports zero use, steps
+    nothing, refuses unknown slots and NULL arguments with RTTDA_E_INVAL, and is destroyed."""
+    lib = rttda.load()
+    h = ctypes.c_void_p()
+    assert lib.rttda_pool_create(1 << 30, ctypes.byref(h)) == rttda.OK
+    used, active = ctypes.c_size_t(7), ctypes.c_int32(7)
+    assert lib.rttda_pool_usage(h, ctypes.byref(used), ctypes.byref(active)) == rttda.OK
+    assert used.value == 0 and active.value == 0
+    issued = ctypes.c_int32(-1)
+    assert lib.rttda_pool_step(h, 10, ctypes.byref(issued)) == rttda.OK and issued.value == 0
+    assert lib.rttda_pool_step(h, 0, None) == rttda.E_INVAL
+    done, fin = ctypes.c_int64(), ctypes.c_int32()
+    assert lib.rttda_pool_poll(h, 0, ctypes.byref(done), ctypes.byref(fin)) == rttda.E_INVAL
+    assert lib.rttda_pool_release(h, 3) == rttda.E_INVAL
+    slot = ctypes.c_int32()
+    assert lib.rttda_pool_admit(h, None, 1, None, 0.05, 10, rttda.INTEG_RK4, None, None, None, 0,
+                                ctypes.byref(slot)) == rttda.E_INVAL
+    assert lib.rttda_pool_create(1, None) == rttda.E_INVAL
+    assert lib.rttda_pool_destroy(h) == rttda.OK
+    assert lib.rttda_pool_destroy(None) == rttda.E_INVAL
