@@ -6,7 +6,13 @@ contraction, the field/trace product and the FP64 epilogue) for all right-hand s
 workload, inputs resident in HBM.  Default workload: o=60, v=400, N_Q=1500, x/y/z delta kicks as
 3 right-hand sides, dt = 0.05 au, FP32 factors (synthetic, seeded).
 
-    python bench.py [--steps K] [--warmup W] [--workload cfg2|cfg1|cfg4]
+    python bench.py [--steps K] [--warmup W] [--workload cfg2|cfg1|cfg3|cfg4]
+                    [--precision fp32|mixed] [--integrator rk4|sso] [--graph-compare]
+
+cfg1: o10 v40 N_Q120, z kick; cfg3: o240 v1800 N_Q5000, x/y/z kicks, split BF16; cfg4: o40
+v300 N_Q1000, 64 Gaussian-pulse carriers.  With --integrator sso a step is one split-operator
+step (2 real sigma).  The default run adds the FP32 oracle timed on the host cores on a bounded
+sample (cpu_baseline) and the batched-mixed against plain-FP32-single comparison.
 
 Prints one JSON line.  The timed region brackets exactly K steps with device synchronisation;
 per-kernel-class durations come from HIP events recorded by the library on its stream inside
