@@ -11,7 +11,7 @@ workload, inputs resident in HBM.  Default workload: o=60, v=400, N_Q=1500, x/y/
 
 cfg1: o10 v40 N_Q120, z kick; cfg3: o240 v1800 N_Q5000, x/y/z kicks, split BF16; cfg4: o40
 v300 N_Q1000, 64 Gaussian-pulse carriers.  With --integrator sso a step is one split-operator
-step (2 real sigma).  The default run adds the FP32 oracle timed on the host cores on a bounded
+step (2 real sigma).  The default run adds the FP64 oracle timed on the host cores on a bounded
 sample (cpu_baseline) and the batched-mixed against plain-FP32-single comparison.
 
 Prints one JSON line.  The timed region brackets exactly K steps with device synchronisation;
