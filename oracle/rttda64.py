@@ -42,15 +42,35 @@ FWHM_TO_SIGMA = 2.35482
 PULSE_NONE, PULSE_DELTA, PULSE_CW, PULSE_GAUSS, PULSE_CHIRP, PULSE_DELTA_EXACT = 0, 1, 2, 3, 4, 5
 
 
+class BF16Stored:
+    """Factors kept as their stored BF16 bit patterns (uint16, [N_Q, ...]) and read back as FP64
+    one range of Q at a time, for shapes whose FP64 copy would not fit in host memory.  A BF16
+    value is the upper half of the FP32 with the same bits, so the read is exact."""
+
+    def __init__(self, bits: np.ndarray):
+        if bits.dtype != np.uint16:
+            raise TypeError("BF16Stored takes uint16 bit patterns")
+        self.bits = bits
+        self.shape = bits.shape
+
+    def __getitem__(self, index):
+        return (self.bits[index].astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def _factor(b):
+    return b if isinstance(b, BF16Stored) else np.asarray(b, dtype=np.float64)
+
+
 class Operator:
-    """FP64 copies of the stored inputs of one molecule."""
+    """FP64 copies of the stored inputs of one molecule (factors also as BF16Stored, read per Q
+    range)."""
 
     def __init__(self, e_occ, e_virt, b_ov, b_oo, b_vv, mu, cx):
         self.e_occ = np.asarray(e_occ, dtype=np.float64)
         self.e_virt = np.asarray(e_virt, dtype=np.float64)
-        self.b_ov = np.asarray(b_ov, dtype=np.float64)
-        self.b_oo = np.asarray(b_oo, dtype=np.float64)
-        self.b_vv = np.asarray(b_vv, dtype=np.float64)
+        self.b_ov = _factor(b_ov)
+        self.b_oo = _factor(b_oo)
+        self.b_vv = _factor(b_vv)
         self.mu = np.asarray(mu, dtype=np.float64)
         self.cx = float(cx)
         self.o = self.e_occ.shape[0]
@@ -70,20 +90,28 @@ def orbital_gaps(op: Operator) -> np.ndarray:
     return op.e_virt[None, :] - op.e_occ[:, None]
 
 
-def coulomb(op: Operator, C: np.ndarray) -> np.ndarray:
-    """J_ia = 2 sum_jb (ia|jb) C_jb with (ia|jb) = sum_Q B^Q_ia B^Q_jb."""
-    d = np.einsum("qjb,jb->q", op.b_ov, C)
-    return 2.0 * np.einsum("q,qia->ia", d, op.b_ov)
+def coulomb(op: Operator, C: np.ndarray, q_chunk: int = 256) -> np.ndarray:
+    """J_ia = 2 sum_jb (ia|jb) C_jb with (ia|jb) = sum_Q B^Q_ia B^Q_jb, as
+    d_Q = sum_jb B^Q_jb C_jb and J = 2 sum_Q d_Q B^Q, the sum over Q taken a range of Q at a time.
+    C may carry leading dimensions (several real planes at once)."""
+    J = np.zeros_like(C)
+    for q0 in range(0, op.nq, q_chunk):
+        B = op.b_ov[q0:min(op.nq, q0 + q_chunk)]
+        d = np.einsum("qjb,...jb->...q", B, C)
+        J += 2.0 * np.einsum("...q,qia->...ia", d, B)
+    return J
 
 
 def exchange(op: Operator, C: np.ndarray, q_chunk: int = 64) -> np.ndarray:
-    """K_ia = sum_jb (ij|ab) C_jb = sum_Q (B^Q_oo C B^Q_vv)_ia, (ij|ab) = sum_Q B^Q_ij B^Q_ab."""
-    K = np.zeros_like(C)
+    """K_ia = sum_jb (ij|ab) C_jb = sum_Q (B^Q_oo C B^Q_vv)_ia, (ij|ab) = sum_Q B^Q_ij B^Q_ab.
+    C may carry one leading dimension (several real planes at once)."""
+    Cb = C.reshape((-1,) + C.shape[-2:])  # (planes, o, v)
+    K = np.zeros_like(Cb)
     for q0 in range(0, op.nq, q_chunk):
         q1 = min(op.nq, q0 + q_chunk)
-        V = np.matmul(op.b_oo[q0:q1], C)  # (nq_chunk, o, v)
-        K += np.matmul(V, op.b_vv[q0:q1]).sum(axis=0)
-    return K
+        V = np.matmul(op.b_oo[q0:q1][:, None], Cb[None])  # (nq_chunk, planes, o, v)
+        K += np.matmul(V, op.b_vv[q0:q1][:, None]).sum(axis=0)
+    return K.reshape(C.shape)
 
 
 def apply_A_real(op: Operator, C: np.ndarray) -> np.ndarray:
@@ -91,9 +119,11 @@ def apply_A_real(op: Operator, C: np.ndarray) -> np.ndarray:
 
 
 def apply_A(op: Operator, C: np.ndarray) -> np.ndarray:
-    """A is real, so it acts on the real and imaginary parts of C separately."""
+    """A is real, so it acts on the real and imaginary parts of C separately (both planes in one
+    pass over the factors)."""
     if np.iscomplexobj(C):
-        return apply_A_real(op, C.real) + 1j * apply_A_real(op, C.imag)
+        planes = apply_A_real(op, np.stack([C.real, C.imag]))
+        return planes[0] + 1j * planes[1]
     return apply_A_real(op, C)
 
 
@@ -468,6 +498,78 @@ class EigenRoute:
             return trace, y
         return trace
 
+    def field_free_trace_blocked(self, pulse, dt: float, n_steps: int, c0=1.0 + 0j, C=None, block: int = 256):
+        """The same trace as propagate_field_free, trace[n] = Re <X_n | M | X_n> with the exact
+        field-free RK4 map y_n = R(-i w dt)^n y_0, evaluated for large ov: each block of steps is
+        taken back to the amplitude basis, X_n = U y_n (one matrix product per block), and M acts
+        there in its factorised form (apply_dipole), so the dense eigenbasis dipole U^T M U is
+        never formed."""
+        if C is None:
+            C = np.zeros((self.op.o, self.op.v), dtype=np.complex128)
+        blocks = dipole_blocks(self.op, pulse.direction)
+        if pulse.kind in (PULSE_DELTA, PULSE_DELTA_EXACT):
+            c0, C = apply_kick(self.op, blocks, pulse, complex(c0), np.asarray(C, dtype=np.complex128))
+        elif pulse.kind != PULSE_NONE:
+            raise ValueError("field-free route takes only delta or no pulse")
+        y = self.to_eig(c0, C)
+        R = rk4_amplification(-1j * self.w * dt)
+        logR = np.log(R)
+        Uexc = self.U[1:, 1:]
+        o, v = self.op.o, self.op.v
+        trace = np.empty(n_steps + 1)
+        for n0 in range(0, n_steps + 1, block):
+            n = np.arange(n0, min(n_steps + 1, n0 + block))
+            Y = np.exp(np.outer(n, logR)) * y[None, :]  # rows: y_n = R^n y_0
+            Xc = (Y[:, 1:].real @ Uexc.T) + 1j * (Y[:, 1:].imag @ Uexc.T)  # amplitudes C_n (rows)
+            for k in range(n.size):
+                trace[n[k]] = dipole_expectation(blocks, Y[k, 0], Xc[k].reshape(o, v))
+        return trace
+
+    def propagate_rk4_many(self, pulses, dt: float, n_steps: int, n_pop: int = 0, pop_every: int = 1):
+        """RK4 with fields for several right-hand sides that share one polarisation, run in the
+        eigenbasis from the ground state (after any delta kick), all RHS as the columns of one
+        matrix.  Returns (trace [n_steps+1, R], pops) where pops [n_samples, R, 1 + n_pop] holds
+        |y_0|^2 and the populations |y_I|^2 of the n_pop lowest TI-TDA states (eq. populations) at
+        steps 0, pop_every, 2 pop_every, ..."""
+        d = np.asarray(pulses[0].direction, dtype=np.float64)
+        for p in pulses:
+            if not np.array_equal(np.asarray(p.direction, dtype=np.float64), d):
+                raise ValueError("propagate_rk4_many takes pulses of one polarisation")
+        blocks = dipole_blocks(self.op, d)
+        Rn = len(pulses)
+        Y = np.empty((self.w.size, Rn), dtype=np.complex128)
+        for r, p in enumerate(pulses):
+            c0, C = apply_kick(self.op, blocks, p, 1.0 + 0j, np.zeros((self.op.o, self.op.v), dtype=np.complex128))
+            Y[:, r] = self.to_eig(c0, C)
+        Me = self.dipole_eig(d)
+        w = self.w[:, None]
+
+        def fields(t):
+            return np.array([field_value(p, t) for p in pulses])
+
+        def f(t, Y, MY=None):
+            if MY is None:
+                MY = Me @ Y
+            return -1j * (w * Y - fields(t)[None, :] * MY)
+
+        n_samp = n_steps // pop_every + 1
+        trace = np.empty((n_steps + 1, Rn))
+        pops = np.empty((n_samp, Rn, 1 + n_pop))
+        MY = Me @ Y
+        for n in range(n_steps + 1):
+            trace[n] = np.real(np.sum(np.conj(Y) * MY, axis=0))
+            if n % pop_every == 0:
+                pops[n // pop_every] = (np.abs(Y[:1 + n_pop]) ** 2).T
+            if n == n_steps:
+                break
+            k1 = f(n * dt, Y, MY)
+            k2 = f((n + 0.5) * dt, Y + 0.5 * dt * k1)
+            k3 = f((n + 0.5) * dt, Y + 0.5 * dt * k2)
+            k4 = f((n + 1.0) * dt, Y + dt * k3)
+            Y = Y + dt / 6.0 * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
+            MY = Me @ Y
+        return trace, pops
+
     def propagate_rk4(self, pulse, dt: float, n_steps: int, c0=1.0 + 0j, C=None):
         """RK4 with a field, run in the eigenbasis (RK4 commutes with the change of basis)."""
         if C is None:
@@ -492,6 +594,23 @@ class EigenRoute:
             y = y + dt / 6.0 * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
             trace[n + 1] = float(np.real(np.conj(y) @ (Me @ y)))
         return trace, y
+
+
+def linear_kick_trace(w, z, kappa: float, dt: float, n_steps: int, chunk: int = 512) -> np.ndarray:
+    """The part of the field-free dipole trace after a first-order kick of strength kappa from the
+    ground state that is linear in kappa: with eigenvalues w_J of A and z_J = <U_J, sqrt2 mu_ov.d>
+    (the ground-excited dipole elements of the eigenstates), the kicked state in the eigenbasis is
+    y_0 = e_0 + i kappa z, the RK4 map multiplies y_J by R(-i w_J dt) per step, and
+        mu(t_n) = -2 kappa sum_J z_J^2 Im R(-i w_J dt)^n + O(kappa^2).
+    The O(kappa^2) remainder is the excited-excited dipole of the response (not included)."""
+    w = np.asarray(w, dtype=np.float64)
+    wts = np.asarray(z, dtype=np.float64) ** 2
+    logR = np.log(rk4_amplification(-1j * w * dt))
+    out = np.empty(n_steps + 1)
+    for n0 in range(0, n_steps + 1, chunk):
+        n = np.arange(n0, min(n_steps + 1, n0 + chunk))
+        out[n] = -2.0 * kappa * (np.exp(np.outer(n, logR)).imag @ wts)
+    return out
 
 
 # ----------------------------------------------------------------------------------------

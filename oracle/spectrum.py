@@ -94,6 +94,49 @@ def peaks(trace, dt: float, kappa: float, rel_height: float = 0.05, omega_max: f
     return pk
 
 
+def correlation_spectrum(corr, dt: float, omega) -> np.ndarray:
+    """The spectrum of a time-correlation function (eq. time_correlation_function) by the paper's
+    omega-weighted transform (eq. fourier_transform), with the same half-Hann window as the dipole
+    spectrum:  R(omega) = omega Re sum_n h_n R_n exp(i omega t_n) dt  for each omega (un-gridded).
+    For R_n = sum_I |y_I|^2 r_I^n with |r_I| = 1, r_I = exp(-i w_I dt), the terms peak at w_I."""
+    corr = np.asarray(corr, dtype=np.complex128)
+    omega = np.atleast_1d(np.asarray(omega, dtype=np.float64))
+    s = corr * window(corr.size)
+    t = np.arange(corr.size) * dt
+    out = np.empty(omega.size)
+    for k, om in enumerate(omega):
+        out[k] = om * float(np.real(np.sum(s * np.exp(1j * om * t)))) * dt
+    return out
+
+
+def correlation_peaks(corr, dt: float, omega, rel_height: float = 0.05, refine: bool = True):
+    """Local maxima of correlation_spectrum on the grid omega (at least rel_height of the largest),
+    each refined by maximising the un-gridded transform within one grid step (golden section)."""
+    omega = np.asarray(omega, dtype=np.float64)
+    S = correlation_spectrum(corr, dt, omega)
+    out = []
+    for om, h in find_peaks(omega, S, rel_height=rel_height):
+        if refine:
+            g = (math.sqrt(5.0) - 1.0) / 2.0
+            dw = omega[1] - omega[0]
+            a, b = om - dw, om + dw
+            c, d = b - g * (b - a), a + g * (b - a)
+            fc, fd = correlation_spectrum(corr, dt, c)[0], correlation_spectrum(corr, dt, d)[0]
+            while b - a > 1e-10:
+                if fc > fd:
+                    b, d, fd = d, c, fc
+                    c = b - g * (b - a)
+                    fc = correlation_spectrum(corr, dt, c)[0]
+                else:
+                    a, c, fc = c, d, fd
+                    d = a + g * (b - a)
+                    fd = correlation_spectrum(corr, dt, d)[0]
+            om = 0.5 * (a + b)
+            h = correlation_spectrum(corr, dt, om)[0]
+        out.append((om, h))
+    return out
+
+
 def resolution(total_time_au: float) -> float:
     """Frequency resolution 2 pi / T in Ha."""
     return 2.0 * math.pi / total_time_au

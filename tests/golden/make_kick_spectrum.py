@@ -2,11 +2,9 @@
 
 Calls only the FP64 oracle and the seeded input generator.  Route: dense A (explicit DF
 sums), eigh, and the first-order (linear in kappa) dipole trace of the exact RK4 map in the
-eigenbasis,
-    mu(t_n) = -2 kappa sum_J z_J^2 Im R(-i w_J dt)^n,   z = U^T (sqrt2 mu_ov . d),
-which is the full trace minus its O(kappa^2) part (a smooth background that moves peak
-positions by far less than 1e-6 Ha).  Peaks come from oracle.spectrum (same post-processing
-as applied to GPU traces).
+eigenbasis (oracle.rttda64.linear_kick_trace), which is the full trace minus its O(kappa^2)
+part (a smooth background that moves peak positions by far less than 1e-6 Ha).  Peaks come from
+oracle.spectrum (same post-processing as applied to GPU traces).
 
     python tests/golden/make_kick_spectrum.py cfg2
 """
@@ -22,18 +20,6 @@ sys.path.insert(0, ROOT)
 from oracle import rttda64 as O  # noqa: E402
 from oracle import spectrum as S  # noqa: E402
 from paper_2601_16949_amd import inputs as I  # noqa: E402
-
-
-def linear_trace(w, z, kappa, dt, n_steps, chunk=512):
-    R = O.rk4_amplification(-1j * w * dt)
-    logR = np.log(R)
-    out = np.empty(n_steps + 1)
-    wts = z * z
-    for n0 in range(0, n_steps + 1, chunk):
-        n = np.arange(n0, min(n_steps + 1, n0 + chunk))
-        Rn = np.exp(np.outer(n, logR))
-        out[n] = -2.0 * kappa * (Rn.imag @ wts)
-    return out
 
 
 def main(name):
@@ -54,7 +40,7 @@ def main(name):
     for r, p in enumerate(wl.pulses):
         _, mov, _ = O.dipole_blocks(op, p.direction)
         z = U.T @ (np.sqrt(2.0) * mov.reshape(-1))
-        tr = linear_trace(w, z, p.e0, wl.dt, wl.n_steps)
+        tr = O.linear_kick_trace(w, z, p.e0, wl.dt, wl.n_steps)
         pk = S.peaks(tr, wl.dt, p.e0, rel_height=0.05, omega_max=8.0)
         for om, h in pk:
             lines.append(f"{r} {om:.10f} {h:.6e}")

@@ -1,6 +1,6 @@
 """Device spectra (rttda_spectrum, eq. fourier_transform and eq. spectrum_average) of GPU dipole
-traces and time correlations against the test harness's transform of the same signals (FP64 on
-both sides).  (The signals themselves are checked against the oracle elsewhere: traces in the
+traces and time correlations against the oracle's transforms of the same signals
+(oracle.spectrum.dtft and oracle.spectrum.correlation_spectrum, FP64 on both sides).  (The signals themselves are checked against the oracle elsewhere: traces in the
 parity tests, correlations in test_gpu_corr.)"""
 import numpy as np
 import pytest
@@ -38,15 +38,12 @@ def test_spectra_match_the_transform_definition(gpu_lib):
     C = gpu_lib.spectrum(corr, dt, omega).cpu().numpy()
     torch.cuda.synchronize()
     trh, ch = tr.cpu().numpy(), corr.cpu().numpy()
-    h = SP.window(n + 1)
-    t = np.arange(n + 1) * dt
     worst = 0.0
     for s in range(3):
         for j in range(0, omega.size, 50):
             ref = SP.dtft(trh[:, s], dt, kappa, omega[j])
             worst = max(worst, abs(S[s, j] - ref) / np.max(np.abs(S[s])))
-            z = np.sum(h * (ch[:, s, 0] + 1j * ch[:, s, 1]) * np.exp(1j * omega[j] * t)) * dt
-            refc = omega[j] * z.real
+            refc = SP.correlation_spectrum(ch[:, s, 0] + 1j * ch[:, s, 1], dt, omega[j])[0]
             worst = max(worst, abs(C[s, j] - refc) / np.max(np.abs(C[s])))
     say(f"[spectrum] worst relative deviation from the transform definition {worst:.2e}")
     assert worst < 1e-10

@@ -600,3 +600,156 @@ def test_exact_kick_unitary_second_order_and_group():
     assert 6.5 < errs[0] / errs[1] < 9.5  # third order
     b0, B = O.kick_exact(op, d, 0.1, *O.kick_exact(op, d, 0.2, c0, C))
     assert abs(b0 - a0) < 1e-13 and np.max(np.abs(B - A)) < 1e-13
+
+
+# ------------------------------------------------------------------------------------------
+# Chirped pulse (eq. chirped_pulse): the carrier's instantaneous frequency is omega + beta tau
+# ------------------------------------------------------------------------------------------
+def _zero_crossings(f, a, b, n=20000):
+    """Roots of f on [a, b]: sign changes on a fine grid, each refined by bisection."""
+    t = np.linspace(a, b, n + 1)
+    y = np.array([f(x) for x in t])
+    out = []
+    for k in np.where(np.sign(y[:-1]) * np.sign(y[1:]) < 0)[0]:
+        lo, hi = t[k], t[k + 1]
+        flo = y[k]
+        for _ in range(80):
+            mid = 0.5 * (lo + hi)
+            fm = f(mid)
+            if np.sign(fm) == np.sign(flo):
+                lo, flo = mid, fm
+            else:
+                hi = mid
+        out.append(0.5 * (lo + hi))
+    return np.array(out)
+
+
+def test_chirp_instantaneous_frequency():
+    """A linear chirp of rate beta: the local carrier frequency at tau = t - t0 is omega + beta tau
+    (the text after the pulse equations: a time-dependent frequency).  Read off the zero crossings
+    of E(t) found numerically: half a period around tau is pi / (omega + beta tau).  A rate of
+    beta/2 or 2 beta in the phase would give pi / (omega + beta tau / 2) or pi / (omega + 2 beta tau)."""
+    w, beta, t0 = 0.5, 2e-3, 300.0
+    p = pulse(I.PULSE_CHIRP, e0=1.0, omega=w, t0=t0, fwhm=1e9, beta=beta)  # flat envelope
+    # (grid ends off the root at tau = 0, so no grid point falls on a zero)
+    z = _zero_crossings(lambda t: O.field_value(p, t), t0 - 150.0 + 1e-3 * np.sqrt(2.0), t0 + 150.0)
+    assert z.size > 20
+    mids = 0.5 * (z[1:] + z[:-1]) - t0
+    half = np.diff(z)
+    pred = np.pi / (w + beta * mids)
+    # the spacing of consecutive roots equals pi over the frequency at their midpoint up to O(beta^2)
+    assert np.max(np.abs(half - pred) / pred) < 2e-3
+    # the frequency changes across the window: beta tau reaches 0.3 of omega at the edges
+    wrong = np.pi / (w + 0.5 * beta * mids)
+    assert np.max(np.abs(half - wrong) / wrong) > 5e-2
+    # the Gaussian envelope is that of the transform-limited pulse (eq. transform_limited)
+    g = pulse(I.PULSE_GAUSS, e0=0.02, omega=0.5, t0=400.0, fwhm=400.0, phase=0.3)
+    c = pulse(I.PULSE_CHIRP, e0=0.02, omega=0.5, t0=400.0, fwhm=400.0, beta=0.0, phase=0.3)
+    for t in (0.0, 123.0, 400.0, 777.0):
+        assert O.field_value(c, t) == O.field_value(g, t)
+
+
+# ------------------------------------------------------------------------------------------
+# Correlation spectrum (eq. time_correlation_function, eq. fourier_transform)
+# ------------------------------------------------------------------------------------------
+def test_correlation_spectrum_peaks_at_rk4_frequencies():
+    """R(omega) = omega F[R(t)] of the oracle's correlation function after a kick: its peaks sit at
+    the RK4-modified excitation energies -arg r(-i w_I dt)/dt (eigenvalues of the dense A), and
+    their heights follow w_I |y_I|^2, |y_I|^2 being the weight of eigenstate I in the kicked state."""
+    op = tiny_op(o=2, v=3, nq=2, scale=0.2)
+    route = O.EigenRoute(op)
+    d = (0.0, 0.0, 1.0)
+    kappa, dt, n = 0.05, 0.2, 20000
+    p = pulse(I.PULSE_DELTA, e0=kappa, direction=d)
+    corr = O.propagate_correlation(op, p, dt, n)
+    blocks = O.dipole_blocks(op, d)
+    c0, C = O.kick(blocks, kappa, 1.0 + 0j, np.zeros((2, 3), complex))
+    weight = np.abs(route.to_eig(c0, C)[1:]) ** 2
+    wI = route.w[1:]
+    wt = -np.angle(O.rk4_amplification(-1j * wI * dt)) / dt
+    grid = np.arange(0.2, 3.0, 2e-3)
+    pk = S.correlation_peaks(corr, dt, grid, rel_height=0.05)
+    strength = wt * weight
+    expect = [k for k in range(wI.size) if strength[k] >= 0.1 * strength.max()]
+    assert len(expect) >= 2
+    for k in expect:
+        assert min(abs(om - wt[k]) for om, _ in pk) < 1e-6, (wt[k], pk)
+    # on its own peak, term I contributes w_I |y_I|^2 sum_n h_n |r_I|^n dt (the RK4 map shrinks each
+    # mode by |r_I| <= 1 per step); the ground state (weight ~1, frequency 0) adds w dt/2, the
+    # endpoint term of the sum (h_0 = 1 at t = 0), and the other modes leak far less
+    hn = S.window(n + 1)
+    y0 = abs(route.to_eig(c0, C)[0]) ** 2
+    for k in expect:
+        damp = np.sum(hn * np.abs(O.rk4_amplification(-1j * wI[k] * dt)) ** np.arange(n + 1)) * dt
+        h = S.correlation_spectrum(corr, dt, wt[k])[0] - wt[k] * 0.5 * dt * y0
+        assert abs(h - strength[k] * damp) < 2e-3 * strength[k] * damp, (k, h, strength[k] * damp)
+
+
+# ------------------------------------------------------------------------------------------
+# Linear-in-kappa kick trace and the blocked field-free trace (eigen route O2 variants)
+# ------------------------------------------------------------------------------------------
+def test_linear_kick_trace_is_the_odd_part_of_the_full_trace():
+    """The first-order kick makes the state affine in kappa, so the trace is a + b kappa + c kappa^2
+    exactly and (trace(kappa) - trace(-kappa)) / 2 is its linear part b kappa."""
+    op = tiny_op(o=2, v=4, nq=3)
+    route = O.EigenRoute(op)
+    d = (0.6, 0.0, 0.8)
+    kappa, dt, n = 0.03, 0.05, 400
+    tp = route.propagate_field_free(pulse(I.PULSE_DELTA, e0=kappa, direction=d), dt, n)
+    tm = route.propagate_field_free(pulse(I.PULSE_DELTA, e0=-kappa, direction=d), dt, n)
+    _, mov, _ = O.dipole_blocks(op, d)
+    z = route.U[1:, 1:].T @ (np.sqrt(2.0) * mov.reshape(-1))
+    lin = O.linear_kick_trace(route.w[1:], z, kappa, dt, n)
+    odd = 0.5 * (tp - tm)
+    assert np.max(np.abs(lin - odd)) < 1e-13 * np.max(np.abs(odd))
+    assert np.max(np.abs(tp - lin)) > 1e-4 * np.max(np.abs(lin))  # the kappa^2 part is there
+
+
+def test_field_free_trace_blocked_equals_eigen_and_direct_routes():
+    op = tiny_op(o=3, v=5, nq=4)
+    route = O.EigenRoute(op)
+    p = pulse(I.PULSE_DELTA, e0=1e-2, direction=(0.0, 0.6, 0.8))
+    dt, n = 0.05, 700
+    t1, _, _ = O.propagate(op, p, dt, n)
+    t2 = route.propagate_field_free(p, dt, n)
+    t3 = route.field_free_trace_blocked(p, dt, n, block=64)
+    scale = np.max(np.abs(t1))
+    assert np.max(np.abs(t3 - t2)) < 1e-12 * scale
+    assert np.max(np.abs(t3 - t1)) < 1e-11 * scale
+
+
+def test_propagate_rk4_many_equals_single_routes_and_populations():
+    """The batched field route against the single-RHS eigen route (itself equal to the direct route,
+    P7), and its populations against the projection of the direct route's state."""
+    op = tiny_op(o=2, v=4, nq=3)
+    route = O.EigenRoute(op)
+    d = (0.0, 0.0, 1.0)
+    pulses = [pulse(I.PULSE_GAUSS, e0=0.05, omega=w, t0=3.0, fwhm=4.0, phase=np.pi / 2, direction=d)
+              for w in (0.4, 0.9)] + [pulse(I.PULSE_DELTA, e0=1e-2, direction=d)]
+    dt, n = 0.05, 160
+    tr, pops = route.propagate_rk4_many(pulses, dt, n, n_pop=3, pop_every=40)
+    assert pops.shape == (5, 3, 4)
+    w3, U3 = O.lowest_states(op, 3)
+    for r, p in enumerate(pulses):
+        ref, _ = route.propagate_rk4(p, dt, n)
+        np.testing.assert_allclose(tr[:, r], ref, atol=1e-13)
+        t1, c0, C = O.propagate(op, p, dt, n)
+        np.testing.assert_allclose(pops[-1, r], O.state_populations(U3, c0, C), atol=1e-12)
+        assert np.max(pops[:, r, 1:]) > 1e-6
+    with pytest.raises(ValueError):
+        route.propagate_rk4_many([pulses[0], pulse(I.PULSE_GAUSS, e0=0.05, omega=0.4, direction=(1, 0, 0))], dt, 2)
+
+
+def test_bf16_stored_factors_read_back_exactly():
+    """Factors kept as BF16 bit patterns read back as the same FP64 values as the BF16-rounded
+    arrays, so the streamed operator and the in-memory one give the same sigma."""
+    shape = I.Shape(3, 8, 5, b_scale=0.05, storage="bf16")
+    prob = I.make_problem(shape, 31)
+    op = O.Operator.from_problem(prob)
+    ops = O.Operator(prob.e_occ, prob.e_virt, O.BF16Stored(I.bf16_bits(prob.b_ov)),
+                     O.BF16Stored(I.bf16_bits(prob.b_oo)), O.BF16Stored(I.bf16_bits(prob.b_vv)), prob.mu, prob.cx)
+    assert np.array_equal(ops.b_vv[1:4], op.b_vv[1:4])
+    C = I.random_state(3, 8, 1, seed=3)[1][0]
+    np.testing.assert_array_equal(O.apply_A(ops, C), O.apply_A(op, C))
+    with pytest.raises(TypeError):
+        O.BF16Stored(prob.b_ov)
