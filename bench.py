@@ -103,8 +103,9 @@ def traffic_for(variant: str, workload: str, splits: int, slices: int):
     return e["fetch_bytes"] + e["write_bytes"]
 
 
-def cpu_baseline(wl, prob, budget_s: float):
-    """The FP64 oracle (direct route) timed on this host's cores on a bounded sample."""
+def oracle_run(wl, prob, pulses, budget_s: float, max_steps: int = 1000):
+    """The FP64 oracle's direct route from the ground state (after the kicks) for as many RK4 steps
+    of all RHS as fit in budget_s: (trace [steps+1, R], steps, seconds, BLAS threads)."""
     from oracle import rttda64 as O
 
     try:
@@ -114,32 +115,63 @@ def cpu_baseline(wl, prob, budget_s: float):
     except Exception:  # pragma: no cover
         cores = os.cpu_count() or 1
     op = O.Operator.from_problem(prob)
-    R = len(wl.pulses)
-    fc, fx = flops_per_sigma(prob.o, prob.v, prob.nq)
-    steps = 0
+    states, trace = [], [[]]
     t0 = time.perf_counter()
-    states = []
-    for p in wl.pulses:
+    for p in pulses:
         blocks = O.dipole_blocks(op, p.direction)
-        c0, C = O.kick(blocks, p.e0, 1.0 + 0j, np.zeros((prob.o, prob.v), complex)) if p.kind == I.PULSE_DELTA \
-            else (1.0 + 0j, np.zeros((prob.o, prob.v), complex))
+        c0, C = O.apply_kick(op, blocks, p, 1.0 + 0j, np.zeros((prob.o, prob.v), complex))
         states.append([blocks, c0, C])
+        trace[0].append(O.dipole_expectation(blocks, c0, C))
+    steps = 0
     while True:
-        for r, p in enumerate(wl.pulses):
+        row = []
+        for r, p in enumerate(pulses):
             blocks, c0, C = states[r]
             states[r][1], states[r][2] = O.rk4_step(op, blocks, p, wl.dt, steps, c0, C)
+            row.append(O.dipole_expectation(blocks, states[r][1], states[r][2]))
+        trace.append(row)
         steps += 1
         el = time.perf_counter() - t0
-        if el > budget_s or steps >= 1000:
+        if el > budget_s or steps >= max_steps:
             break
+    return np.array(trace), steps, el, int(cores)
+
+
+def cpu_baseline(wl, prob, budget_s: float):
+    """The FP64 oracle (direct route) timed on this host's cores on a bounded sample; its trace is
+    kept for the error of the GPU result against it."""
+    R = len(wl.pulses)
+    tr, steps, el, cores = oracle_run(wl, prob, wl.pulses, budget_s)
+    fc, fx = flops_per_sigma(prob.o, prob.v, prob.nq)
     gflops = steps * R * 4 * (fc + fx) / el / 1e9
     fs_h = steps * wl.dt * AU_FS * R / (el / 3600.0)
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        nproc = os.cpu_count() or 1
     return {"value": round(gflops, 3), "unit": "sigma GFLOP/s (FP64)", "cores": int(cores), "kind": "oracle",
-            "sample": f"{steps} RK4 steps x {R} RHS of {wl.name} ({el:.1f} s)", "fs_per_hour": round(fs_h, 4)}
+            "nproc": nproc,
+            "sample": f"{steps} RK4 steps x {R} RHS of {wl.name} ({el:.1f} s, NumPy FP64 over {cores} BLAS threads)",
+            "fs_per_hour": round(fs_h, 4)}, tr
 
 
-def short_leg(wl, precision: str, pulses, steps: int, warmup: int = 5):
-    """Aggregate fs/hour and sigma GFLOP/s of a short timed run (comparison legs)."""
+def trace_error(ctx, wl, pulses, ref):
+    """max |mu_gpu - mu_oracle| / max |mu_oracle| over the oracle's steps, the GPU run from a fresh
+    ground state on the same context (the launch configuration of the timed run)."""
+    import torch
+    from paper_2601_16949_amd import rttda
+
+    n = ref.shape[0] - 1
+    c0, c = rttda.ground_state(len(pulses), ctx.o, ctx.v)
+    got = ctx.propagate(pulses, wl.dt, n, c0, c)
+    torch.cuda.synchronize()
+    got = got.cpu().numpy()
+    return float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+
+
+def short_leg(wl, precision: str, pulses, steps: int, warmup: int = 5, oracle_s: float = 0.0):
+    """Aggregate fs/hour and sigma GFLOP/s of a short timed run (comparison legs); with oracle_s > 0
+    also its trace error against the FP64 oracle over the oracle steps that fit in oracle_s."""
     import torch
     from paper_2601_16949_amd import rttda
 
@@ -158,10 +190,15 @@ def short_leg(wl, precision: str, pulses, steps: int, warmup: int = 5):
     el = time.perf_counter() - t0
     fc, fx = flops_per_sigma(prob.o, prob.v, prob.nq)
     tun = ctx.get_tuning()
-    return {"precision": precision, "nrhs": R, "steps": steps, "ms_per_step": round(1e3 * el / steps, 4),
-            "fs_per_hour": round(steps * wl.dt * AU_FS * R / (el / 3600.0), 3),
-            "sigma_gflops": round(steps * 4 * R * (fc + fx) / el / 1e9, 2),
-            "exchange_variant": ctx.variant_name(tun["exchange_variant"]), "autotuned": tuned}
+    out = {"precision": precision, "nrhs": R, "steps": steps, "ms_per_step": round(1e3 * el / steps, 4),
+           "fs_per_hour": round(steps * wl.dt * AU_FS * R / (el / 3600.0), 3),
+           "sigma_gflops": round(steps * 4 * R * (fc + fx) / el / 1e9, 2),
+           "exchange_variant": ctx.variant_name(tun["exchange_variant"]), "autotuned": tuned}
+    if oracle_s > 0:
+        ref, k, _, _ = oracle_run(wl, prob, pulses, oracle_s)
+        out["error_vs_oracle"] = {"rel_trace_err": trace_error(ctx, wl, pulses, ref), "steps": k,
+                                  "bar": 1e-5 if precision == "fp32" else 1e-4}
+    return out
 
 
 def main():
@@ -219,6 +256,11 @@ def main():
         dev = rttda.DeviceProblem(prob, wl.precision)
     R = len(wl.pulses)
     ctx = rttda.Context(dev, max_rhs=R)
+    # time-step guard: Lanczos bound on rho(A) against the integrator's stability limit
+    rho, rho_bound = ctx.spectral_radius(30)
+    limit = 2.5 if args.integrator == "rk4" else 2.0
+    if rho_bound * wl.dt > limit:
+        raise SystemExit(f"refused: rho(A) dt <= {rho_bound * wl.dt:.3f} exceeds the stability limit {limit}")
     tuned = False
     if args.variant or args.splits:
         ctx.set_tuning(exchange_variant=args.variant, exchange_splits=args.splits)
@@ -288,6 +330,8 @@ def main():
                      "avg_launch_us": round(ex_avg_ms * 1e3, 2), "algorithmic_flops_per_launch": ex_flops},
         "kernels": breakdown,
         "guard_bad_step": bad,
+        "stability": {"rho_bound": round(rho_bound, 6), "rho_dt": round(rho_bound * wl.dt, 4), "limit": limit,
+                      "lanczos_steps": 30},
         "trace_finite": bool(torch.isfinite(trace).all().item()),
     }
     if args.graph_compare:
@@ -309,13 +353,25 @@ def main():
         # single solve (1 RHS) on the same shape; the accuracy of the mixed path against the FP64
         # oracle (trace <= 1e-4) is checked by the parity tests
         del ctx, dev
+        ctx = None
         torch.cuda.empty_cache()
         single = short_leg(wl, "fp32", wl.pulses[:1], 100)
-        mixed = short_leg(wl, "mixed", wl.pulses, 200)
+        mixed = short_leg(wl, "mixed", wl.pulses, 200, oracle_s=0.0 if args.no_cpu_baseline else 8.0)
         out["mixed_vs_fp32_single"] = {"fp32_single": single, "mixed_batched": mixed,
                                        "ratio_fs_per_hour": round(mixed["fs_per_hour"] / single["fs_per_hour"], 3)}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, prob, args.cpu_budget)
+        out["cpu_baseline"], ref = cpu_baseline(wl, prob, args.cpu_budget)
+        if ctx is not None:
+            err = trace_error(ctx, wl, wl.pulses, ref)
+        else:  # the comparison legs freed the timed context: a fresh one in the same configuration
+            ctx2 = rttda.Context(rttda.DeviceProblem(prob, wl.precision), max_rhs=R)
+            if args.variant or args.splits:
+                ctx2.set_tuning(exchange_variant=args.variant, exchange_splits=args.splits)
+            else:
+                ctx2.use_tuned(R, args.integrator)
+            err = trace_error(ctx2, wl, wl.pulses, ref)
+        out["error_vs_oracle"] = {"rel_trace_err": err, "steps": int(ref.shape[0] - 1),
+                                  "bar": 1e-5 if wl.precision == "fp32" else 1e-4}
     print(json.dumps(out), flush=True)
 
 

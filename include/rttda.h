@@ -25,8 +25,10 @@
  * Conventions shared by every entry point
  * ---------------------------------------
  *  - All array arguments are DEVICE pointers owned by the caller (host pointers
- *    are marked "host").  Device arrays must be 16-byte aligned and stay alive
- *    for as long as a context that refers to them.
+ *    are marked "host").  Device arrays must be 16-byte aligned, except the
+ *    per-step outputs of the propagators (trace, norms, correlation, populations,
+ *    energy), which are written one double at a time and need 8-byte alignment;
+ *    inputs stay alive for as long as a context that refers to them.
  *  - Complex amplitudes are stored as separate real planes:
  *        c0 : f64 [nrhs][2]           (re, im)
  *        c  : f64 [nrhs][2][o][v]     (plane 0 = Re C, plane 1 = Im C)
@@ -145,7 +147,9 @@ rttda_status rttda_sigma(rttda_ctx *ctx, int32_t nrhs, const double *field, cons
  *   trace[k][r] = Re <X_r | M_dr | X_r> at step step0 + k, k = 0..n_steps
  * (f64 [n_steps+1][nrhs]); norms likewise receives |c0|^2 + |C|^2 if not NULL.
  * The norm guard records the first step at which a norm is non-finite or more
- * than twice its value at the start of the call; read it with rttda_guard(). */
+ * than twice its value at the start of the call; read it with rttda_guard().
+ * A call that fails its argument checks (including RTTDA_E_UNSUPPORTED for an
+ * exact kick beyond the series' reach) leaves c0 and c untouched. */
 rttda_status rttda_propagate(rttda_ctx *ctx, int32_t nrhs, const rttda_pulse *pulses, double dt,
                              int64_t step0, int64_t n_steps, double *c0, double *c, double *trace,
                              double *norms);
@@ -168,6 +172,17 @@ rttda_status rttda_propagate_sso(rttda_ctx *ctx, int32_t nrhs, const rttda_pulse
  * after its delta kicks (the paper's epsilon just after the pulse) and the inner product runs over
  * the ground amplitude and both planes. */
 rttda_status rttda_set_correlation(rttda_ctx *ctx, double *corr);
+
+/* Energy output for the next rttda_propagate call on ctx (that call only; NULL clears it): energy
+ * (device [n_steps+1][nrhs] FP64, caller-owned) receives E_r(t_n) = <X_r | diag(0, A) | X_r> =
+ * sum over both planes of C . (A C), the expectation of the field-free Hamiltonian of eqs.
+ * ode_rt_tda and A_matrix_element2 (A_00 = 0), at steps step0..step0+n_steps.  Computed from the
+ * products A C that the first RK4 stage of each step forms anyway (partial sums per block of the
+ * FP64 epilogue, added in a fixed order); the last sample costs one more product.  Field-free RK4
+ * moves it by the per-mode factor |R(-i w dt)|^2 per step (no drift beyond that).  The split-
+ * operator route does not produce it: rttda_propagate_sso returns RTTDA_E_UNSUPPORTED while an
+ * energy output is pending. */
+rttda_status rttda_set_energy(rttda_ctx *ctx, double *energy);
 
 /* Eigenstate populations as an output of the next rttda_propagate or rttda_propagate_sso call
  * on ctx (that call only; pops NULL clears it): pops (device [n_steps+1][nrhs][k] FP64, 16-byte
@@ -210,8 +225,11 @@ rttda_status rttda_guard(rttda_ctx *ctx, int64_t *first_bad_step);
  * stream, so the work of different requests overlaps on the device; at most one chunk per
  * request is in flight), and frees the budget when the request is released.  A request's
  * result is the same as that of one rttda_propagate(_sso) call over all its steps: the
- * chunks resume at the request's own step counter.  The pool owns no device memory and
- * is not thread-safe; contexts admitted to a pool must not be used elsewhere until released.
+ * chunks resume at the request's own step counter, and the norm guard keeps its reference
+ * norm and first bad step across them.  A request whose chunk fails (for instance an exact
+ * kick beyond the series' reach) stops; the others carry on, and rttda_pool_poll and
+ * rttda_pool_result report its status.  The pool owns no device memory and is not
+ * thread-safe; contexts admitted to a pool must not be used elsewhere until released.
  * --------------------------------------------------------------------------------------- */
 typedef struct rttda_pool rttda_pool;
 typedef enum { RTTDA_INTEG_RK4 = 0, RTTDA_INTEG_SSO = 1 } rttda_integrator;
@@ -219,7 +237,8 @@ rttda_status rttda_pool_create(size_t budget_bytes, rttda_pool **out);
 rttda_status rttda_pool_destroy(rttda_pool *pool); /* waits for in-flight chunks */
 /* Admit a request; *slot receives its id.  pulses (host, [nrhs]) are copied; c0, c
  * (device, updated in place) and trace (device [n_steps+1][nrhs] or NULL) must outlive the
- * slot.  RTTDA_E_NOMEM when footprint_bytes does not fit the remaining budget. */
+ * slot.  The pulses, dt and pointers are checked as rttda_propagate checks them
+ * (RTTDA_E_INVAL).  RTTDA_E_NOMEM when footprint_bytes does not fit the remaining budget. */
 rttda_status rttda_pool_admit(rttda_pool *pool, rttda_ctx *ctx, int32_t nrhs, const rttda_pulse *pulses,
                               double dt, int64_t n_steps, int32_t integrator, double *c0, double *c,
                               double *trace, size_t footprint_bytes, int32_t *slot);
@@ -228,8 +247,13 @@ rttda_status rttda_pool_admit(rttda_pool *pool, rttda_ctx *ctx, int32_t nrhs, co
  * the number of chunks enqueued (may be NULL). */
 rttda_status rttda_pool_step(rttda_pool *pool, int64_t chunk_steps, int32_t *issued);
 /* Non-blocking progress of a slot: steps enqueued so far and whether all its steps have
- * finished on the device. */
+ * finished on the device.  Returns the status of a failed chunk (the slot then counts as
+ * finished) after filling both outputs. */
 rttda_status rttda_pool_poll(rttda_pool *pool, int32_t slot, int64_t *steps_enqueued, int32_t *finished);
+/* Wait for a slot's work and report its outcome: the status of a failed chunk, else the norm
+ * guard over all its chunks (RTTDA_E_UNSTABLE, with the first bad step in *first_bad_step,
+ * may be NULL; -1 when it never tripped). */
+rttda_status rttda_pool_result(rttda_pool *pool, int32_t slot, int64_t *first_bad_step);
 /* Wait for a slot's work, return its footprint to the budget and retire the slot. */
 rttda_status rttda_pool_release(rttda_pool *pool, int32_t slot);
 /* Budget in use and number of admitted (unreleased) requests. */

@@ -525,7 +525,8 @@ class EigenRoute:
                 trace[n[k]] = dipole_expectation(blocks, Y[k, 0], Xc[k].reshape(o, v))
         return trace
 
-    def propagate_rk4_many(self, pulses, dt: float, n_steps: int, n_pop: int = 0, pop_every: int = 1):
+    def propagate_rk4_many(self, pulses, dt: float, n_steps: int, n_pop: int = 0, pop_every: int = 1,
+                           progress=None):
         """RK4 with fields for several right-hand sides that share one polarisation, run in the
         eigenbasis from the ground state (after any delta kick), all RHS as the columns of one
         matrix.  Returns (trace [n_steps+1, R], pops) where pops [n_samples, R, 1 + n_pop] holds
@@ -547,15 +548,19 @@ class EigenRoute:
         def fields(t):
             return np.array([field_value(p, t) for p in pulses])
 
+        def mul(Y):  # Me Y with the real and imaginary parts as the columns of one real product
+            Z = Me @ np.concatenate([Y.real, Y.imag], axis=1)
+            return Z[:, :Rn] + 1j * Z[:, Rn:]
+
         def f(t, Y, MY=None):
             if MY is None:
-                MY = Me @ Y
+                MY = mul(Y)
             return -1j * (w * Y - fields(t)[None, :] * MY)
 
         n_samp = n_steps // pop_every + 1
         trace = np.empty((n_steps + 1, Rn))
         pops = np.empty((n_samp, Rn, 1 + n_pop))
-        MY = Me @ Y
+        MY = mul(Y)
         for n in range(n_steps + 1):
             trace[n] = np.real(np.sum(np.conj(Y) * MY, axis=0))
             if n % pop_every == 0:
@@ -567,7 +572,9 @@ class EigenRoute:
             k3 = f((n + 0.5) * dt, Y + 0.5 * dt * k2)
             k4 = f((n + 1.0) * dt, Y + dt * k3)
             Y = Y + dt / 6.0 * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
-            MY = Me @ Y
+            MY = mul(Y)
+            if progress is not None and (n + 1) % 1000 == 0:
+                progress(n + 1)
         return trace, pops
 
     def propagate_rk4(self, pulse, dt: float, n_steps: int, c0=1.0 + 0j, C=None):

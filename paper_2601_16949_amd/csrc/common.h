@@ -24,13 +24,17 @@ struct DevState {
   long long step;      // absolute step index of the current state c
   long long step0;     // step index at the start of the current propagate call
   long long bad_step;  // first step at which the norm guard tripped, -1 if none
-  long long pad;
+  long long keep_ref;  // 1: the call resumes a run (the guard's reference norm and first bad step
+                       // carry over from the previous call), 0: both restart with the call
   double *trace;       // trace row of step0 ([n_steps+1][nrhs]) or NULL; set per call, so a
   double *norms;       // captured step graph stays valid across calls with new output arrays
   double *corr;        // time-correlation output ([n_steps+1][nrhs][2]) or NULL, likewise
   double *pops;        // eigenstate populations output ([n_steps+1][nrhs][popk]) or NULL, likewise
   const double *popU;  // the popk unit vectors ([popk][o][v]) the states are projected on
   long long popk;
+  double *energy;      // energy output <X|diag(0,A)|X> ([n_steps+1][nrhs]) or NULL, likewise
+  const double *epart; // the epilogue's per-block energy partial sums [nrhs][nbe]
+  long long nbe;
 };
 constexpr int POP_MAX = 64;  // eigenstates per populations output
 
@@ -54,10 +58,14 @@ enum : int {
   SM_SIGMA0 = 16,   // s0 = -E g with E preset by the host
   SM_OUT = 32,      // out[r] = <X|M|X>  (dipole_trace entry point)
   SM_KEEP_E = 64,   // keep the E slots written by the host
+  SM_ENERGY = 128,  // energy sample at index step - step0 from the epilogue's partial sums
 };
 
 // Epilogue modes.
-enum : int { EP_RK4 = 0, EP_SIGMA = 1 };
+enum : int { EP_RK4 = 0, EP_SIGMA = 1, EP_ENERGY = 2 };
+// Epilogue grid: blocks per RHS along ia (the energy partial sums come one per block)
+constexpr int EP_BX_MAX = 2048;
+int epilogue_blocks(long long ov);
 // symplectic split-operator update modes (k_sso_update)
 enum : int { SSO_KICK_FIRST = 0, SSO_KICK = 1, SSO_DRIFT = 2 };
 
@@ -83,10 +91,11 @@ hipError_t launch_field(hipStream_t s, const double *X, const double *X0, const 
 hipError_t launch_scalar(hipStream_t s, int R, int nbf, int stage, int mode, double dt, const DevPulse *pulses,
                          DevState *st, const double *part, double *sc, double *c0, double *acc0, double *xs0,
                          double *out, double *normref, double *s0);
+// epart != NULL: also the per-block partial sums of <X, A X> per RHS ([R][epilogue_blocks(ov)])
 hipError_t launch_epilogue(hipStream_t s, int prec, int R, int o, int v, int nslab, int stage, int mode,
                            int use_field, double dt, const double *D, const float *P, const double *F,
                            const double *sc, const double *Xin, double *c, double *acc, double *xs64, float *x32,
-                           __hip_bfloat16 *xhi, __hip_bfloat16 *xlo, double *s_out);
+                           __hip_bfloat16 *xhi, __hip_bfloat16 *xlo, double *s_out, double *epart = nullptr);
 hipError_t launch_sso_update(hipStream_t s, int prec, int R, int o, int v, int nslab, int mode, int use_field,
                              double dt, const double *D, const float *P, const double *F, const double *sc, double *c,
                              double *c0, double *W, double *W0, float *x32, __hip_bfloat16 *xhi,
@@ -126,7 +135,8 @@ hipError_t launch_kick(hipStream_t s, int R, int ov, const DevPulse *pulses, con
 hipError_t launch_kick_term(hipStream_t s, int R, int ov, const DevPulse *pulses, const double *F, const double *sc,
                             double inv_j, double *T, double *T0, double *c, double *c0);
 hipError_t launch_set_state(hipStream_t s, DevState *st, long long step0, double *trace, double *norms,
-                            double *corr, double *pops, const double *popU, int popk);
+                            double *corr, double *pops, const double *popU, int popk, double *energy = nullptr,
+                            const double *epart = nullptr, long long nbe = 0, int resume = 0);
 // eigenstate populations |<U_I | X_r>|^2 at the current step (no-op unless st->pops is set)
 hipError_t launch_pop(hipStream_t s, int R, size_t ov, const double *X, const DevState *st);
 hipError_t launch_spectrum(hipStream_t s, int kind, const double *sig, int n_t, int nsig, double dt, double kappa,

@@ -397,7 +397,7 @@ __global__ __launch_bounds__(256) void k_scalar(int R, int nbf, int stage, int m
         if (mode & SM_TRACE) {
           if (trace) trace[k * R + r] = t;
           if (norms) norms[k * R + r] = n2;
-          if (k == 0) {
+          if (k == 0 && !st->keep_ref) {
             normref[r] = n2;
           } else if (!(n2 <= 2.0 * normref[r])) {  // also catches NaN
             bad = 1;
@@ -434,6 +434,17 @@ __global__ __launch_bounds__(256) void k_scalar(int R, int nbf, int stage, int m
       }
     }
     __syncthreads();
+  }
+  // energy sample: the epilogue's per-block partial sums of each RHS, added lane-wise then by a
+  // fixed shuffle tree (one wave per RHS)
+  if ((mode & SM_ENERGY) && st->energy) {
+    const long long nbe = st->nbe;
+    for (int r = wave; r < R; r += (int)(blockDim.x >> 6)) {
+      double e = 0.0;
+      for (long long b = lane; b < nbe; b += 64) e += st->epart[(size_t)r * nbe + b];
+      e = wave_sum(e);
+      if (lane == 0) st->energy[k * R + r] = e;
+    }
   }
   if (threadIdx.x == 0) {
     if (bad && st->bad_step < 0) st->bad_step = step;
@@ -622,12 +633,12 @@ __global__ __launch_bounds__(256) void k_epilogue(int R, int o, int v, int nslab
                                                   double *__restrict__ c, double *__restrict__ acc,
                                                   double *__restrict__ xs64, float *__restrict__ x32,
                                                   __hip_bfloat16 *__restrict__ xhi, __hip_bfloat16 *__restrict__ xlo,
-                                                  double *__restrict__ s_out) {
+                                                  double *__restrict__ s_out, double *__restrict__ epart) {
   const size_t ov = (size_t)o * v;
-  const size_t total = (size_t)R * ov;
   const size_t slab = 2 * (size_t)R * ov;  // floats per partial slab
-  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
-    const size_t r = e / ov, ia = e - r * ov;
+  const size_t r = blockIdx.y;             // one RHS per block row
+  double en = 0.0;                         // this thread's part of <X, A X> (both planes)
+  for (size_t ia = blockIdx.x * (size_t)blockDim.x + threadIdx.x; ia < ov; ia += (size_t)gridDim.x * blockDim.x) {
     const size_t i0 = r * 2 * ov + ia, i1 = i0 + ov;
     const double x0 = Xin[i0], x1 = Xin[i1];
     const double d = D[ia];
@@ -652,6 +663,8 @@ __global__ __launch_bounds__(256) void k_epilogue(int R, int o, int v, int nslab
       p1 += (double)P[sl * slab + i1];
     }
     double s0v = d * x0 + p0, s1v = d * x1 + p1;
+    if (epart) en += x0 * s0v + x1 * s1v;
+    if (mode == EP_ENERGY) continue;
     if (use_field) {
       const double E = sc[r * SC_STRIDE + SC_E];
       s0v -= E * F[i0];
@@ -692,6 +705,13 @@ __global__ __launch_bounds__(256) void k_epilogue(int R, int o, int v, int nslab
       split_bf16(n0, xhi[i0], xlo[i0]);
       split_bf16(n1, xhi[i1], xlo[i1]);
     }
+  }
+  if (epart) {  // block sum in a fixed order: waves, then the four wave totals
+    __shared__ double ws[4];
+    en = wave_sum(en);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = en;
+    __syncthreads();
+    if (threadIdx.x == 0) epart[r * gridDim.x + blockIdx.x] = (ws[0] + ws[1]) + (ws[2] + ws[3]);
   }
 }
 
@@ -747,11 +767,16 @@ __global__ void k_kick_term(int R, int ov, const DevPulse *__restrict__ pulses, 
 }
 
 __global__ void k_set_state(DevState *st, long long step0, double *trace, double *norms, double *corr, double *pops,
-                            const double *popU, int popk) {
+                            const double *popU, int popk, double *energy, const double *epart, long long nbe,
+                            int resume) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     st->step = step0;
     st->step0 = step0;
-    st->bad_step = -1;
+    if (!resume) st->bad_step = -1;
+    st->keep_ref = resume;
+    st->energy = energy;
+    st->epart = epart;
+    st->nbe = nbe;
     st->trace = trace;
     st->norms = norms;
     st->corr = corr;
@@ -929,17 +954,18 @@ hipError_t launch_scalar(hipStream_t s, int R, int nbf, int stage, int mode, dou
 hipError_t launch_epilogue(hipStream_t s, int prec, int R, int o, int v, int nslab, int stage, int mode,
                            int use_field, double dt, const double *D, const float *P, const double *F,
                            const double *sc, const double *Xin, double *c, double *acc, double *xs64, float *x32,
-                           __hip_bfloat16 *xhi, __hip_bfloat16 *xlo, double *s_out) {
-  const long long n = (long long)R * o * v;
-  dim3 grid(grid_for(n, 256, 65536));
+                           __hip_bfloat16 *xhi, __hip_bfloat16 *xlo, double *s_out, double *epart) {
+  dim3 grid(epilogue_blocks((long long)o * v), R);
   if (prec == RTTDA_PREC_MIXED_BF16)
     hipLaunchKernelGGL((k_epilogue<1>), grid, dim3(256), 0, s, R, o, v, nslab, stage, mode, use_field, dt, D, P, F,
-                       sc, Xin, c, acc, xs64, x32, xhi, xlo, s_out);
+                       sc, Xin, c, acc, xs64, x32, xhi, xlo, s_out, epart);
   else
     hipLaunchKernelGGL((k_epilogue<0>), grid, dim3(256), 0, s, R, o, v, nslab, stage, mode, use_field, dt, D, P, F,
-                       sc, Xin, c, acc, xs64, x32, xhi, xlo, s_out);
+                       sc, Xin, c, acc, xs64, x32, xhi, xlo, s_out, epart);
   return hipGetLastError();
 }
+
+int epilogue_blocks(long long ov) { return (int)std::min<long long>((ov + 255) / 256, EP_BX_MAX); }
 
 hipError_t launch_sso_update(hipStream_t s, int prec, int R, int o, int v, int nslab, int mode, int use_field,
                              double dt, const double *D, const float *P, const double *F, const double *sc, double *c,
@@ -1008,8 +1034,10 @@ hipError_t launch_kick_term(hipStream_t s, int R, int ov, const DevPulse *pulses
 }
 
 hipError_t launch_set_state(hipStream_t s, DevState *st, long long step0, double *trace, double *norms,
-                            double *corr, double *pops, const double *popU, int popk) {
-  hipLaunchKernelGGL(k_set_state, dim3(1), dim3(64), 0, s, st, step0, trace, norms, corr, pops, popU, popk);
+                            double *corr, double *pops, const double *popU, int popk, double *energy,
+                            const double *epart, long long nbe, int resume) {
+  hipLaunchKernelGGL(k_set_state, dim3(1), dim3(64), 0, s, st, step0, trace, norms, corr, pops, popU, popk, energy,
+                     epart, nbe, resume);
   return hipGetLastError();
 }
 

@@ -64,6 +64,7 @@ inline bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 
 struct Layout {
   size_t D, moo, mov, mvv, xs64, xs0, acc, acc0, F, part, sc, x32, xhi, xlo, dvec, P, pulses, state, normref;
   size_t xref, xref0;  // reference state of the time-correlation output (state at the start of a call)
+  size_t epart;        // per-block partial sums of the energy output ([R][EP_BX_MAX] FP64)
   size_t scratch, scratch_bytes;  // W hi/lo of the large-o exchange path (0 bytes when it does not apply)
   size_t lz, lzp;                 // Lanczos guard: three FP64 vectors of ov, block partial sums
   size_t total;
@@ -105,6 +106,7 @@ Layout make_layout(int o, int v, int nq, int R, int prec) {
   L.normref = take((size_t)R * 8);
   L.xref = take(ns * ov * 8);
   L.xref0 = take(ns * 8);
+  L.epart = take((size_t)R * EP_BX_MAX * 8);
   L.scratch_bytes = 0;
   if (prec == RTTDA_PREC_MIXED_BF16 && nq > 0 && o >= XGEMM_O_MIN && o <= 256 && o % 8 == 0 && v % 8 == 0) {
     const size_t per_q = (size_t)v * ns * o * 4;  // W hi + lo for one Q at the largest RHS count
@@ -185,7 +187,7 @@ struct GraphEntry {
   int nrhs = 0, steps = 0, mode = 0, integ = 0;
   double dt = 0;
   const void *c0 = nullptr, *c = nullptr;
-  bool trace = false, norms = false, corr = false, pops = false;
+  bool trace = false, norms = false, corr = false, pops = false, energy = false;
   hipGraphExec_t exec = nullptr;
 };
 
@@ -236,6 +238,7 @@ struct rttda_ctx {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int overlap = 2;  // 1: Coulomb pair on the second stream, 2: in order on the context's stream
   double *corr_next = nullptr;  // time-correlation output of the next propagate call
+  double *energy_next = nullptr;  // energy output of the next propagate call
   double *pops_next = nullptr;  // populations output of the next propagate call, its vectors and count
   const double *popU_next = nullptr;
   int popk_next = 0;
@@ -273,6 +276,7 @@ struct rttda_ctx {
   double *normref() const { return at<double>(L.normref); }
   double *xref() const { return at<double>(L.xref); }
   double *xref0() const { return at<double>(L.xref0); }
+  double *epart() const { return at<double>(L.epart); }
 };
 
 namespace {
@@ -432,8 +436,8 @@ rttda_status enqueue_two_electron(rttda_ctx *ctx, int ns) {
 int nslab(const rttda_ctx *ctx) { return ctx->nq > 0 ? ctx->sj + ctx->sk : 0; }
 
 // One RK4 step (4 stages) on the context's stream.
-rttda_status enqueue_step(rttda_ctx *ctx, int nrhs, double dt, bool has_field, bool corr, bool pops, double *c0,
-                          double *c) {
+rttda_status enqueue_step(rttda_ctx *ctx, int nrhs, double dt, bool has_field, bool corr, bool pops, bool energy,
+                          double *c0, double *c) {
   hipStream_t s = ctx->stream;
   const int o = ctx->o, v = ctx->v;
   for (int stage = 0; stage < 4; ++stage) {
@@ -453,13 +457,14 @@ rttda_status enqueue_step(rttda_ctx *ctx, int nrhs, double dt, bool has_field, b
     if (stage == 0) mode |= SM_TRACE;
     if (has_field) mode |= SM_C0 | SM_EFIELD;
     if (stage == 3) mode |= SM_INC;
+    if (stage == 1 && energy) mode |= SM_ENERGY;  // the sample of this step, from stage 0's partials
     HIP_TRY(launch_scalar(s, nrhs, ctx->L.nbf, stage, mode, dt, ctx->pulses(), ctx->state(), ctx->part(), ctx->sc(),
                           c0, ctx->acc0(), ctx->xs0(), nullptr, ctx->normref(), nullptr));
     if (corr && stage == 0) HIP_TRY(launch_corr(s, nrhs, ctx->ov, c, c0, ctx->xref(), ctx->xref0(), ctx->state()));
     if (pops && stage == 0) HIP_TRY(launch_pop(s, nrhs, ctx->ov, c, ctx->state()));
     HIP_TRY(launch_epilogue(s, ctx->prec, nrhs, o, v, nslab(ctx), stage, EP_RK4, has_field ? 1 : 0, dt, ctx->D(),
                             ctx->P(), ctx->F(), ctx->sc(), Xin, c, ctx->acc(), ctx->xs64(), ctx->x32(), ctx->xhi(),
-                            ctx->xlo(), nullptr));
+                            ctx->xlo(), nullptr, energy && stage == 0 ? ctx->epart() : nullptr));
     if (pr) HIP_TRY(ctx->prof.end(PC_EPILOGUE, s));
   }
   return RTTDA_OK;
@@ -925,8 +930,10 @@ enum : int { INTEG_RK4 = 0, INTEG_SSO = 1 };
 // Unitary kick exp(i kappa M) X for the RHS with PULSE_DELTA_EXACT, as the Taylor series
 // sum_j (i kappa M)^j X / j!.  |M X| <= (|mu_oo|_F + |mu_vv|_F + 2 sqrt2 |mu_ov|_F) |X| = b |X|,
 // so J terms leave at most x^(J+1)/(J+1)! e^x of |X| with x = kappa b; J is the smallest with
-// that below 1e-17.  The terms live in the stage buffers (xs64, xs0).
-rttda_status exact_kick(rttda_ctx *ctx, int nrhs, const rttda_pulse *pulses, double *c0, double *c) {
+// that below 1e-17.  exact_kick_terms finds J from the dipole blocks of this call (it reads them
+// back, so it synchronises) and refuses before anything touches the state; exact_kick_apply runs
+// the series, with the terms in the stage buffers (xs64, xs0).
+rttda_status exact_kick_terms(rttda_ctx *ctx, int nrhs, const rttda_pulse *pulses, int *terms) {
   hipStream_t hs = ctx->stream;
   const int o = ctx->o, v = ctx->v;
   const long long ov = (long long)ctx->ov;
@@ -958,6 +965,14 @@ rttda_status exact_kick(rttda_ctx *ctx, int nrhs, const rttda_pulse *pulses, dou
   if (J > 120)
     return fail(RTTDA_E_UNSUPPORTED, "exact kick: kappa |M| bound %.3g too large for the series (use a smaller kick)",
                 x);
+  *terms = J;
+  return RTTDA_OK;
+}
+
+rttda_status exact_kick_apply(rttda_ctx *ctx, int nrhs, int J, double *c0, double *c) {
+  hipStream_t hs = ctx->stream;
+  const int o = ctx->o, v = ctx->v;
+  const long long ov = (long long)ctx->ov;
   double *T = ctx->xs64(), *T0 = ctx->xs0();
   HIP_TRY(hipMemcpyAsync(T, c, (size_t)2 * nrhs * ov * sizeof(double), hipMemcpyDeviceToDevice, hs));
   HIP_TRY(hipMemcpyAsync(T0, c0, (size_t)2 * nrhs * sizeof(double), hipMemcpyDeviceToDevice, hs));
@@ -970,26 +985,21 @@ rttda_status exact_kick(rttda_ctx *ctx, int nrhs, const rttda_pulse *pulses, dou
   return RTTDA_OK;
 }
 
-rttda_status propagate_impl(rttda_ctx *ctx, int32_t nrhs, const rttda_pulse *pulses, double dt, int64_t step0,
-                            int64_t n_steps, double *c0, double *c, double *trace, double *norms, int integ) {
-  if (!ctx) return fail(RTTDA_E_INVAL, "ctx is NULL");
-  double *corr = ctx->corr_next;  // applies to this call only
-  ctx->corr_next = nullptr;
-  double *pops = ctx->pops_next;
-  const double *popU = ctx->popU_next;
-  const int popk = ctx->popk_next;
-  ctx->pops_next = nullptr;
-  ctx->popU_next = nullptr;
-  ctx->popk_next = 0;
-  rttda_status st = check_nrhs(ctx, nrhs);
-  if (st != RTTDA_OK) return st;
+inline bool aligned8(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
+
+// Host-side checks of a propagation request (pulses, dt, step range, state and output pointers);
+// nothing is enqueued.
+rttda_status check_request(int32_t nrhs, const rttda_pulse *pulses, double dt, int64_t step0, int64_t n_steps,
+                           const double *c0, const double *c, const double *trace, const double *norms,
+                           bool *has_field, bool *has_kick, bool *has_exact) {
   if (!pulses || !c0 || !c) return fail(RTTDA_E_INVAL, "NULL argument (pulses, c0 and c are required)");
-  if (!aligned16(c0) || !aligned16(c) || (trace && !aligned16(trace)) || (norms && !aligned16(norms)) ||
-      (corr && !aligned16(corr)) || (pops && !aligned16(pops)))
-    return fail(RTTDA_E_INVAL, "device arrays must be 16-byte aligned");
+  if (!aligned16(c0) || !aligned16(c)) return fail(RTTDA_E_INVAL, "c0 and c must be 16-byte aligned");
+  // outputs are written one double at a time
+  if ((trace && !aligned8(trace)) || (norms && !aligned8(norms)))
+    return fail(RTTDA_E_INVAL, "trace and norms must be 8-byte aligned");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(RTTDA_E_INVAL, "dt must be finite and > 0 (got %g)", dt);
   if (step0 < 0 || n_steps < 0) return fail(RTTDA_E_INVAL, "step0 and n_steps must be >= 0");
-  bool has_field = false, has_kick = false, has_exact = false;
+  bool f = false, k = false, e = false;
   for (int r = 0; r < nrhs; ++r) {
     const rttda_pulse &p = pulses[r];
     if (p.kind < RTTDA_PULSE_NONE || p.kind > RTTDA_PULSE_DELTA_EXACT) return fail(RTTDA_E_INVAL, "pulse %d: bad kind", r);
@@ -999,23 +1009,59 @@ rttda_status propagate_impl(rttda_ctx *ctx, int32_t nrhs, const rttda_pulse *pul
       if (!std::isfinite(x)) return fail(RTTDA_E_INVAL, "pulse %d: non-finite parameter", r);
     if ((p.kind == RTTDA_PULSE_GAUSS || p.kind == RTTDA_PULSE_CHIRP) && !(p.fwhm > 0))
       return fail(RTTDA_E_INVAL, "pulse %d: fwhm must be > 0", r);
-    if ((st = check_dirs(p.dir, 1)) != RTTDA_OK) return fail(RTTDA_E_INVAL, "pulse %d: dir is not a unit vector", r);
-    has_field |= (p.kind == RTTDA_PULSE_CW || p.kind == RTTDA_PULSE_GAUSS || p.kind == RTTDA_PULSE_CHIRP);
-    has_kick |= (p.kind == RTTDA_PULSE_DELTA && p.e0 != 0.0);
-    has_exact |= (p.kind == RTTDA_PULSE_DELTA_EXACT && p.e0 != 0.0);
+    if (check_dirs(p.dir, 1) != RTTDA_OK) return fail(RTTDA_E_INVAL, "pulse %d: dir is not a unit vector", r);
+    f |= (p.kind == RTTDA_PULSE_CW || p.kind == RTTDA_PULSE_GAUSS || p.kind == RTTDA_PULSE_CHIRP);
+    k |= (p.kind == RTTDA_PULSE_DELTA && p.e0 != 0.0);
+    e |= (p.kind == RTTDA_PULSE_DELTA_EXACT && p.e0 != 0.0);
   }
+  if (has_field) *has_field = f;
+  if (has_kick) *has_kick = k;
+  if (has_exact) *has_exact = e;
+  return RTTDA_OK;
+}
+
+// resume: the call continues a run of earlier calls on this context (the serving pool's chunks):
+// the norm guard keeps its reference norm and first bad step across the calls.
+rttda_status propagate_impl(rttda_ctx *ctx, int32_t nrhs, const rttda_pulse *pulses, double dt, int64_t step0,
+                            int64_t n_steps, double *c0, double *c, double *trace, double *norms, int integ,
+                            bool resume = false) {
+  if (!ctx) return fail(RTTDA_E_INVAL, "ctx is NULL");
+  double *corr = ctx->corr_next;  // the pending outputs apply to this call only
+  ctx->corr_next = nullptr;
+  double *pops = ctx->pops_next;
+  const double *popU = ctx->popU_next;
+  const int popk = ctx->popk_next;
+  ctx->pops_next = nullptr;
+  ctx->popU_next = nullptr;
+  ctx->popk_next = 0;
+  double *energy = ctx->energy_next;
+  ctx->energy_next = nullptr;
+  rttda_status st = check_nrhs(ctx, nrhs);
+  if (st != RTTDA_OK) return st;
+  bool has_field = false, has_kick = false, has_exact = false;
+  if ((st = check_request(nrhs, pulses, dt, step0, n_steps, c0, c, trace, norms, &has_field, &has_kick,
+                          &has_exact)) != RTTDA_OK)
+    return st;
+  if ((corr && !aligned8(corr)) || (pops && !aligned8(pops)) || (energy && !aligned8(energy)))
+    return fail(RTTDA_E_INVAL, "correlation, population and energy outputs must be 8-byte aligned");
+  if (energy && integ != INTEG_RK4)
+    return fail(RTTDA_E_UNSUPPORTED, "the energy output is produced by the RK4 integrator only");
   if ((st = upload_pulses(ctx, reinterpret_cast<const DevPulse *>(pulses), nrhs)) != RTTDA_OK) return st;
   hipStream_t hs = ctx->stream;
   const int o = ctx->o, v = ctx->v;
   HIP_TRY(launch_mu_blocks(hs, ctx->d.mu, ctx->pulses(), o, v, nrhs, ctx->moo(), ctx->mov(), ctx->mvv()));
-  HIP_TRY(launch_set_state(hs, ctx->state(), step0, trace, norms, corr, pops, popU, popk));
+  int kick_terms = 0;
+  if (has_exact && step0 == 0 && (st = exact_kick_terms(ctx, nrhs, pulses, &kick_terms)) != RTTDA_OK) return st;
+  // from here on the call changes the state
+  HIP_TRY(launch_set_state(hs, ctx->state(), step0, trace, norms, corr, pops, popU, popk, energy, ctx->epart(),
+                           epilogue_blocks((long long)ctx->ov), resume ? 1 : 0));
   if (has_kick && step0 == 0) {
     HIP_TRY(launch_field(hs, c, c0, ctx->moo(), ctx->mov(), ctx->mvv(), o, v, nrhs, ctx->F(), ctx->part()));
     HIP_TRY(launch_scalar(hs, nrhs, ctx->L.nbf, 0, 0, dt, ctx->pulses(), ctx->state(), ctx->part(), ctx->sc(), c0,
                           ctx->acc0(), ctx->xs0(), nullptr, ctx->normref(), nullptr));
     HIP_TRY(launch_kick(hs, nrhs, (int)ctx->ov, ctx->pulses(), ctx->F(), ctx->sc(), c, c0));
   }
-  if (has_exact && step0 == 0 && (st = exact_kick(ctx, nrhs, pulses, c0, c)) != RTTDA_OK) return st;
+  if (has_exact && step0 == 0 && (st = exact_kick_apply(ctx, nrhs, kick_terms, c0, c)) != RTTDA_OK) return st;
   if (corr) {  // reference state of the time-correlation function: the state after the kicks
     HIP_TRY(hipMemcpyAsync(ctx->xref(), c, (size_t)2 * nrhs * ctx->ov * sizeof(double), hipMemcpyDeviceToDevice, hs));
     HIP_TRY(hipMemcpyAsync(ctx->xref0(), c0, (size_t)2 * nrhs * sizeof(double), hipMemcpyDeviceToDevice, hs));
@@ -1027,7 +1073,8 @@ rttda_status propagate_impl(rttda_ctx *ctx, int32_t nrhs, const rttda_pulse *pul
   if (st != RTTDA_OK) return st;
   auto step = [&]() {
     return integ == INTEG_SSO ? enqueue_sso_step(ctx, nrhs, dt, has_field, corr != nullptr, pops != nullptr, c0, c)
-                              : enqueue_step(ctx, nrhs, dt, has_field, corr != nullptr, pops != nullptr, c0, c);
+                              : enqueue_step(ctx, nrhs, dt, has_field, corr != nullptr, pops != nullptr,
+                                             energy != nullptr, c0, c);
   };
 
   const int spg = ctx->steps_per_graph;
@@ -1038,7 +1085,8 @@ rttda_status propagate_impl(rttda_ctx *ctx, int32_t nrhs, const rttda_pulse *pul
     GraphEntry &G = ctx->graph;
     const bool hit = G.valid && G.nrhs == nrhs && G.steps == spg && G.mode == mode && G.integ == integ &&
                      G.dt == dt && G.c0 == c0 && G.c == c && G.trace == (trace != nullptr) &&
-                     G.norms == (norms != nullptr) && G.corr == (corr != nullptr) && G.pops == (pops != nullptr);
+                     G.norms == (norms != nullptr) && G.corr == (corr != nullptr) && G.pops == (pops != nullptr) &&
+                     G.energy == (energy != nullptr);
     if (!hit) {
       drop_graph(ctx);
       hipGraph_t graph = nullptr;
@@ -1068,6 +1116,7 @@ rttda_status propagate_impl(rttda_ctx *ctx, int32_t nrhs, const rttda_pulse *pul
       G.norms = norms != nullptr;
       G.corr = corr != nullptr;
       G.pops = pops != nullptr;
+      G.energy = energy != nullptr;
     }
     const int64_t reps = n_steps / spg;
     for (int64_t k = 0; k < reps; ++k) HIP_TRY(hipGraphLaunch(G.exec, hs));
@@ -1081,6 +1130,15 @@ rttda_status propagate_impl(rttda_ctx *ctx, int32_t nrhs, const rttda_pulse *pul
                         c0, ctx->acc0(), ctx->xs0(), nullptr, ctx->normref(), nullptr));
   if (corr) HIP_TRY(launch_corr(hs, nrhs, ctx->ov, c, c0, ctx->xref(), ctx->xref0(), ctx->state()));
   if (pops) HIP_TRY(launch_pop(hs, nrhs, ctx->ov, c, ctx->state()));
+  if (energy) {  // the final energy sample needs one more product A c
+    if ((st = to_stage_copy(ctx, c, nrhs)) != RTTDA_OK) return st;
+    if ((st = enqueue_two_electron(ctx, 2 * nrhs)) != RTTDA_OK) return st;
+    HIP_TRY(launch_epilogue(hs, ctx->prec, nrhs, o, v, nslab(ctx), 0, EP_ENERGY, 0, dt, ctx->D(), ctx->P(), ctx->F(),
+                            ctx->sc(), c, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                            ctx->epart()));
+    HIP_TRY(launch_scalar(hs, nrhs, ctx->L.nbf, 0, SM_ENERGY, dt, ctx->pulses(), ctx->state(), ctx->part(), ctx->sc(),
+                          c0, ctx->acc0(), ctx->xs0(), nullptr, ctx->normref(), nullptr));
+  }
   return RTTDA_OK;
 }
 
@@ -1096,6 +1154,12 @@ rttda_status rttda_propagate(rttda_ctx *ctx, int32_t nrhs, const rttda_pulse *pu
 rttda_status rttda_set_correlation(rttda_ctx *ctx, double *corr) {
   if (!ctx) return fail(RTTDA_E_INVAL, "ctx is NULL");
   ctx->corr_next = corr;
+  return RTTDA_OK;
+}
+
+rttda_status rttda_set_energy(rttda_ctx *ctx, double *energy) {
+  if (!ctx) return fail(RTTDA_E_INVAL, "ctx is NULL");
+  ctx->energy_next = energy;
   return RTTDA_OK;
 }
 
@@ -1382,6 +1446,8 @@ struct rttda_pool {
     size_t bytes = 0;
     hipEvent_t ev = nullptr;
     bool live = false, pending = false;
+    rttda_status err = RTTDA_OK;  // status of the chunk that failed (the slot then stops stepping)
+    std::string msg;
   };
   size_t budget = 0, used = 0;
   std::vector<Slot> slots;
@@ -1415,7 +1481,11 @@ rttda_status rttda_pool_admit(rttda_pool *pool, rttda_ctx *ctx, int32_t nrhs, co
   if (st != RTTDA_OK) return st;
   if (integrator != RTTDA_INTEG_RK4 && integrator != RTTDA_INTEG_SSO)
     return fail(RTTDA_E_INVAL, "integrator must be RTTDA_INTEG_RK4 or RTTDA_INTEG_SSO");
-  if (!(dt > 0.0) || !std::isfinite(dt) || n_steps < 0) return fail(RTTDA_E_INVAL, "bad dt or n_steps");
+  // the request's own checks (pulses, dt, pointers) at admission, so that a bad request is refused
+  // here instead of failing inside a later pool step
+  if ((st = check_request(nrhs, pulses, dt, 0, n_steps, c0, c, trace, nullptr, nullptr, nullptr, nullptr)) !=
+      RTTDA_OK)
+    return st;
   for (const auto &sl : pool->slots)
     if (sl.live && sl.ctx == ctx) return fail(RTTDA_E_STATE, "context already admitted");
   if (footprint_bytes > pool->budget - std::min(pool->used, pool->budget))
@@ -1439,6 +1509,8 @@ rttda_status rttda_pool_admit(rttda_pool *pool, rttda_ctx *ctx, int32_t nrhs, co
   sl.bytes = footprint_bytes;
   sl.live = true;
   sl.pending = false;
+  sl.err = RTTDA_OK;
+  sl.msg.clear();
   pool->used += footprint_bytes;
   *slot = (int32_t)k;
   return RTTDA_OK;
@@ -1457,8 +1529,13 @@ rttda_status rttda_pool_step(rttda_pool *pool, int64_t chunk_steps, int32_t *iss
     const int64_t k = std::min(chunk_steps, sl.n_steps - sl.done);
     double *tr = sl.trace ? sl.trace + (size_t)sl.done * sl.nrhs : nullptr;
     rttda_status st = propagate_impl(sl.ctx, sl.nrhs, sl.pulses.data(), sl.dt, sl.done, k, sl.c0, sl.c, tr,
-                                     nullptr, sl.integ == RTTDA_INTEG_SSO ? INTEG_SSO : INTEG_RK4);
-    if (st != RTTDA_OK) return st;
+                                     nullptr, sl.integ == RTTDA_INTEG_SSO ? INTEG_SSO : INTEG_RK4, sl.done > 0);
+    if (st != RTTDA_OK) {  // this request stops here; the others carry on
+      sl.err = st;
+      sl.msg = g_last_error;
+      sl.done = sl.n_steps;
+      continue;
+    }
     HIP_TRY(hipEventRecord(sl.ev, sl.ctx->stream));
     sl.pending = true;
     sl.done += k;
@@ -1484,7 +1561,22 @@ rttda_status rttda_pool_poll(rttda_pool *pool, int32_t slot, int64_t *steps_enqu
   }
   if (steps_enqueued) *steps_enqueued = sl.done;
   if (finished) *finished = fin;
+  if (sl.err != RTTDA_OK) return fail(sl.err, "slot %d stopped: %s", slot, sl.msg.c_str());
   return RTTDA_OK;
+}
+
+rttda_status rttda_pool_result(rttda_pool *pool, int32_t slot, int64_t *first_bad_step) {
+  if (!pool || slot < 0 || slot >= (int32_t)pool->slots.size() || !pool->slots[slot].live)
+    return fail(RTTDA_E_INVAL, "no such slot");
+  rttda_pool::Slot &sl = pool->slots[slot];
+  if (first_bad_step) *first_bad_step = -1;
+  if (sl.pending) HIP_TRY(hipEventSynchronize(sl.ev));
+  sl.pending = false;
+  if (sl.err != RTTDA_OK) return fail(sl.err, "slot %d stopped: %s", slot, sl.msg.c_str());
+  int64_t bad = -1;
+  rttda_status st = rttda_guard(sl.ctx, &bad);
+  if (first_bad_step) *first_bad_step = bad;
+  return st;
 }
 
 rttda_status rttda_pool_release(rttda_pool *pool, int32_t slot) {

@@ -114,12 +114,12 @@ def _rng(seed: int, tensor: int, q: int = 0) -> np.random.Generator:
 
 
 def round_bf16(x: np.ndarray) -> np.ndarray:
-    """Round FP32 values to the nearest BF16 (ties to even); returns FP32."""
+    """Round FP32 values to the nearest BF16 (ties to even); returns FP32.  (For finite values the
+    bit pattern plus 0x7FFF plus the kept lowest bit stays below 2^32, so 32-bit arithmetic is exact.)"""
     x = np.ascontiguousarray(x, dtype=np.float32)
-    u = x.view(np.uint32).astype(np.uint64)
-    lsb = (u >> 16) & 1
-    r = ((u + 0x7FFF + lsb) >> 16) << 16
-    out = r.astype(np.uint32).view(np.float32)
+    u = x.view(np.uint32)
+    r = (u + (np.uint32(0x7FFF) + ((u >> 16) & np.uint32(1)))) & np.uint32(0xFFFF0000)
+    out = r.view(np.float32)
     # NaN/Inf are not produced by this generator; keep them untouched anyway
     bad = ~np.isfinite(x)
     if bad.any():
@@ -142,9 +142,16 @@ def _store(x: np.ndarray, storage: str) -> np.ndarray:
     raise ValueError(f"unknown storage dtype {storage!r}")
 
 
+_UPPER = {}
+
+
 def _sym(m: np.ndarray) -> np.ndarray:
-    up = np.triu(m)
-    return up + np.triu(m, 1).T
+    """The upper triangle (with the diagonal) of m mirrored into the lower one."""
+    n = m.shape[0]
+    mask = _UPPER.get(n)
+    if mask is None:
+        mask = _UPPER[n] = np.triu(np.ones((n, n), dtype=bool))
+    return np.where(mask, m, m.T)
 
 
 def gen_b_ov(shape: Shape, seed: int, q: int) -> np.ndarray:
@@ -190,6 +197,58 @@ def make_problem(shape: Shape, seed: int) -> Problem:
         b_oo[q] = gen_b_oo(shape, seed, q)
         b_vv[q] = gen_b_vv(shape, seed, q)
     return Problem(shape, seed, e_occ, e_virt, b_ov, b_oo, b_vv, gen_mu(shape, seed))
+
+
+def factor_bits_range(shape: Shape, seed: int, q0: int, q1: int, pool=None):
+    """The BF16-stored factors of Q = q0..q1-1 (the same values as make_problem) as uint16 bit
+    patterns: (b_ov [n][o][v], b_oo [n][o][o], b_vv [n][v][v]).  Q values are drawn in parallel
+    when a concurrent.futures executor is given (each Q has its own stream)."""
+    if shape.storage != "bf16":
+        raise ValueError("factor_bits_range is for BF16 storage")
+    n, o, v = q1 - q0, shape.o, shape.v
+    out = (np.empty((n, o, v), np.uint16), np.empty((n, o, o), np.uint16), np.empty((n, v, v), np.uint16))
+
+    def one(q):
+        k = q - q0
+        out[0][k] = bf16_bits(gen_b_ov(shape, seed, q))
+        out[1][k] = bf16_bits(gen_b_oo(shape, seed, q))
+        out[2][k] = bf16_bits(gen_b_vv(shape, seed, q))
+
+    if pool is None:
+        for q in range(q0, q1):
+            one(q)
+    else:
+        list(pool.map(one, range(q0, q1)))
+    return out
+
+
+def upload_factors_streamed(shape: Shape, seed: int, device: str = "cuda:0", threads: int = 16, q_chunk: int = 64,
+                            progress=None):
+    """Device tensors of a BF16-stored problem too large to hold on the host in FP32 (the o240
+    shape's factors take 37 GB): the factors of make_problem drawn on the host a range of Q at a
+    time (threads in parallel) and copied to the device as BF16.  Returns the dict of
+    make_device_tensors (e_occ, e_virt, b_ov, b_oo, b_vv, mu), with exactly make_problem's values."""
+    import concurrent.futures as cf
+
+    import torch
+
+    o, v, nq = shape.o, shape.v, shape.nq
+    e_occ, e_virt = gen_energies(shape, seed)
+    out = {"e_occ": torch.from_numpy(e_occ).to(device), "e_virt": torch.from_numpy(e_virt).to(device),
+           "mu": torch.from_numpy(gen_mu(shape, seed)).to(device)}
+    dev = [torch.empty((nq, o, v), dtype=torch.bfloat16, device=device),
+           torch.empty((nq, o, o), dtype=torch.bfloat16, device=device),
+           torch.empty((nq, v, v), dtype=torch.bfloat16, device=device)]
+    with cf.ThreadPoolExecutor(max_workers=threads) as pool:
+        for q0 in range(0, nq, q_chunk):
+            q1 = min(nq, q0 + q_chunk)
+            bits = factor_bits_range(shape, seed, q0, q1, pool)
+            for t, b in zip(dev, bits):
+                t[q0:q1].view(torch.int16).copy_(torch.from_numpy(b.view(np.int16)))
+            if progress is not None:
+                progress(q1)
+    out.update(b_ov=dev[0], b_oo=dev[1], b_vv=dev[2])
+    return out
 
 
 def random_state(o: int, v: int, nrhs: int, seed: int, c0_scale: float = 1.0, c_scale: float = 1.0):

@@ -69,6 +69,7 @@ EXPORTS = {
                                         ctypes.POINTER(_I32)]),
     "rttda_pool_step": (ctypes.c_int, [_VP, _I64, ctypes.POINTER(_I32)]),
     "rttda_pool_poll": (ctypes.c_int, [_VP, _I32, ctypes.POINTER(_I64), ctypes.POINTER(_I32)]),
+    "rttda_pool_result": (ctypes.c_int, [_VP, _I32, ctypes.POINTER(_I64)]),
     "rttda_pool_release": (ctypes.c_int, [_VP, _I32]),
     "rttda_pool_usage": (ctypes.c_int, [_VP, ctypes.POINTER(_SZ), ctypes.POINTER(_I32)]),
     "rttda_set_profiling": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
@@ -87,6 +88,7 @@ EXPORTS = {
                                            ctypes.c_double, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "rttda_set_correlation": (ctypes.c_int, [_VP, _VP]),
+    "rttda_set_energy": (ctypes.c_int, [_VP, _VP]),
     "rttda_set_populations": (ctypes.c_int, [_VP, _I32, _VP, _VP]),
     "rttda_spectrum": (ctypes.c_int, [_VP, _I32, _VP, _I32, _I32, _D, _D, _I32, _D, _D, _I32, _VP]),
     "rttda_dipole_trace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
@@ -283,12 +285,14 @@ class Context:
 
     def propagate(self, pulses, dt: float, n_steps: int, c0, c, step0: int = 0, trace=None, norms=None,
                   want_trace: bool = True, want_norms: bool = False, integrator: str = "rk4", corr=None,
-                  pops=None, pop_vectors=None):
+                  pops=None, pop_vectors=None, energy=None):
         """Advance in place with RK4 (rttda_propagate) or the symplectic split operator
         (integrator="sso", rttda_propagate_sso).  corr: a device FP64 tensor [n_steps+1, nrhs, 2]
         that receives the time-correlation function (rttda_set_correlation), or None.  pops: a
         device FP64 tensor [n_steps+1, nrhs, k] that receives the populations of the k unit vectors
-        pop_vectors [k, o, v] at every step (rttda_set_populations), or None."""
+        pop_vectors [k, o, v] at every step (rttda_set_populations), or None.  energy: a device FP64
+        tensor [n_steps+1, nrhs] that receives <X|diag(0,A)|X> at every step (rttda_set_energy,
+        RK4 only), or None."""
         import torch
 
         if integrator not in ("rk4", "sso"):
@@ -309,6 +313,8 @@ class Context:
             k = int(pop_vectors.shape[0])
             _dev_check(pop_vectors, torch.float64, (k, self.o, self.v), "pop_vectors")
             _dev_check(pops, torch.float64, (n_steps + 1, nrhs, k), "pops")
+        if energy is not None:
+            _dev_check(energy, torch.float64, (n_steps + 1, nrhs), "energy")
         self._enter()
         try:
             try:
@@ -316,10 +322,13 @@ class Context:
                     _check(self.lib.rttda_set_correlation(self.handle, _ptr(corr)))
                 if pops is not None:
                     _check(self.lib.rttda_set_populations(self.handle, k, _ptr(pop_vectors), _ptr(pops)))
+                if energy is not None:
+                    _check(self.lib.rttda_set_energy(self.handle, _ptr(energy)))
             except RttdaError:
                 # the outputs apply to the next propagate call: none may stay pending for a later one
                 self.lib.rttda_set_correlation(self.handle, None)
                 self.lib.rttda_set_populations(self.handle, 0, None, None)
+                self.lib.rttda_set_energy(self.handle, None)
                 raise
             _check(fn(self.handle, nrhs, cp, float(dt), int(step0), int(n_steps), _ptr(c0), _ptr(c),
                       _ptr(trace) if trace is not None else None, _ptr(norms) if norms is not None else None))
@@ -548,6 +557,15 @@ class Pool:
         done, fin = ctypes.c_int64(), ctypes.c_int32()
         _check(self.lib.rttda_pool_poll(self.handle, int(slot), ctypes.byref(done), ctypes.byref(fin)))
         return done.value, bool(fin.value)
+
+    def result(self, slot: int) -> int:
+        """Wait for a slot and return the first step at which its norm guard tripped (-1 if
+        never); raises RttdaError with the slot's status if one of its chunks failed."""
+        bad = ctypes.c_int64(-1)
+        st = self.lib.rttda_pool_result(self.handle, int(slot), ctypes.byref(bad))
+        if st not in (OK, E_UNSTABLE):
+            _check(st)
+        return int(bad.value)
 
     def release(self, slot: int):
         _check(self.lib.rttda_pool_release(self.handle, int(slot)))

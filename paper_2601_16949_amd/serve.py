@@ -114,9 +114,9 @@ class Server:
         return slot
 
     def _retire(self, s: Slot, now: float):
+        bad = self.pool.result(s.pool_slot)  # the guard over all the request's chunks
         self.pool.release(s.pool_slot)
         tr = s.trace.cpu().numpy()[:, 0] if self.keep_traces else None
-        bad = s.ctx.guard()
         if bad != -1:
             raise rttda.RttdaError(rttda.E_UNSTABLE, f"request {s.req.rid}: norm guard at step {bad}")
         s.ctx.close()
