@@ -79,13 +79,14 @@ class Result:
 
 class Server:
     def __init__(self, budget_bytes: int, chunk_steps: int = 128, precision: str = "mixed", device: str = "cuda:0",
-                 keep_traces: bool = True, max_active: int = 64):
+                 keep_traces: bool = True, max_active: int = 64, progress=None):
         self.budget = int(budget_bytes)
         self.chunk = int(chunk_steps)
         self.precision = precision
         self.device = device
         self.keep_traces = keep_traces
         self.max_active = max_active
+        self.progress = progress  # called with a line of text when a request retires, or None
         self.pool = rttda.Pool(self.budget)
         self.peak_used = 0
         self.active: List[Slot] = []
@@ -121,6 +122,8 @@ class Server:
             raise rttda.RttdaError(rttda.E_UNSTABLE, f"request {s.req.rid}: norm guard at step {bad}")
         s.ctx.close()
         self.results[s.req.rid] = Result(s.req.rid, s.req.shape.o, s.req.n_steps, s.req.arrival, s.t_admit, now, tr)
+        if self.progress is not None:
+            self.progress(f"request {s.req.rid} (o={s.req.shape.o}, {s.req.n_steps} steps) done at {now:.2f} s")
 
     # ------------------------------------------------------------------------------------
     def run(self, requests: List[I.Request], time_scale: float = 1.0, realtime: bool = True) -> dict:
@@ -205,15 +208,19 @@ def main(argv=None):
     ap.add_argument("--chunk", type=int, default=100)
     ap.add_argument("--load", type=float, default=0.7)
     ap.add_argument("--seed", type=int, default=I.SEED_BASE + 5)
+    ap.add_argument("--verbose", action="store_true", help="a line on stderr per retired request")
     a = ap.parse_args(argv)
     budget = int(a.budget_gib * (1 << 30))
     burst = _scaled_requests(a.requests, a.seed, a.o_max, a.steps_scale, rate=1e9)
-    srv = Server(budget, chunk_steps=a.chunk, precision="mixed", keep_traces=False)
+    import sys
+
+    say = (lambda m: print(m, file=sys.stderr, flush=True)) if a.verbose else None
+    srv = Server(budget, chunk_steps=a.chunk, precision="mixed", keep_traces=False, progress=say)
     b = srv.run(burst, realtime=False)
     capacity = a.requests / b["makespan_s"]
     rate = a.load * capacity
     stream = _scaled_requests(a.requests, a.seed, a.o_max, a.steps_scale, rate=rate)
-    srv2 = Server(budget, chunk_steps=a.chunk, precision="mixed", keep_traces=False)
+    srv2 = Server(budget, chunk_steps=a.chunk, precision="mixed", keep_traces=False, progress=say)
     p = srv2.run(stream, realtime=True)
     torch.cuda.synchronize()
     print(json.dumps({"mix": {"requests": a.requests, "o": [10, a.o_max], "v": "7.5 o", "n_aux": "20 o",
