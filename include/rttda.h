@@ -208,6 +208,20 @@ rttda_status rttda_spectrum(void *stream, int32_t kind, const double *signal, in
 rttda_status rttda_dipole_trace(rttda_ctx *ctx, int32_t nrhs, const double *dir, const double *c0,
                                 const double *c, double *out);
 
+/* rttda_sigma without a context or workspace, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  desc
+ * describes the operator as for rttda_create, except that its workspace fields are ignored: the
+ * scratch is a static device array of 64 MiB that every device this entry point runs on keeps
+ * until the process ends.  Arguments and outputs are those of rttda_sigma, with 1 <= nrhs <= 64.
+ * RTTDA_E_NOMEM when the shape and nrhs need more scratch than the array holds (its partial slabs
+ * of the exchange are capped at 16 MiB, so larger problems use fewer Q splits than a context
+ * would).  Calls on one device share the array: overlapping calls race, so serialise them (one
+ * stream, or wait between streams); each call rewrites whatever it reads.  The device current on
+ * the calling thread must be desc->stream's.  Synchronises desc->stream once (after its small
+ * host-to-device copies) and returns with the sigma work queued on it.  Calls no allocator. */
+rttda_status rttda_sigma_noalloc(const rttda_desc *desc, int32_t nrhs, const double *field, const double *dir,
+                                 const double *c0, const double *c, double *s0, double *s);
+
 /* Synchronise the context's stream and report the norm guard of the last
  * rttda_propagate: *first_bad_step = -1 if it never tripped, else the absolute
  * step index; returns RTTDA_E_UNSTABLE in the latter case.  Covers

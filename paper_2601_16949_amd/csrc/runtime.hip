@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -72,7 +73,10 @@ struct Layout {
   int sk_max, sj_max;
 };
 
-Layout make_layout(int o, int v, int nq, int R, int prec) {
+// slab_bytes: workspace for the exchange's partial K slabs (at least 32 slabs); gemm_scratch: carve
+// the W scratch of the large-o GEMM exchange path where that path applies
+Layout make_layout(int o, int v, int nq, int R, int prec, size_t slab_bytes = SK_SLAB_BYTES,
+                   bool gemm_scratch = true) {
   Layout L{};
   const size_t ov = (size_t)o * v;
   const size_t ns = 2 * (size_t)R;
@@ -84,7 +88,7 @@ Layout make_layout(int o, int v, int nq, int R, int prec) {
   };
   L.nbf = field_blocks_a(v) * field_blocks_i(o);
   L.sj_max = nq > 0 ? std::min(SJ_MAX, nq) : 0;
-  L.sk_max = nq > 0 ? std::min({SK_MAX, nq, (int)std::max<size_t>(32, SK_SLAB_BYTES / (ns * ov * 4))}) : 0;
+  L.sk_max = nq > 0 ? std::min({SK_MAX, nq, (int)std::max<size_t>(32, slab_bytes / (ns * ov * 4))}) : 0;
   L.D = take(ov * 8);
   L.moo = take((size_t)R * o * o * 8);
   L.mov = take((size_t)R * ov * 8);
@@ -108,7 +112,8 @@ Layout make_layout(int o, int v, int nq, int R, int prec) {
   L.xref0 = take(ns * 8);
   L.epart = take((size_t)R * EP_BX_MAX * 8);
   L.scratch_bytes = 0;
-  if (prec == RTTDA_PREC_MIXED_BF16 && nq > 0 && o >= XGEMM_O_MIN && o <= 256 && o % 8 == 0 && v % 8 == 0) {
+  if (gemm_scratch && prec == RTTDA_PREC_MIXED_BF16 && nq > 0 && o >= XGEMM_O_MIN && o <= 256 && o % 8 == 0 &&
+      v % 8 == 0) {
     const size_t per_q = (size_t)v * ns * o * 4;  // W hi + lo for one Q at the largest RHS count
     L.scratch_bytes = std::min((size_t)nq * per_q, std::max(per_q, XGEMM_SCRATCH_MAX));
   }
@@ -679,6 +684,23 @@ rttda_status check_nrhs(const rttda_ctx *ctx, int nrhs) {
   return RTTDA_OK;
 }
 
+// sigma's device work once the directions (pulse table) and the E slots are on the device:
+// dipole blocks, stage copy, Coulomb pair and exchange, field product, s0 and the sigma epilogue
+rttda_status sigma_enqueue(rttda_ctx *ctx, int nrhs, const double *c0, const double *c, double *s0, double *s) {
+  hipStream_t hs = ctx->stream;
+  rttda_status st;
+  HIP_TRY(launch_mu_blocks(hs, ctx->d.mu, ctx->pulses(), ctx->o, ctx->v, nrhs, ctx->moo(), ctx->mov(), ctx->mvv()));
+  if ((st = to_stage_copy(ctx, c, nrhs)) != RTTDA_OK) return st;
+  if ((st = enqueue_two_electron(ctx, 2 * nrhs)) != RTTDA_OK) return st;
+  HIP_TRY(launch_field(hs, c, c0, ctx->moo(), ctx->mov(), ctx->mvv(), ctx->o, ctx->v, nrhs, ctx->F(), ctx->part()));
+  HIP_TRY(launch_scalar(hs, nrhs, ctx->L.nbf, 0, SM_SIGMA0 | SM_KEEP_E, 0.0, ctx->pulses(), ctx->state(),
+                        ctx->part(), ctx->sc(), const_cast<double *>(c0), ctx->acc0(), ctx->xs0(), nullptr,
+                        ctx->normref(), s0));
+  HIP_TRY(launch_epilogue(hs, ctx->prec, nrhs, ctx->o, ctx->v, nslab(ctx), 0, EP_SIGMA, 1, 0.0, ctx->D(), ctx->P(),
+                          ctx->F(), ctx->sc(), c, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, s));
+  return RTTDA_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -885,16 +907,7 @@ rttda_status rttda_sigma(rttda_ctx *ctx, int32_t nrhs, const double *field, cons
   HIP_TRY(hipMemcpyAsync(ctx->sc(), sc.data(), sc.size() * sizeof(double), hipMemcpyHostToDevice, hs));
   HIP_TRY(hipStreamSynchronize(hs));
   drop_graph(ctx);
-  HIP_TRY(launch_mu_blocks(hs, ctx->d.mu, ctx->pulses(), ctx->o, ctx->v, nrhs, ctx->moo(), ctx->mov(), ctx->mvv()));
-  if ((st = to_stage_copy(ctx, c, nrhs)) != RTTDA_OK) return st;
-  if ((st = enqueue_two_electron(ctx, 2 * nrhs)) != RTTDA_OK) return st;
-  HIP_TRY(launch_field(hs, c, c0, ctx->moo(), ctx->mov(), ctx->mvv(), ctx->o, ctx->v, nrhs, ctx->F(), ctx->part()));
-  HIP_TRY(launch_scalar(hs, nrhs, ctx->L.nbf, 0, SM_SIGMA0 | SM_KEEP_E, 0.0, ctx->pulses(), ctx->state(),
-                        ctx->part(), ctx->sc(), const_cast<double *>(c0), ctx->acc0(), ctx->xs0(), nullptr,
-                        ctx->normref(), s0));
-  HIP_TRY(launch_epilogue(hs, ctx->prec, nrhs, ctx->o, ctx->v, nslab(ctx), 0, EP_SIGMA, 1, 0.0, ctx->D(), ctx->P(),
-                          ctx->F(), ctx->sc(), c, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, s));
-  return RTTDA_OK;
+  return sigma_enqueue(ctx, nrhs, c0, c, s0, s);
 }
 
 rttda_status rttda_dipole_trace(rttda_ctx *ctx, int32_t nrhs, const double *dir, const double *c0, const double *c,
@@ -1611,3 +1624,111 @@ rttda_status rttda_guard(rttda_ctx *ctx, int64_t *first_bad_step) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------------------------
+// sigma for callers that cannot allocate device memory: the workspace is a static device array
+// ---------------------------------------------------------------------------------------------
+namespace {
+constexpr size_t NOALLOC_BYTES = (size_t)64 << 20;       // the static scratch of each device
+constexpr size_t NOALLOC_SLAB_BYTES = (size_t)16 << 20;  // of it, for the exchange's partial slabs
+constexpr int NOALLOC_MAX_RHS = 64;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+}  // namespace
+
+// Every device the library runs this entry point on holds its own copy until the process ends.
+// Host code reaches it only through the address hipGetSymbolAddress returns for the current
+// device (the name itself is a host-side stand-in).
+static __device__ __align__(256) char scratch[NOALLOC_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// The current device's address of `scratch`, looked up on the first call on that device.
+rttda_status scratch_address(void **out) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(RTTDA_E_UNSUPPORTED, "device %d beyond %d", dev, NOALLOC_MAX_DEVICES);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return fail(RTTDA_E_DEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return RTTDA_OK;
+}
+}  // namespace
+
+extern "C" rttda_status rttda_sigma_noalloc(const rttda_desc *desc, int32_t nrhs, const double *field,
+                                            const double *dir, const double *c0, const double *c, double *s0,
+                                            double *s) {
+  rttda_status st = validate_desc(desc, false);
+  if (st != RTTDA_OK) return st;
+  {
+    const void *ptrs[] = {desc->e_occ, desc->e_virt, desc->mu};
+    for (const void *p : ptrs)
+      if (!p || !aligned16(p)) return fail(RTTDA_E_INVAL, "e_occ, e_virt and mu must be non-NULL and 16-byte aligned");
+    if (desc->n_aux > 0)
+      for (const void *p : {desc->b_ov, desc->b_oo, desc->b_vv})
+        if (!p || !aligned16(p)) return fail(RTTDA_E_INVAL, "factors must be non-NULL and 16-byte aligned");
+  }
+  if (nrhs < 1 || nrhs > NOALLOC_MAX_RHS) return fail(RTTDA_E_INVAL, "nrhs=%d outside 1..%d", nrhs, NOALLOC_MAX_RHS);
+  if (!field || !dir || !c0 || !c || !s0 || !s) return fail(RTTDA_E_INVAL, "NULL array argument");
+  if (!aligned16(c0) || !aligned16(c) || !aligned16(s0) || !aligned16(s))
+    return fail(RTTDA_E_INVAL, "device arrays must be 16-byte aligned");
+  if ((st = check_dirs(dir, nrhs)) != RTTDA_OK) return st;
+  for (int r = 0; r < nrhs; ++r)
+    if (!std::isfinite(field[r])) return fail(RTTDA_E_INVAL, "field %d not finite", r);
+  const int o = desc->n_occ, v = desc->n_virt, nq = desc->n_aux, prec = desc->precision;
+  const Layout L = make_layout(o, v, nq, nrhs, prec, NOALLOC_SLAB_BYTES, false);
+  if (L.total > NOALLOC_BYTES)
+    return fail(RTTDA_E_NOMEM, "o=%d v=%d n_aux=%d nrhs=%d needs %zu bytes of scratch; the static scratch holds %zu",
+                o, v, nq, nrhs, L.total, NOALLOC_BYTES);
+  int xv = -1;
+  if (nq > 0) {
+    xv = auto_variant(prec, o, 2 * nrhs, v, L);  // no W scratch here, so never the large-o GEMM path
+    if (xv < 0) return fail(RTTDA_E_UNSUPPORTED, "no exchange kernel for o=%d in precision %d", o, prec);
+  }
+  void *base = nullptr;
+  if ((st = scratch_address(&base)) != RTTDA_OK) return st;
+  if (xv >= 0) HIP_TRY(variant_of(prec, xv)->prepare());
+
+  // a context over the static scratch: no pinned staging, events or second stream
+  rttda_ctx ctx;
+  ctx.d = *desc;
+  ctx.stream = static_cast<hipStream_t>(desc->stream);
+  ctx.o = o;
+  ctx.v = v;
+  ctx.nq = nq;
+  ctx.R = nrhs;
+  ctx.prec = prec;
+  ctx.ov = (size_t)o * v;
+  ctx.L = L;
+  ctx.ws = static_cast<char *>(base);
+  ctx.xvar = xv;
+  ctx.overlap = 2;
+  if (nq > 0) {
+    ctx.sk = auto_splits(variant_of(prec, xv), o, 2 * nrhs, v, nq, L.sk_max, L);
+    ctx.sj = L.sj_max;
+  }
+  // directions and field strengths: host arrays copied into the scratch, waited for before they
+  // leave scope
+  DevPulse hp[NOALLOC_MAX_RHS];
+  double hsc[NOALLOC_MAX_RHS * SC_STRIDE];
+  for (int r = 0; r < nrhs; ++r) {
+    memset(&hp[r], 0, sizeof(DevPulse));
+    hp[r].kind = RTTDA_PULSE_NONE;
+    memcpy(hp[r].dir, dir + 3 * r, 3 * sizeof(double));
+    for (int k = 0; k < SC_STRIDE; ++k) hsc[r * SC_STRIDE + k] = 0.0;
+    hsc[r * SC_STRIDE + SC_E] = field[r];
+  }
+  hipStream_t hs = ctx.stream;
+  HIP_TRY(hipMemcpyAsync(ctx.pulses(), hp, sizeof(DevPulse) * nrhs, hipMemcpyHostToDevice, hs));
+  HIP_TRY(hipMemcpyAsync(ctx.sc(), hsc, sizeof(double) * SC_STRIDE * nrhs, hipMemcpyHostToDevice, hs));
+  HIP_TRY(launch_gaps(hs, desc->e_occ, desc->e_virt, o, v, ctx.D()));
+  HIP_TRY(launch_set_state(hs, ctx.state(), 0, nullptr, nullptr, nullptr, nullptr, nullptr, 0));
+  HIP_TRY(hipStreamSynchronize(hs));
+  return sigma_enqueue(&ctx, nrhs, c0, c, s0, s);
+}

@@ -91,6 +91,8 @@ EXPORTS = {
     "rttda_set_energy": (ctypes.c_int, [_VP, _VP]),
     "rttda_set_populations": (ctypes.c_int, [_VP, _I32, _VP, _VP]),
     "rttda_spectrum": (ctypes.c_int, [_VP, _I32, _VP, _I32, _I32, _D, _D, _I32, _D, _D, _I32, _VP]),
+    "rttda_sigma_noalloc": (ctypes.c_int, [ctypes.POINTER(CDesc), _I32, ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_double), _VP, _VP, _VP, _VP]),
     "rttda_dipole_trace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "rttda_guard": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
@@ -450,6 +452,36 @@ class Context:
 
     def variant_name(self, k: int) -> str:
         return self.lib.rttda_exchange_variant_name(self.desc.precision, k).decode()
+
+
+def sigma_noalloc(dev: DeviceProblem, field: Sequence[float], dirs, c0, c, s0=None, s=None, stream=None):
+    """rttda_sigma_noalloc: s = H X for the operator dev without a context or workspace (the
+    library's static device scratch).  Returns (s0, s); s0 and s may be passed preallocated."""
+    import torch
+
+    lib = load()
+    nrhs = c.shape[0]
+    _dev_check(c0, torch.float64, (nrhs, 2), "c0")
+    _dev_check(c, torch.float64, (nrhs, 2, dev.o, dev.v), "c")
+    s0 = torch.empty_like(c0) if s0 is None else s0
+    s = torch.empty_like(c) if s is None else s
+    d = CDesc()
+    d.n_occ, d.n_virt, d.n_aux = dev.o, dev.v, dev.nq
+    d.precision = PREC_FP32 if dev.precision == "fp32" else PREC_MIXED_BF16
+    d.b_dtype = F32 if d.precision == PREC_FP32 else BF16
+    d.max_rhs = nrhs
+    d.cx = dev.cx
+    d.e_occ, d.e_virt, d.mu = _ptr(dev.e_occ), _ptr(dev.e_virt), _ptr(dev.mu)
+    if dev.nq > 0:
+        d.b_ov, d.b_oo, d.b_vv = _ptr(dev.b_ov), _ptr(dev.b_oo), _ptr(dev.b_vv)
+    st = stream if stream is not None else torch.cuda.current_stream(c.device)
+    d.stream = st.cuda_stream
+    f = (ctypes.c_double * nrhs)(*[float(x) for x in field])
+    dd = np.ascontiguousarray(np.asarray(dirs, dtype=np.float64).reshape(nrhs, 3))
+    dd = dd / np.linalg.norm(dd, axis=1, keepdims=True)
+    _check(lib.rttda_sigma_noalloc(ctypes.byref(d), nrhs, f, dd.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                   _ptr(c0), _ptr(c), _ptr(s0), _ptr(s)))
+    return s0, s
 
 
 def workspace_bytes(o: int, v: int, nq: int, precision: str, max_rhs: int) -> int:

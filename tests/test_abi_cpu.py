@@ -160,3 +160,19 @@ def test_pool_host_logic_without_device_work():
     assert lib.rttda_pool_create(1, None) == rttda.E_INVAL
     assert lib.rttda_pool_destroy(h) == rttda.OK
     assert lib.rttda_pool_destroy(None) == rttda.E_INVAL
+
+
+def test_sigma_noalloc_host_checks():
+    """rttda_sigma_noalloc refuses bad arguments and shapes beyond its static scratch before any
+    device work (the pointers below are never dereferenced)."""
+    lib = rttda.load()
+    f = (ctypes.c_double * 3)(0.0, 0.0, 0.0)
+    dirs = (ctypes.c_double * 9)(0, 0, 1, 0, 0, 1, 0, 0, 1)
+    fake = 1 << 20
+    assert lib.rttda_sigma_noalloc(None, 1, f, dirs, fake, fake, fake, fake) == rttda.E_INVAL
+    d = desc(o=240, v=1800, nq=8, max_rhs=3)
+    d.e_occ = d.e_virt = d.mu = d.b_ov = d.b_oo = d.b_vv = fake
+    assert lib.rttda_sigma_noalloc(ctypes.byref(d), 3, f, dirs, fake, fake, fake, fake) == rttda.E_NOMEM
+    assert "static scratch" in lib.rttda_last_error().decode()
+    assert lib.rttda_sigma_noalloc(ctypes.byref(d), 65, f, dirs, fake, fake, fake, fake) == rttda.E_INVAL
+    assert lib.rttda_sigma_noalloc(ctypes.byref(d), 1, f, dirs, fake + 8, fake, fake, fake) == rttda.E_INVAL
