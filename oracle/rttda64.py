@@ -514,15 +514,22 @@ class EigenRoute:
         y = self.to_eig(c0, C)
         R = rk4_amplification(-1j * self.w * dt)
         logR = np.log(R)
-        Uexc = self.U[1:, 1:]
+        Uexc = np.ascontiguousarray(self.U[1:, 1:])  # (BLAS takes contiguous operands only)
         o, v = self.op.o, self.op.v
+        moo, mov, mvv = blocks
         trace = np.empty(n_steps + 1)
         for n0 in range(0, n_steps + 1, block):
             n = np.arange(n0, min(n_steps + 1, n0 + block))
             Y = np.exp(np.outer(n, logR)) * y[None, :]  # rows: y_n = R^n y_0
-            Xc = (Y[:, 1:].real @ Uexc.T) + 1j * (Y[:, 1:].imag @ Uexc.T)  # amplitudes C_n (rows)
-            for k in range(n.size):
-                trace[n[k]] = dipole_expectation(blocks, Y[k, 0], Xc[k].reshape(o, v))
+            Yr, Yi = np.ascontiguousarray(Y[:, 1:].real), np.ascontiguousarray(Y[:, 1:].imag)
+            Xc = (Yr @ Uexc.T) + 1j * (Yi @ Uexc.T)  # amplitudes C_n (rows)
+            # Re <X_n | M | X_n> for the whole block, M X by the same rules as apply_dipole
+            C = Xc.reshape(n.size, o, v)
+            c0 = Y[:, 0]
+            F = (Xc.reshape(n.size * o, v) @ mvv).reshape(n.size, o, v) - np.matmul(moo, C) \
+                + SQRT2 * mov[None] * c0[:, None, None]
+            g = SQRT2 * np.sum(mov[None] * C, axis=(1, 2))
+            trace[n] = (np.conj(c0) * g).real + np.sum(np.conj(C) * F, axis=(1, 2)).real
         return trace
 
     def propagate_rk4_many(self, pulses, dt: float, n_steps: int, n_pop: int = 0, pop_every: int = 1,
