@@ -322,6 +322,11 @@ typedef struct rttda_tuning {
                                exchange, 2 = both in order on the context's stream; the
                                default is 1 when the exchange has at least 5e10 flops per
                                stage at max_rhs, else 2                                     */
+  int32_t small_path;       /* 1 = small-problem path: per RK4 stage one launch for the
+                               Coulomb and exchange partial sums and one single-workgroup
+                               launch for the whole stage epilogue (o*v <= 2048, max_rhs <= 64);
+                               2 = the general kernels; the default is 1 where it applies and
+                               the exchange has at most 2e9 flops per stage at max_rhs       */
 } rttda_tuning;
 rttda_status rttda_set_tuning(rttda_ctx *ctx, const rttda_tuning *t);
 rttda_status rttda_get_tuning(const rttda_ctx *ctx, rttda_tuning *t);

@@ -38,6 +38,25 @@ struct DevState {
 };
 constexpr int POP_MAX = 64;  // eigenstates per populations output
 
+constexpr double SQRT2 = 1.4142135623730951;
+constexpr double FWHM_TO_SIGMA = 2.35482;
+
+// Field of one pulse at time t (eqs. continuous wave, transform_limited, chirped_pulse).
+// Delta pulses act as a kick at t = 0 and contribute no continuous field.
+__device__ inline double pulse_field(const DevPulse &p, double t) {
+  if (p.kind == RTTDA_PULSE_CW) return p.e0 * sin(p.omega * t + p.phase);
+  if (p.kind == RTTDA_PULSE_GAUSS || p.kind == RTTDA_PULSE_CHIRP) {
+    const double s = p.fwhm / FWHM_TO_SIGMA;
+    const double tau = t - p.t0;
+    const double env = exp(-tau * tau / (2.0 * s * s));
+    const double arg = (p.kind == RTTDA_PULSE_GAUSS) ? p.omega * tau + p.phase
+                                                      : (p.omega + 0.5 * p.beta * tau) * tau + p.phase;
+    return p.e0 * env * sin(arg);
+  }
+  return 0.0;
+}
+
+
 // Per-RHS scalar slots (f64): g_re, g_im, E(t_stage), spare.
 constexpr int SC_STRIDE = 4;
 constexpr int SC_GRE = 0, SC_GIM = 1, SC_E = 2;
@@ -63,6 +82,17 @@ enum : int {
 
 // Epilogue modes.
 enum : int { EP_RK4 = 0, EP_SIGMA = 1, EP_ENERGY = 2 };
+// Small problems (o v <= SMALL_OV_MAX, at most SMALL_R_MAX RHS): one launch for the Coulomb and
+// exchange partial slabs of a stage, one single-workgroup launch for the whole stage epilogue.
+constexpr int SMALL_OV_MAX = 2048;
+constexpr int SMALL_R_MAX = 64;
+hipError_t launch_small_2e(hipStream_t s, int b_dtype, const void *Bov, const void *Boo, const void *Bvv,
+                           const float *X, int o, int v, int nq, int ns, int nsplit, float cx, float *P);
+hipError_t launch_small_epi(hipStream_t s, int prec, int R, int o, int v, int nslab, int stage, int use_field,
+                            int want_trace, double dt, const DevPulse *pulses, DevState *st, const double *D,
+                            const float *P, const double *moo, const double *mov, const double *mvv,
+                            const double *Xin, double *c, double *c0, double *acc, double *acc0, double *xs64,
+                            double *xs0, float *x32, __hip_bfloat16 *xhi, __hip_bfloat16 *xlo, double *normref);
 // Epilogue grid: blocks per RHS along ia (the energy partial sums come one per block)
 constexpr int EP_BX_MAX = 2048;
 int epilogue_blocks(long long ov);

@@ -8,26 +8,8 @@ namespace rttda {
 
 namespace {
 
-constexpr double SQRT2 = 1.4142135623730951;
-constexpr double FWHM_TO_SIGMA = 2.35482;
-
 __device__ __forceinline__ float load_b(const float *p, size_t i) { return p[i]; }
 __device__ __forceinline__ float load_b(const __hip_bfloat16 *p, size_t i) { return __bfloat162float(p[i]); }
-
-// Field of one pulse at time t (eqs. continuous wave, transform_limited, chirped_pulse).
-// Delta pulses act as a kick at t = 0 and contribute no continuous field.
-__device__ double pulse_field(const DevPulse &p, double t) {
-  if (p.kind == RTTDA_PULSE_CW) return p.e0 * sin(p.omega * t + p.phase);
-  if (p.kind == RTTDA_PULSE_GAUSS || p.kind == RTTDA_PULSE_CHIRP) {
-    const double s = p.fwhm / FWHM_TO_SIGMA;
-    const double tau = t - p.t0;
-    const double env = exp(-tau * tau / (2.0 * s * s));
-    const double arg = (p.kind == RTTDA_PULSE_GAUSS) ? p.omega * tau + p.phase
-                                                      : (p.omega + 0.5 * p.beta * tau) * tau + p.phase;
-    return p.e0 * env * sin(arg);
-  }
-  return 0.0;
-}
 
 template <typename T>
 __device__ __forceinline__ T wave_sum(T x) {

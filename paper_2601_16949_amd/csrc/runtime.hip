@@ -55,6 +55,8 @@ constexpr int SJ_MAX = 8;    // Coulomb second-product Q splits
 constexpr int SK_MAX = 768;  // exchange Q splits
 // exchange flops per stage (at the largest RHS count) from which the Coulomb pair gets its own stream
 constexpr double OVERLAP_MIN_FLOPS = 5e10;
+// exchange flops per stage (at the largest RHS count) up to which small shapes take the small path
+constexpr double SMALL_MAX_FLOPS = 2e9;
 // the exchange's partial K slabs (one per split) take at most this much workspace, or 32 slabs
 constexpr size_t SK_SLAB_BYTES = (size_t)256 << 20;
 constexpr size_t ALIGN = 256;
@@ -242,6 +244,9 @@ struct rttda_ctx {
   hipStream_t aux = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int overlap = 2;  // 1: Coulomb pair on the second stream, 2: in order on the context's stream
+  // small problems: the stage's Coulomb + exchange slabs in one launch (small_splits slabs) and the
+  // RK4 stage epilogue in one single-workgroup launch
+  int small = 0, small_splits = 0;
   double *corr_next = nullptr;  // time-correlation output of the next propagate call
   double *energy_next = nullptr;  // energy output of the next propagate call
   double *pops_next = nullptr;  // populations output of the next propagate call, its vectors and count
@@ -413,6 +418,13 @@ rttda_status enqueue_two_electron(rttda_ctx *ctx, int ns) {
   const int ov = (int)ctx->ov;
   hipStream_t s = ctx->stream;
   const bool pr = ctx->prof.on;
+  if (ctx->small) {
+    if (pr) HIP_TRY(ctx->prof.begin(PC_EXCHANGE, s));
+    HIP_TRY(launch_small_2e(s, ctx->d.b_dtype, ctx->d.b_ov, ctx->d.b_oo, ctx->d.b_vv, ctx->x32(), ctx->o, ctx->v,
+                            ctx->nq, ns, ctx->small_splits, (float)ctx->d.cx, ctx->P()));
+    if (pr) HIP_TRY(ctx->prof.end(PC_EXCHANGE, s));
+    return RTTDA_OK;
+  }
   // the Coulomb pair and the exchange read the same stage copy and write disjoint partial slabs
   const bool fork = ctx->aux != nullptr && ctx->overlap == 1;
   hipStream_t sc = fork ? ctx->aux : s;
@@ -438,13 +450,34 @@ rttda_status enqueue_two_electron(rttda_ctx *ctx, int ns) {
   return RTTDA_OK;
 }
 
-int nslab(const rttda_ctx *ctx) { return ctx->nq > 0 ? ctx->sj + ctx->sk : 0; }
+int nslab(const rttda_ctx *ctx) { return ctx->nq > 0 ? (ctx->small ? ctx->small_splits : ctx->sj + ctx->sk) : 0; }
+
+// the small path applies to the shape (o v and the RHS count within its single-workgroup limits)
+bool small_fits(int o, int v, int R) { return (long long)o * v <= SMALL_OV_MAX && R <= SMALL_R_MAX; }
 
 // One RK4 step (4 stages) on the context's stream.
 rttda_status enqueue_step(rttda_ctx *ctx, int nrhs, double dt, bool has_field, bool corr, bool pops, bool energy,
                           double *c0, double *c) {
   hipStream_t s = ctx->stream;
   const int o = ctx->o, v = ctx->v;
+  if (ctx->small) {  // two launches per stage
+    for (int stage = 0; stage < 4; ++stage) {
+      double *Xin = stage == 0 ? c : ctx->xs64();
+      rttda_status st = enqueue_two_electron(ctx, 2 * nrhs);
+      if (st != RTTDA_OK) return st;
+      const bool pr = ctx->prof.on;
+      if (pr) HIP_TRY(ctx->prof.begin(PC_EPILOGUE, s));
+      if (corr && stage == 0) HIP_TRY(launch_corr(s, nrhs, ctx->ov, c, c0, ctx->xref(), ctx->xref0(), ctx->state()));
+      if (pops && stage == 0) HIP_TRY(launch_pop(s, nrhs, ctx->ov, c, ctx->state()));
+      HIP_TRY(launch_small_epi(s, ctx->prec, nrhs, o, v, nslab(ctx), stage, has_field ? 1 : 0, stage == 0 ? 1 : 0, dt,
+                               ctx->pulses(), ctx->state(), ctx->D(), ctx->P(), ctx->moo(), ctx->mov(), ctx->mvv(), Xin,
+                               c, c0, ctx->acc(), ctx->acc0(), ctx->xs64(), ctx->xs0(), ctx->x32(), ctx->xhi(),
+                               ctx->xlo(), ctx->normref()));
+      if (pr) HIP_TRY(ctx->prof.end(PC_EPILOGUE, s));
+    }
+    (void)energy;  // the small epilogue writes the energy sample itself (stage 0)
+    return RTTDA_OK;
+  }
   for (int stage = 0; stage < 4; ++stage) {
     double *Xin = stage == 0 ? c : ctx->xs64();
     double *X0 = stage == 0 ? c0 : ctx->xs0();
@@ -761,6 +794,11 @@ rttda_status rttda_create(const rttda_desc *desc, rttda_ctx **out) {
     // the Coulomb pair runs alongside the exchange only where the exchange is long enough to
     // cover the cost of the fork and join (small problems and many concurrent contexts lose)
     ctx->overlap = 4.0 * ctx->nq * (double)ctx->ov * (ctx->o + ctx->v) * ctx->R >= OVERLAP_MIN_FLOPS ? 1 : 2;
+    // the small path: at most 2e9 exchange flops per stage (a few tens of microseconds of FP32 FMA),
+    // Q split so that the grid has about 256 workgroups
+    ctx->small_splits = std::max(1, std::min({(256 + 2 * ctx->R - 1) / (2 * ctx->R), ctx->nq, L.sj_max + L.sk_max}));
+    ctx->small = small_fits(ctx->o, ctx->v, ctx->R) &&
+                 4.0 * ctx->nq * (double)ctx->ov * (ctx->o + ctx->v) * ctx->R <= SMALL_MAX_FLOPS ? 1 : 0;
   }
   hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&ctx->h_pulses), sizeof(DevPulse) * ctx->R);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->upload_ev, hipEventDisableTiming);
@@ -859,6 +897,15 @@ rttda_status rttda_set_tuning(rttda_ctx *ctx, const rttda_tuning *t) {
     if (t->overlap != 1 && t->overlap != 2) return fail(RTTDA_E_INVAL, "overlap must be 0, 1 or 2");
     ctx->overlap = t->overlap;
   }
+  // an explicit exchange tile or split count asks for the general kernels
+  if ((t->exchange_variant || t->exchange_splits) && !t->small_path) ctx->small = 0;
+  if (t->small_path) {
+    if (t->small_path != 1 && t->small_path != 2) return fail(RTTDA_E_INVAL, "small_path must be 0, 1 or 2");
+    if (t->small_path == 1 && (!small_fits(ctx->o, ctx->v, ctx->R) || ctx->nq == 0))
+      return fail(RTTDA_E_UNSUPPORTED, "the small path takes o*v <= %d, max_rhs <= %d and n_aux > 0", SMALL_OV_MAX,
+                  SMALL_R_MAX);
+    ctx->small = t->small_path == 1 ? 1 : 0;
+  }
   if (t->steps_per_graph) ctx->steps_per_graph = t->steps_per_graph;
   drop_graph(ctx);
   return RTTDA_OK;
@@ -873,6 +920,7 @@ rttda_status rttda_get_tuning(const rttda_ctx *ctx, rttda_tuning *t) {
   t->steps_per_graph = ctx->steps_per_graph;
   t->exchange_chunk = ctx->qchunk;
   t->overlap = ctx->overlap;
+  t->small_path = ctx->small ? 1 : 2;
   return RTTDA_OK;
 }
 
@@ -1137,12 +1185,22 @@ rttda_status propagate_impl(rttda_ctx *ctx, int32_t nrhs, const rttda_pulse *pul
   }
   for (int64_t k = done; k < n_steps; ++k)
     if ((st = step()) != RTTDA_OK) return st;
-  // final trace sample at step0 + n_steps
+  // final samples at step0 + n_steps
+  if (corr) HIP_TRY(launch_corr(hs, nrhs, ctx->ov, c, c0, ctx->xref(), ctx->xref0(), ctx->state()));
+  if (pops) HIP_TRY(launch_pop(hs, nrhs, ctx->ov, c, ctx->state()));
+  if (ctx->small && integ == INTEG_RK4) {  // the small epilogue's own sums, as at every step
+    if (energy) {  // the energy sample needs one more product A c
+      if ((st = to_stage_copy(ctx, c, nrhs)) != RTTDA_OK) return st;
+      if ((st = enqueue_two_electron(ctx, 2 * nrhs)) != RTTDA_OK) return st;
+    }
+    HIP_TRY(launch_small_epi(hs, ctx->prec, nrhs, o, v, energy ? nslab(ctx) : 0, -1, 0, 1, dt, ctx->pulses(),
+                             ctx->state(), ctx->D(), ctx->P(), ctx->moo(), ctx->mov(), ctx->mvv(), c, c, c0, ctx->acc(),
+                             ctx->acc0(), ctx->xs64(), ctx->xs0(), ctx->x32(), ctx->xhi(), ctx->xlo(), ctx->normref()));
+    return RTTDA_OK;
+  }
   HIP_TRY(launch_field(hs, c, c0, ctx->moo(), ctx->mov(), ctx->mvv(), o, v, nrhs, ctx->F(), ctx->part()));
   HIP_TRY(launch_scalar(hs, nrhs, ctx->L.nbf, 0, SM_TRACE, dt, ctx->pulses(), ctx->state(), ctx->part(), ctx->sc(),
                         c0, ctx->acc0(), ctx->xs0(), nullptr, ctx->normref(), nullptr));
-  if (corr) HIP_TRY(launch_corr(hs, nrhs, ctx->ov, c, c0, ctx->xref(), ctx->xref0(), ctx->state()));
-  if (pops) HIP_TRY(launch_pop(hs, nrhs, ctx->ov, c, ctx->state()));
   if (energy) {  // the final energy sample needs one more product A c
     if ((st = to_stage_copy(ctx, c, nrhs)) != RTTDA_OK) return st;
     if ((st = enqueue_two_electron(ctx, 2 * nrhs)) != RTTDA_OK) return st;
