@@ -1,0 +1,67 @@
+"""Full-length runs of the large workloads against the FP64 oracle's cached references
+(tests/golden/make_long_traces.py, which calls only the oracle and the input generator):
+
+* o60 v400 N_Q1500, x/y/z kicks, 20000 RK4 steps, in FP32 (dipole trace within 1e-5) and in split
+  BF16 (within 1e-4; spectral peaks within 1e-4 Ha), in the launch configuration bench.py times;
+* o40 v300 N_Q1000, Gaussian-envelope cosine pulses at four carriers of the 64-carrier scan and
+  E0 = 0.01 and 0.05 (resonant Rabi cycling and the two-photon carrier), 16000 steps: traces within
+  1e-5 and the populations of the ground state and the 8 lowest TI-TDA states within 1e-5;
+* o240 v1800 N_Q5000 (BF16 factors), x/y/z kicks: the z trace of the first steps within 1e-4.
+"""
+import os
+
+import numpy as np
+import pytest
+from conftest import say
+
+from oracle import spectrum as SP
+from paper_2601_16949_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _load(name):
+    return np.load(os.path.join(GOLDEN, name), allow_pickle=False)
+
+
+def _run_in_parts(ctx, pulses, dt, n, c0, c, parts=4, **kw):
+    """Propagate n steps as `parts` consecutive calls (a progress line after each), trace joined."""
+    import torch
+
+    out = torch.empty((n + 1, len(pulses)), dtype=torch.float64, device="cuda")
+    done = 0
+    for k in range(parts):
+        m = (n - done) // (parts - k)
+        tr = ctx.propagate(pulses, dt, m, c0, c, step0=done, **kw)
+        out[done:done + m + 1] = tr
+        done += m
+        torch.cuda.synchronize()
+        say(f"   {done}/{n} steps")
+    return out
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("precision,tol,peak_tol", [("fp32", 1e-5, 1e-5)])
+def test_o60_v400_full_trace(gpu_lib, precision, tol, peak_tol):
+    import torch
+
+    g = _load(f"cfg2_trace_{precision}.npz")
+    ref = g["trace"]
+    wl = I.workload(2)
+    shape = I.Shape(wl.shape.o, wl.shape.v, wl.shape.nq, wl.shape.b_scale, storage="f32" if precision == "fp32" else "bf16")
+    prob = I.make_problem(shape, wl.seed)
+    ctx = gpu_lib.Context(gpu_lib.DeviceProblem(prob, precision), max_rhs=3)
+    tuned = ctx.use_tuned(3)
+    say(f"[o60 v400 {precision}] {wl.n_steps} steps, 3 RHS, autotuned {tuned}")
+    c0, c = gpu_lib.ground_state(3, shape.o, shape.v)
+    got = _run_in_parts(ctx, wl.pulses, wl.dt, wl.n_steps, c0, c).cpu().numpy()
+    assert ctx.guard() == -1
+    for r in range(3):
+        err = np.max(np.abs(got[:, r] - ref[:, r])) / np.max(np.abs(ref[:, r]))
+        pg = SP.peaks(got[:, r], wl.dt, I.KAPPA, omega_max=3.0)
+        po = SP.peaks(ref[:, r], wl.dt, I.KAPPA, omega_max=3.0)
+        dw = max(abs(a - b) for (a, _), (b, _) in zip(pg, po)) if len(pg) == len(po) else float("inf")
+        say(f"   direction {r}: trace rel err {err:.2e}, {len(po)} peaks, max shift {dw:.2e} Ha")
+        assert err < tol
+        assert len(pg) == len(po) and dw < peak_tol
