@@ -327,6 +327,9 @@ typedef struct rttda_tuning {
                                launch for the whole stage epilogue (o*v <= 2048, max_rhs <= 64);
                                2 = the general kernels; the default is 1 where it applies and
                                the exchange has at most 2e9 flops per stage at max_rhs       */
+  int32_t coulomb_path;     /* 1 = the Coulomb pair as vector-unit GEMVs, 2 = as skinny GEMMs
+                               on the FP32 matrix cores; the default is 2 from 16 RHS
+                               (max_rhs), else 1                                              */
 } rttda_tuning;
 rttda_status rttda_set_tuning(rttda_ctx *ctx, const rttda_tuning *t);
 rttda_status rttda_get_tuning(const rttda_ctx *ctx, rttda_tuning *t);

@@ -86,6 +86,13 @@ enum : int { EP_RK4 = 0, EP_SIGMA = 1, EP_ENERGY = 2 };
 // exchange partial slabs of a stage, one single-workgroup launch for the whole stage epilogue.
 constexpr int SMALL_OV_MAX = 2048;
 constexpr int SMALL_R_MAX = 64;
+// LDS of the two small-path kernels: the epilogue stages one RHS's X (two planes), mu_vv and mu_oo
+// in FP64, the partial-sum kernel a slice's X and W and one Q's B_vv and B_oo in FP32
+constexpr int SMALL_LDS_DOUBLES = 12288;
+inline bool small_shape_ok(int o, int v) {
+  return (long long)o * v <= SMALL_OV_MAX && 2LL * o * v + (long long)v * v + (long long)o * o <= SMALL_LDS_DOUBLES;
+}
+hipError_t prepare_small();  // one-time kernel attributes (dynamic LDS); call outside graph capture
 hipError_t launch_small_2e(hipStream_t s, int b_dtype, const void *Bov, const void *Boo, const void *Bvv,
                            const float *X, int o, int v, int nq, int ns, int nsplit, float cx, float *P);
 hipError_t launch_small_epi(hipStream_t s, int prec, int R, int o, int v, int nslab, int stage, int use_field,
@@ -116,6 +123,12 @@ hipError_t launch_gemv1(hipStream_t s, int b_dtype, const void *B, const float *
                         float *dpart);
 hipError_t launch_gemv2(hipStream_t s, int b_dtype, const void *B, const float *dvec, int nq, int ov, int ns,
                         int nsplit, float *P);
+// The same pair on the FP32 matrix cores for batches of many slices (the context's 2 max_rhs >= 32):
+// d in nes ia chunks (coulomb_mfma_chunks, at most GEMV1_CHUNKS_MAX) summed into chunk slot 0 of
+// dpart, then the partial slabs P[split][s][ia] of J.
+int coulomb_mfma_chunks(int nq, int ov);
+hipError_t launch_coulomb_mfma(hipStream_t s, int b_dtype, const void *B, const float *X, int nq, int ov, int ns,
+                               int nes, int nsplit, float *dpart, float *P);
 hipError_t launch_field(hipStream_t s, const double *X, const double *X0, const double *moo, const double *mov,
                         const double *mvv, int o, int v, int R, double *F, double *part);
 hipError_t launch_scalar(hipStream_t s, int R, int nbf, int stage, int mode, double dt, const DevPulse *pulses,

@@ -57,6 +57,9 @@ constexpr int SK_MAX = 768;  // exchange Q splits
 constexpr double OVERLAP_MIN_FLOPS = 5e10;
 // exchange flops per stage (at the largest RHS count) up to which small shapes take the small path
 constexpr double SMALL_MAX_FLOPS = 2e9;
+constexpr int SMALL_SPLITS = 64;
+// slices (2 max_rhs) from which the Coulomb pair runs on the matrix cores
+constexpr int COUL_MFMA_MIN_SLICES = 32;
 // the exchange's partial K slabs (one per split) take at most this much workspace, or 32 slabs
 constexpr size_t SK_SLAB_BYTES = (size_t)256 << 20;
 constexpr size_t ALIGN = 256;
@@ -247,6 +250,8 @@ struct rttda_ctx {
   // small problems: the stage's Coulomb + exchange slabs in one launch (small_splits slabs) and the
   // RK4 stage epilogue in one single-workgroup launch
   int small = 0, small_splits = 0;
+  // Coulomb pair on the matrix cores (batches of many slices) instead of the vector-unit GEMVs
+  int coul_mfma = 0;
   double *corr_next = nullptr;  // time-correlation output of the next propagate call
   double *energy_next = nullptr;  // energy output of the next propagate call
   double *pops_next = nullptr;  // populations output of the next propagate call, its vectors and count
@@ -433,9 +438,14 @@ rttda_status enqueue_two_electron(rttda_ctx *ctx, int ns) {
     HIP_TRY(hipStreamWaitEvent(ctx->aux, ctx->ev_fork, 0));
   }
   if (pr) HIP_TRY(ctx->prof.begin(PC_COULOMB, sc));
-  const int nes = gemv1_chunks(ctx->nq, ov);
-  HIP_TRY(launch_gemv1(sc, ctx->d.b_dtype, ctx->d.b_ov, ctx->x32(), ctx->nq, ov, ns, nes, ctx->dvec()));
-  HIP_TRY(launch_gemv2(sc, ctx->d.b_dtype, ctx->d.b_ov, ctx->dvec(), ctx->nq, ov, ns, ctx->sj, ctx->P()));
+  if (ctx->coul_mfma) {
+    HIP_TRY(launch_coulomb_mfma(sc, ctx->d.b_dtype, ctx->d.b_ov, ctx->x32(), ctx->nq, ov, ns,
+                                coulomb_mfma_chunks(ctx->nq, ov), ctx->sj, ctx->dvec(), ctx->P()));
+  } else {
+    const int nes = gemv1_chunks(ctx->nq, ov);
+    HIP_TRY(launch_gemv1(sc, ctx->d.b_dtype, ctx->d.b_ov, ctx->x32(), ctx->nq, ov, ns, nes, ctx->dvec()));
+    HIP_TRY(launch_gemv2(sc, ctx->d.b_dtype, ctx->d.b_ov, ctx->dvec(), ctx->nq, ov, ns, ctx->sj, ctx->P()));
+  }
   if (pr) HIP_TRY(ctx->prof.end(PC_COULOMB, sc));
   if (fork) HIP_TRY(hipEventRecord(ctx->ev_join, ctx->aux));
   const ExchangeVariant *x = variant_of(ctx->prec, ctx->xvar);
@@ -453,7 +463,7 @@ rttda_status enqueue_two_electron(rttda_ctx *ctx, int ns) {
 int nslab(const rttda_ctx *ctx) { return ctx->nq > 0 ? (ctx->small ? ctx->small_splits : ctx->sj + ctx->sk) : 0; }
 
 // the small path applies to the shape (o v and the RHS count within its single-workgroup limits)
-bool small_fits(int o, int v, int R) { return (long long)o * v <= SMALL_OV_MAX && R <= SMALL_R_MAX; }
+bool small_fits(int o, int v, int R) { return small_shape_ok(o, v) && R <= SMALL_R_MAX; }
 
 // One RK4 step (4 stages) on the context's stream.
 rttda_status enqueue_step(rttda_ctx *ctx, int nrhs, double dt, bool has_field, bool corr, bool pops, bool energy,
@@ -776,6 +786,7 @@ rttda_status rttda_create(const rttda_desc *desc, rttda_ctx **out) {
       return fail(RTTDA_E_UNSUPPORTED, "no exchange kernel for o=%d in precision %d", desc->n_occ, desc->precision);
   }
   if (xv >= 0) HIP_TRY(variant_of(desc->precision, xv)->prepare());
+  HIP_TRY(prepare_small());
   rttda_ctx *ctx = new rttda_ctx();
   ctx->d = *desc;
   ctx->stream = static_cast<hipStream_t>(desc->stream);
@@ -794,9 +805,10 @@ rttda_status rttda_create(const rttda_desc *desc, rttda_ctx **out) {
     // the Coulomb pair runs alongside the exchange only where the exchange is long enough to
     // cover the cost of the fork and join (small problems and many concurrent contexts lose)
     ctx->overlap = 4.0 * ctx->nq * (double)ctx->ov * (ctx->o + ctx->v) * ctx->R >= OVERLAP_MIN_FLOPS ? 1 : 2;
-    // the small path: at most 2e9 exchange flops per stage (a few tens of microseconds of FP32 FMA),
-    // Q split so that the grid has about 256 workgroups
-    ctx->small_splits = std::max(1, std::min({(256 + 2 * ctx->R - 1) / (2 * ctx->R), ctx->nq, L.sj_max + L.sk_max}));
+    // the small path: at most 2e9 exchange flops per stage (a few tens of microseconds of FP32 FMA);
+    // up to SMALL_SPLITS Q ranges (the epilogue adds one slab per range)
+    ctx->small_splits = std::max(1, std::min({SMALL_SPLITS, ctx->nq, L.sj_max + L.sk_max}));
+    ctx->coul_mfma = 2 * ctx->R >= COUL_MFMA_MIN_SLICES ? 1 : 0;
     ctx->small = small_fits(ctx->o, ctx->v, ctx->R) &&
                  4.0 * ctx->nq * (double)ctx->ov * (ctx->o + ctx->v) * ctx->R <= SMALL_MAX_FLOPS ? 1 : 0;
   }
@@ -899,6 +911,10 @@ rttda_status rttda_set_tuning(rttda_ctx *ctx, const rttda_tuning *t) {
   }
   // an explicit exchange tile or split count asks for the general kernels
   if ((t->exchange_variant || t->exchange_splits) && !t->small_path) ctx->small = 0;
+  if (t->coulomb_path) {
+    if (t->coulomb_path != 1 && t->coulomb_path != 2) return fail(RTTDA_E_INVAL, "coulomb_path must be 0, 1 or 2");
+    ctx->coul_mfma = t->coulomb_path == 2 ? 1 : 0;
+  }
   if (t->small_path) {
     if (t->small_path != 1 && t->small_path != 2) return fail(RTTDA_E_INVAL, "small_path must be 0, 1 or 2");
     if (t->small_path == 1 && (!small_fits(ctx->o, ctx->v, ctx->R) || ctx->nq == 0))
@@ -921,6 +937,7 @@ rttda_status rttda_get_tuning(const rttda_ctx *ctx, rttda_tuning *t) {
   t->exchange_chunk = ctx->qchunk;
   t->overlap = ctx->overlap;
   t->small_path = ctx->small ? 1 : 2;
+  t->coulomb_path = ctx->coul_mfma ? 2 : 1;
   return RTTDA_OK;
 }
 

@@ -50,7 +50,7 @@ class CTuning(ctypes.Structure):
     _fields_ = [("exchange_variant", ctypes.c_int32), ("exchange_splits", ctypes.c_int32),
                 ("coulomb_splits", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("steps_per_graph", ctypes.c_int32), ("exchange_chunk", ctypes.c_int32),
-                ("overlap", ctypes.c_int32), ("small_path", ctypes.c_int32)]
+                ("overlap", ctypes.c_int32), ("small_path", ctypes.c_int32), ("coulomb_path", ctypes.c_int32)]
 
 
 class CProfile(ctypes.Structure):
@@ -419,9 +419,9 @@ class Context:
         return int(bad.value)
 
     def set_tuning(self, exchange_variant=0, exchange_splits=0, coulomb_splits=0, use_graph=0, steps_per_graph=0,
-                   exchange_chunk=0, overlap=0, small_path=0):
+                   exchange_chunk=0, overlap=0, small_path=0, coulomb_path=0):
         t = CTuning(exchange_variant, exchange_splits, coulomb_splits, use_graph, steps_per_graph, exchange_chunk,
-                    overlap, small_path)
+                    overlap, small_path, coulomb_path)
         _check(self.lib.rttda_set_tuning(self.handle, ctypes.byref(t)))
 
     def get_tuning(self) -> dict:

@@ -32,9 +32,50 @@ def request_flops(shape: I.Shape, n_steps: int) -> float:
     return n_steps * 4.0 * (8.0 * shape.nq * ov + 4.0 * shape.nq * ov * (shape.o + shape.v))
 
 
+def padded_sizes(o: int, v: int):
+    """Orbital counts a request is served at: v up to a multiple of 8 and o up to an even count (a
+    multiple of 8 from 121 on), the sizes the direct-to-LDS and large-o GEMM exchange kernels take.
+    The added orbitals carry zero factors and zero dipoles, so their amplitudes stay exactly zero
+    and the request's own amplitudes follow the same equations (only zero terms join the sums)."""
+    vp = (v + 7) // 8 * 8
+    op = (o + 7) // 8 * 8 if o > 120 else (o + 1) // 2 * 2
+    return op, vp
+
+
+def padded_tensors(shape: I.Shape, t: dict, device: str):
+    """The request's tensors embedded in the padded sizes (zero factors and dipoles for the added
+    orbitals; their energies repeat the highest occupied and lowest virtual level, so the gaps of A
+    stay within the request's own range)."""
+    import torch
+
+    o, v = shape.o, shape.v
+    op, vp = padded_sizes(o, v)
+    if (op, vp) == (o, v):
+        return t
+    out = {}
+    out["e_occ"] = torch.cat([t["e_occ"], t["e_occ"][-1:].expand(op - o)]).contiguous()
+    out["e_virt"] = torch.cat([t["e_virt"][:1].expand(vp - v), t["e_virt"]]).contiguous()
+    # (added virtuals go first so that e_virt stays sorted; the factor and dipole columns follow)
+    nq = shape.nq
+    dt = t["b_ov"].dtype
+    b_ov = torch.zeros((nq, op, vp), dtype=dt, device=device)
+    b_ov[:, :o, vp - v:] = t["b_ov"]
+    b_oo = torch.zeros((nq, op, op), dtype=dt, device=device)
+    b_oo[:, :o, :o] = t["b_oo"]
+    b_vv = torch.zeros((nq, vp, vp), dtype=dt, device=device)
+    b_vv[:, vp - v:, vp - v:] = t["b_vv"]
+    n, npd = o + v, op + vp
+    mu = torch.zeros((3, npd, npd), dtype=t["mu"].dtype, device=device)
+    idx = torch.cat([torch.arange(o), op + (vp - v) + torch.arange(v)]).to(device)
+    mu[:, idx[:, None], idx[None, :]] = t["mu"]
+    out.update(b_ov=b_ov, b_oo=b_oo, b_vv=b_vv, mu=mu)
+    return out
+
+
 def footprint(shape: I.Shape, n_steps: int, precision: str) -> int:
-    """HBM bytes a resident request holds."""
-    o, v, nq = shape.o, shape.v, shape.nq
+    """HBM bytes a resident request holds (at its padded sizes)."""
+    o, v = padded_sizes(shape.o, shape.v)
+    nq = shape.nq
     bsz = 4 if precision == "fp32" else 2
     factors = nq * (o * v + o * o + v * v) * bsz
     other = (o + v) * 8 + 3 * (o + v) ** 2 * 8
@@ -105,13 +146,18 @@ class Server:
         stream = torch.cuda.Stream(device=self.device)
         with torch.cuda.stream(stream):
             t = I.make_device_tensors(req.shape, req.seed, device=self.device)
-            dev = rttda.DeviceProblem.from_tensors(req.shape, t, self.precision)
+            op, vp = padded_sizes(req.shape.o, req.shape.v)
+            shp = I.Shape(op, vp, req.shape.nq, req.shape.b_scale, storage=req.shape.storage)
+            dev = rttda.DeviceProblem.from_tensors(shp, padded_tensors(req.shape, t, self.device), self.precision)
             ctx = rttda.Context(dev, max_rhs=1, stream=stream, sync_streams=False)
-            c0, c = rttda.ground_state(1, req.shape.o, req.shape.v, device=self.device)
+            c0, c = rttda.ground_state(1, op, vp, device=self.device)
             trace = torch.empty((req.n_steps + 1, 1), dtype=torch.float64, device=self.device)
         slot = Slot(req, ctx, dev, c0, c, trace, stream, nb, now)
         slot.pool_slot = self.pool.admit(ctx, [req.pulse], req.dt, req.n_steps, c0, c, trace, footprint=nb)
         self.peak_used = max(self.peak_used, self.used)
+        if self.progress is not None:
+            self.progress(f"request {req.rid} (o={req.shape.o}, {req.n_steps} steps, {nb / 2 ** 30:.2f} GiB) admitted "
+                          f"at {now:.2f} s")
         return slot
 
     def _retire(self, s: Slot, now: float):
@@ -137,8 +183,13 @@ class Server:
         t0 = time.perf_counter()
         clock = lambda: time.perf_counter() - t0  # noqa: E731
         max_concurrent = 0
+        last_note = 0.0
         while pending or self.queue or self.active:
             now = clock()
+            if self.progress is not None and now - last_note > 15.0:
+                last_note = now
+                self.progress(f"t={now:.0f} s: {len(self.active)} resident, {len(self.queue)} queued, "
+                              f"{len(self.results)} done, {self.used / 2 ** 30:.1f} GiB in use")
             while pending and (not realtime or pending[0].arrival * time_scale <= now):
                 self.queue.append(pending.popleft())
             # retire finished requests
@@ -209,23 +260,28 @@ def main(argv=None):
     ap.add_argument("--load", type=float, default=0.7)
     ap.add_argument("--seed", type=int, default=I.SEED_BASE + 5)
     ap.add_argument("--verbose", action="store_true", help="a line on stderr per retired request")
+    ap.add_argument("--max-active", type=int, default=64,
+                    help="most requests resident at once (besides the HBM budget): the compute the mix shares")
     a = ap.parse_args(argv)
     budget = int(a.budget_gib * (1 << 30))
     burst = _scaled_requests(a.requests, a.seed, a.o_max, a.steps_scale, rate=1e9)
     import sys
 
     say = (lambda m: print(m, file=sys.stderr, flush=True)) if a.verbose else None
-    srv = Server(budget, chunk_steps=a.chunk, precision="mixed", keep_traces=False, progress=say)
+    srv = Server(budget, chunk_steps=a.chunk, precision="mixed", keep_traces=False, progress=say,
+                 max_active=a.max_active)
     b = srv.run(burst, realtime=False)
     capacity = a.requests / b["makespan_s"]
     rate = a.load * capacity
     stream = _scaled_requests(a.requests, a.seed, a.o_max, a.steps_scale, rate=rate)
-    srv2 = Server(budget, chunk_steps=a.chunk, precision="mixed", keep_traces=False, progress=say)
+    srv2 = Server(budget, chunk_steps=a.chunk, precision="mixed", keep_traces=False, progress=say,
+                  max_active=a.max_active)
     p = srv2.run(stream, realtime=True)
     torch.cuda.synchronize()
     print(json.dumps({"mix": {"requests": a.requests, "o": [10, a.o_max], "v": "7.5 o", "n_aux": "20 o",
                               "steps": [int(500 * a.steps_scale), int(8000 * a.steps_scale)],
-                              "pulses": "50% delta kick, 50% Gaussian-sine", "precision": "mixed"},
+                              "pulses": "50% delta kick, 50% Gaussian-sine", "precision": "mixed",
+                              "max_active": a.max_active, "chunk_steps": a.chunk, "budget_gib": a.budget_gib},
                       "burst": b, "capacity_req_per_s": capacity, "poisson_rate_req_per_s": rate, "poisson": p}))
 
 
