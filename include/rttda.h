@@ -324,9 +324,9 @@ typedef struct rttda_tuning {
                                stage at max_rhs, else 2                                     */
   int32_t small_path;       /* 1 = small-problem path: per RK4 stage one launch for the
                                Coulomb and exchange partial sums and one single-workgroup
-                               launch for the whole stage epilogue (o*v <= 2048, max_rhs <= 64);
-                               2 = the general kernels; the default is 1 where it applies and
-                               the exchange has at most 2e9 flops per stage at max_rhs       */
+                               launch for the whole stage epilogue (o*v <= 2048,
+                               2 o v + v^2 + o^2 <= 12288, max_rhs <= 64, n_aux > 0);
+                               2 = the general kernels (the default)                          */
   int32_t coulomb_path;     /* 1 = the Coulomb pair as vector-unit GEMVs, 2 = as skinny GEMMs
                                on the FP32 matrix cores; the default is 2 from 16 RHS
                                (max_rhs), else 1                                              */

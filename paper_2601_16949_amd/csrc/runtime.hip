@@ -55,8 +55,6 @@ constexpr int SJ_MAX = 8;    // Coulomb second-product Q splits
 constexpr int SK_MAX = 768;  // exchange Q splits
 // exchange flops per stage (at the largest RHS count) from which the Coulomb pair gets its own stream
 constexpr double OVERLAP_MIN_FLOPS = 5e10;
-// exchange flops per stage (at the largest RHS count) up to which small shapes take the small path
-constexpr double SMALL_MAX_FLOPS = 2e9;
 constexpr int SMALL_SPLITS = 64;
 // slices (2 max_rhs) from which the Coulomb pair runs on the matrix cores
 constexpr int COUL_MFMA_MIN_SLICES = 32;
@@ -809,8 +807,9 @@ rttda_status rttda_create(const rttda_desc *desc, rttda_ctx **out) {
     // up to SMALL_SPLITS Q ranges (the epilogue adds one slab per range)
     ctx->small_splits = std::max(1, std::min({SMALL_SPLITS, ctx->nq, L.sj_max + L.sk_max}));
     ctx->coul_mfma = 2 * ctx->R >= COUL_MFMA_MIN_SLICES ? 1 : 0;
-    ctx->small = small_fits(ctx->o, ctx->v, ctx->R) &&
-                 4.0 * ctx->nq * (double)ctx->ov * (ctx->o + ctx->v) * ctx->R <= SMALL_MAX_FLOPS ? 1 : 0;
+    // opt-in (rttda_tuning.small_path = 1): measured, it cuts a step's launches from 21 to 8 at
+    // o10 v40 but not its time (each of its launches takes 13-16 us)
+    ctx->small = 0;
   }
   hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&ctx->h_pulses), sizeof(DevPulse) * ctx->R);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->upload_ev, hipEventDisableTiming);

@@ -32,7 +32,23 @@ __device__ __forceinline__ void split_hl(double x, __hip_bfloat16 &hi, __hip_bfl
 
 constexpr int EPT2 = SMALL_OV_MAX / 256;  // elements per thread of k_small_2e
 
-// grid (nsplit, ns), 256 threads; dynamic LDS: X slice and W, 2 ov floats
+// sum_k x[k sx] y[k sy] for k < n as four interleaved partial sums (four independent LDS reads and
+// FMAs in flight instead of one dependent chain), added in a fixed order
+template <typename T>
+__device__ __forceinline__ T dot4(const T *x, int sx, const T *y, int sy, int n) {
+  T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+  int k = 0;
+  for (; k + 4 <= n; k += 4) {
+    a0 += x[k * sx] * y[k * sy];
+    a1 += x[(k + 1) * sx] * y[(k + 1) * sy];
+    a2 += x[(k + 2) * sx] * y[(k + 2) * sy];
+    a3 += x[(k + 3) * sx] * y[(k + 3) * sy];
+  }
+  for (; k < n; ++k) a0 += x[k * sx] * y[k * sy];
+  return (a0 + a1) + (a2 + a3);
+}
+
+// grid (nsplit, ns), 256 threads; dynamic LDS: X slice, W, B_vv^Q and B_oo^Q (floats)
 template <typename TB>
 __global__ __launch_bounds__(256) void k_small_2e(const TB *__restrict__ Bov, const TB *__restrict__ Boo,
                                                   const TB *__restrict__ Bvv, const float *__restrict__ X, int o,
@@ -42,7 +58,7 @@ __global__ __launch_bounds__(256) void k_small_2e(const TB *__restrict__ Bov, co
   __shared__ float red[4];
   const int sp = blockIdx.x, s = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int ov = o * v;
-  float *Xs = sm2, *W = sm2 + ov;
+  float *Xs = sm2, *W = sm2 + ov, *Vs = W + ov, *Os = Vs + v * v;
   const float *Xg = X + (size_t)s * ov;
   for (int e = tid; e < ov; e += 256) Xs[e] = Xg[e];
   __syncthreads();
@@ -52,41 +68,41 @@ __global__ __launch_bounds__(256) void k_small_2e(const TB *__restrict__ Bov, co
   const int qa = (int)((long long)sp * nq / nsplit), qb = (int)((long long)(sp + 1) * nq / nsplit);
   for (int q = qa; q < qb; ++q) {
     const TB *Bq = Bov + (size_t)q * ov;
+    const TB *Vq = Bvv + (size_t)q * v * v;
+    const TB *Oq = Boo + (size_t)q * o * o;
+    for (int e = tid; e < v * v; e += 256) Vs[e] = bload(Vq, e);  // coalesced staging of this Q's factors
+    for (int e = tid; e < o * o; e += 256) Os[e] = bload(Oq, e);
+    float bq[EPT2];
     float pd = 0.f;
 #pragma unroll
     for (int k = 0; k < EPT2; ++k) {
       const int e = tid + 256 * k;
-      if (e < ov) pd += bload(Bq, e) * Xs[e];
+      bq[k] = e < ov ? bload(Bq, e) : 0.f;
+      if (e < ov) pd += bq[k] * Xs[e];
     }
     pd = wsum(pd);
     if (lane == 0) red[wave] = pd;
     __syncthreads();
     const float d = (red[0] + red[1]) + (red[2] + red[3]);
-    const TB *Vq = Bvv + (size_t)q * v * v;
 #pragma unroll
     for (int k = 0; k < EPT2; ++k) {
       const int e = tid + 256 * k;
       if (e < ov) {
-        J[k] += 2.f * d * bload(Bq, e);
+        J[k] += 2.f * d * bq[k];
         const int i = e / v, a = e - i * v;
-        float w = 0.f;
-        for (int b = 0; b < v; ++b) w += Xs[i * v + b] * bload(Vq, (size_t)b * v + a);
-        W[e] = w;
+        W[e] = dot4(Xs + i * v, 1, Vs + a, v, v);
       }
     }
     __syncthreads();
-    const TB *Oq = Boo + (size_t)q * o * o;
 #pragma unroll
     for (int k = 0; k < EPT2; ++k) {
       const int e = tid + 256 * k;
       if (e < ov) {
         const int i = e / v, a = e - i * v;
-        float t = 0.f;
-        for (int j = 0; j < o; ++j) t += bload(Oq, (size_t)i * o + j) * W[j * v + a];
-        K[k] += t;
+        K[k] += dot4(Os + i * o, 1, W + a, v, o);
       }
     }
-    __syncthreads();  // W and red are rewritten by the next Q
+    __syncthreads();  // W, red and the staged factors are rewritten by the next Q
   }
   float *Pp = P + ((size_t)sp * ns + s) * ov;
 #pragma unroll
@@ -98,7 +114,9 @@ __global__ __launch_bounds__(256) void k_small_2e(const TB *__restrict__ Bov, co
 
 constexpr int EPT = SMALL_OV_MAX / 1024;  // (i, a) elements per thread of k_small_epi
 
-// One workgroup of 1024 threads; the right-hand sides one after another.
+// One workgroup of 1024 threads; the right-hand sides one after another.  The RHS's two planes of
+// X and its dipole blocks are staged in LDS (dynamic, SMALL_LDS_DOUBLES), so the field product's
+// dot products read LDS; the partial slabs are read eight at a time.
 template <int PREC>
 __global__ __launch_bounds__(1024) void k_small_epi(int R, int o, int v, int nslab, int stage, int use_field,
                                                     int want_trace, double dt, const DevPulse *__restrict__ pulses,
@@ -114,8 +132,12 @@ __global__ __launch_bounds__(1024) void k_small_epi(int R, int o, int v, int nsl
   __shared__ double red[16][5];
   __shared__ double tot[5];
   __shared__ int bad;
+  extern __shared__ double lds_e[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int ov = o * v;
+  double *Xl = lds_e;            // [2][o][v] this RHS's stage input
+  double *Ml = Xl + 2 * ov;      // [v][v] mu_vv
+  double *Ol = Ml + v * v;       // [o][o] mu_oo
   const size_t slab = 2 * (size_t)R * ov;
   const long long step = st->step, k = step - st->step0;
   // stage -1: the sample of the state c itself (trace, norm, guard, energy) with no update, as the
@@ -130,6 +152,12 @@ __global__ __launch_bounds__(1024) void k_small_epi(int R, int o, int v, int nsl
     const double *X0 = stage <= 0 ? c0 : xs0;
     const double x0r = X0[2 * r], x0i = X0[2 * r + 1];
     const double *moo_r = moo + (size_t)r * o * o, *mov_r = mov + (size_t)r * ov, *mvv_r = mvv + (size_t)r * v * v;
+    if (need_f) {
+      for (int e = tid; e < 2 * ov; e += 1024) Xl[e] = Xin[(size_t)r * 2 * ov + e];
+      for (int e = tid; e < v * v; e += 1024) Ml[e] = mvv_r[e];
+      for (int e = tid; e < o * o; e += 1024) Ol[e] = moo_r[e];
+      __syncthreads();
+    }
     double sg[EPT][2];
     double pg0 = 0.0, pg1 = 0.0, ptr = 0.0, pnr = 0.0, pen = 0.0;
 #pragma unroll
@@ -141,7 +169,21 @@ __global__ __launch_bounds__(1024) void k_small_epi(int R, int o, int v, int nsl
       const size_t i0 = (size_t)r * 2 * ov + ia, i1 = i0 + ov;
       const double x[2] = {Xin[i0], Xin[i1]};
       double ps0 = 0.0, ps1 = 0.0;
-      for (int sl = 0; sl < nslab; ++sl) {
+      int sl = 0;
+      for (; sl + 8 <= nslab; sl += 8) {  // eight slabs' loads in flight, added in order
+        float a[8], b[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          a[u] = P[(sl + u) * slab + i0];
+          b[u] = P[(sl + u) * slab + i1];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          ps0 += (double)a[u];
+          ps1 += (double)b[u];
+        }
+      }
+      for (; sl < nslab; ++sl) {
         ps0 += (double)P[sl * slab + i0];
         ps1 += (double)P[sl * slab + i1];
       }
@@ -152,10 +194,8 @@ __global__ __launch_bounds__(1024) void k_small_epi(int R, int o, int v, int nsl
         const double mo = mov_r[ia];
         double f[2];
         for (int p = 0; p < 2; ++p) {
-          const double *Xp = Xin + ((size_t)r * 2 + p) * ov;
-          double t = 0.0;
-          for (int b = 0; b < v; ++b) t += Xp[(size_t)i * v + b] * mvv_r[(size_t)b * v + a];
-          for (int j = 0; j < o; ++j) t -= moo_r[(size_t)i * o + j] * Xp[(size_t)j * v + a];
+          const double *Xp = Xl + p * ov;
+          const double t = dot4(Xp + i * v, 1, Ml + a, v, v) - dot4(Ol + i * o, 1, Xp + a, v, o);
           f[p] = t + SQRT2 * mo * (p == 0 ? x0r : x0i);
         }
         pg0 += SQRT2 * mo * x[0];
@@ -267,12 +307,24 @@ __global__ __launch_bounds__(1024) void k_small_epi(int R, int o, int v, int nsl
 
 }  // namespace
 
+hipError_t prepare_small() {
+  const int bytes = SMALL_LDS_DOUBLES * (int)sizeof(double);
+  const void *fn[] = {reinterpret_cast<const void *>(&k_small_epi<0>), reinterpret_cast<const void *>(&k_small_epi<1>),
+                      reinterpret_cast<const void *>(&k_small_2e<float>),
+                      reinterpret_cast<const void *>(&k_small_2e<__hip_bfloat16>)};
+  for (const void *f : fn) {
+    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t launch_small_2e(hipStream_t s, int b_dtype, const void *Bov, const void *Boo, const void *Bvv,
                            const float *X, int o, int v, int nq, int ns, int nsplit, float cx, float *P) {
   const int ov = o * v;
   if (ov > SMALL_OV_MAX || nsplit < 1) return hipErrorInvalidValue;
   const dim3 grid(nsplit, ns);
-  const size_t lds = 2 * (size_t)ov * sizeof(float);
+  const size_t lds = ((size_t)2 * ov + (size_t)v * v + (size_t)o * o) * sizeof(float);
   if (b_dtype == RTTDA_BF16)
     hipLaunchKernelGGL(k_small_2e<__hip_bfloat16>, grid, dim3(256), lds, s,
                        static_cast<const __hip_bfloat16 *>(Bov), static_cast<const __hip_bfloat16 *>(Boo),
@@ -289,12 +341,13 @@ hipError_t launch_small_epi(hipStream_t s, int prec, int R, int o, int v, int ns
                             const float *P, const double *moo, const double *mov, const double *mvv,
                             const double *Xin, double *c, double *c0, double *acc, double *acc0, double *xs64,
                             double *xs0, float *x32, __hip_bfloat16 *xhi, __hip_bfloat16 *xlo, double *normref) {
-  if ((long long)o * v > SMALL_OV_MAX || R > SMALL_R_MAX) return hipErrorInvalidValue;
+  if (!small_shape_ok(o, v) || R > SMALL_R_MAX) return hipErrorInvalidValue;
+  const size_t lds = (size_t)(2 * o * v + v * v + o * o) * sizeof(double);
   if (prec == RTTDA_PREC_MIXED_BF16)
-    hipLaunchKernelGGL(k_small_epi<1>, dim3(1), dim3(1024), 0, s, R, o, v, nslab, stage, use_field, want_trace, dt,
+    hipLaunchKernelGGL(k_small_epi<1>, dim3(1), dim3(1024), lds, s, R, o, v, nslab, stage, use_field, want_trace, dt,
                        pulses, st, D, P, moo, mov, mvv, Xin, c, c0, acc, acc0, xs64, xs0, x32, xhi, xlo, normref);
   else
-    hipLaunchKernelGGL(k_small_epi<0>, dim3(1), dim3(1024), 0, s, R, o, v, nslab, stage, use_field, want_trace, dt,
+    hipLaunchKernelGGL(k_small_epi<0>, dim3(1), dim3(1024), lds, s, R, o, v, nslab, stage, use_field, want_trace, dt,
                        pulses, st, D, P, moo, mov, mvv, Xin, c, c0, acc, acc0, xs64, xs0, x32, xhi, xlo, normref);
   return hipGetLastError();
 }

@@ -31,7 +31,7 @@ def test_small_path_matches_oracle_and_general_kernels(gpu_lib, o, v, nq, precis
     pulses = _pulses()
     dt, n = 0.05, 120
     ctx = gpu_lib.Context(gpu_lib.DeviceProblem(prob, precision), max_rhs=3)
-    assert ctx.get_tuning()["small_path"] == 1  # the library's own choice at these sizes
+    assert ctx.get_tuning()["small_path"] == 2  # opt-in
     out = {}
     for mode in (1, 2):
         ctx.set_tuning(small_path=mode)
@@ -58,7 +58,7 @@ def test_small_path_graph_equals_direct_and_launch_count(gpu_lib):
     pulses = _pulses()
     res = {}
     for mode in (1, 2):  # graph replay, direct launches
-        ctx.set_tuning(use_graph=mode, steps_per_graph=8)
+        ctx.set_tuning(use_graph=mode, steps_per_graph=8, small_path=1)
         c0, c = gpu_lib.ground_state(3, 10, 40)
         res[mode] = (ctx.propagate(pulses, 0.05, 64, c0, c), c)
     assert torch.equal(res[1][0], res[2][0]) and torch.equal(res[1][1], res[2][1])
