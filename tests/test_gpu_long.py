@@ -65,3 +65,39 @@ def test_o60_v400_full_trace(gpu_lib, precision, tol, peak_tol):
         say(f"   direction {r}: trace rel err {err:.2e}, {len(po)} peaks, max shift {dw:.2e} Ha")
         assert err < tol
         assert len(pg) == len(po) and dw < peak_tol
+
+
+@pytest.mark.timeout(600)
+def test_o40_v300_rabi_populations(gpu_lib):
+    import torch
+
+    g = _load("cfg4_rabi_populations.npz")
+    wl = I.workload(4)
+    prob = I.make_problem(wl.shape, wl.seed)
+    pulses = [I.Pulse(kind=I.PULSE_GAUSS, e0=float(e0), omega=float(w), t0=400.0, fwhm=400.0, phase=np.pi / 2,
+                      direction=(0.0, 0.0, 1.0)) for e0, w in zip(g["e0"], g["omega"])]
+    R, n, every = len(pulses), wl.n_steps, int(g["pop_every"])
+    ctx = gpu_lib.Context(gpu_lib.DeviceProblem(prob, "fp32"), max_rhs=R)
+    U = torch.from_numpy(np.ascontiguousarray(g["evecs"])).cuda()
+    c0, c = gpu_lib.ground_state(R, wl.shape.o, wl.shape.v)
+    say(f"[o40 v300] {R} pulses (E0 {sorted(set(g['e0'].tolist()))}), {n} steps, populations of 8 states")
+    tr, pops = np.empty((n + 1, R)), np.empty((n + 1, R, U.shape[0]))
+    done = 0
+    for part in range(4):  # four consecutive calls, a progress line after each
+        m = (n - done) // (4 - part)
+        pp = torch.empty((m + 1, R, U.shape[0]), dtype=torch.float64, device="cuda")
+        t = ctx.propagate(pulses, wl.dt, m, c0, c, step0=done, pops=pp, pop_vectors=U)
+        torch.cuda.synchronize()
+        tr[done:done + m + 1], pops[done:done + m + 1] = t.cpu().numpy(), pp.cpu().numpy()
+        done += m
+        say(f"   {done}/{n} steps")
+    assert ctx.guard() == -1
+    ref_tr, ref_pops = g["trace"], g["pops"]
+    err_tr = np.max(np.abs(tr - ref_tr), axis=0) / np.max(np.abs(ref_tr), axis=0)
+    got_p = pops[::every]
+    err_p = np.max(np.abs(got_p - ref_pops[:, :, 1:]))
+    say(f"   trace rel err per pulse {np.array2string(err_tr, precision=2)}; populations max abs err {err_p:.2e}; "
+        f"largest excited population {ref_pops[:, :, 1:].max():.3f}")
+    assert np.all(err_tr < 1e-5)
+    assert err_p < 1e-5
+    assert ref_pops[:, :, 1:].max() > 0.01  # the pulses move population into the lowest states
