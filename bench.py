@@ -53,6 +53,9 @@ TRAFFIC = {
     ("bf16x2dlp_o64_ws1_wc2_w8", "o60_v400_nq1500_kick_xyz", 220, 6):
         {"file": "exchange_bf16_dl.hip", "src": "c660feeaed33f7d9",
          "fetch_bytes": 260366.92578125 * 1024 * 2.0, "write_bytes": 126374.82421875 * 1024 * 1.0},
+    ("bf16x2k64_o64_wc2_w8", "o60_v400_nq1500_kick_xyz", 165, 6):
+        {"file": "exchange_bf16_dl.hip", "src": "f90b2171f434b93d",
+         "fetch_bytes": 258431.93 * 1024 * 2.0, "write_bytes": 94733.10 * 1024 * 1.0},
     ("f32dlp_o64_ws1_wc1_s1", "o60_v400_nq1500_kick_xyz", 466, 3):
         {"file": "exchange_f32_dl.hip", "src": "a06a6601420a34af",
          "fetch_bytes": 507411.29375 * 1024 * 2.0, "write_bytes": 139592.9125 * 1024 * 1.0},
@@ -184,16 +187,25 @@ def short_leg(wl, precision: str, pulses, steps: int, warmup: int = 5, oracle_s:
     c0, c = rttda.ground_state(R, prob.o, prob.v)
     ctx.propagate(pulses, wl.dt, warmup, c0, c, want_trace=False)
     torch.cuda.synchronize()
+    ctx.set_profiling(True)  # per-kernel-class HIP events inside the timed region, as in the main run
     t0 = time.perf_counter()
     ctx.propagate(pulses, wl.dt, steps, c0, c, step0=warmup)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    prof = ctx.get_profile()
+    ctx.set_profiling(False)
     fc, fx = flops_per_sigma(prob.o, prob.v, prob.nq)
     tun = ctx.get_tuning()
+    ex_us = 1e3 * prof["exchange"]["ms"] / max(prof["exchange"]["launches"], 1)
+    peak = PEAK[precision]
     out = {"precision": precision, "nrhs": R, "steps": steps, "ms_per_step": round(1e3 * el / steps, 4),
            "fs_per_hour": round(steps * wl.dt * AU_FS * R / (el / 3600.0), 3),
            "sigma_gflops": round(steps * 4 * R * (fc + fx) / el / 1e9, 2),
-           "exchange_variant": ctx.variant_name(tun["exchange_variant"]), "autotuned": tuned}
+           "exchange_variant": ctx.variant_name(tun["exchange_variant"]), "autotuned": tuned,
+           # the exchange launch of this leg: algorithmic flops over its average event-timed duration
+           "roofline": {"bound": "mfma", "kernel": "exchange", "avg_launch_us": round(ex_us, 2),
+                        "achieved": round(R * fx / (ex_us * 1e-6) / 1e12, 3), "peak": peak, "unit": "TFLOP/s",
+                        "frac": round(R * fx / (ex_us * 1e-6) / 1e12 / peak, 4)}}
     if oracle_s > 0:
         ref, k, _, _ = oracle_run(wl, prob, pulses, oracle_s)
         out["error_vs_oracle"] = {"rel_trace_err": trace_error(ctx, wl, pulses, ref), "steps": k,
@@ -246,8 +258,10 @@ def main():
         wl.shape = I.Shape(wl.shape.o, wl.shape.v, wl.shape.nq, wl.shape.b_scale,
                            storage="f32" if args.precision == "fp32" else "bf16")
     if args.workload == "cfg3":
-        # 37 GB of factors: drawn on the device (same distributions, torch's generator)
-        t = I.make_device_tensors(wl.shape, wl.seed)
+        # 37 GB of factors: the per-Q host streams, uploaded a range of Q at a time (the values the
+        # oracle's cached reference read)
+        print("# drawing the o240 factors on the host", file=sys.stderr, flush=True)
+        t = I.upload_factors_streamed(wl.shape, wl.seed, threads=16)
         dev = rttda.DeviceProblem.from_tensors(wl.shape, t, wl.precision)
         prob = None
         args.no_cpu_baseline = True
@@ -256,16 +270,16 @@ def main():
         dev = rttda.DeviceProblem(prob, wl.precision)
     R = len(wl.pulses)
     ctx = rttda.Context(dev, max_rhs=R)
-    # time-step guard: Lanczos bound on rho(A) against the integrator's stability limit
-    rho, rho_bound = ctx.spectral_radius(30)
-    limit = 2.5 if args.integrator == "rk4" else 2.0
-    if rho_bound * wl.dt > limit:
-        raise SystemExit(f"refused: rho(A) dt <= {rho_bound * wl.dt:.3f} exceeds the stability limit {limit}")
     tuned = False
     if args.variant or args.splits:
         ctx.set_tuning(exchange_variant=args.variant, exchange_splits=args.splits)
     else:
         tuned = ctx.use_tuned(R, args.integrator)
+    # time-step guard: Lanczos bound on rho(A) against the integrator's stability limit
+    rho, rho_bound = ctx.spectral_radius(30)
+    limit = 2.5 if args.integrator == "rk4" else 2.0
+    if rho_bound * wl.dt > limit:
+        raise SystemExit(f"refused: rho(A) dt <= {rho_bound * wl.dt:.3f} exceeds the stability limit {limit}")
     tun = ctx.get_tuning()
     c0, c = rttda.ground_state(R, dev.o, dev.v)
     ctx.propagate(wl.pulses, wl.dt, args.warmup, c0, c, integrator=args.integrator)
@@ -372,6 +386,16 @@ def main():
             err = trace_error(ctx2, wl, wl.pulses, ref)
         out["error_vs_oracle"] = {"rel_trace_err": err, "steps": int(ref.shape[0] - 1),
                                   "bar": 1e-5 if wl.precision == "fp32" else 1e-4}
+    elif args.workload == "cfg3" and ctx is not None:
+        # the oracle's direct route costs minutes per step here: compare with its cached first steps
+        gold = os.path.join(ROOT, "tests", "golden", "cfg3_trace_z.npz")
+        if os.path.exists(gold):
+            ref = np.load(gold, allow_pickle=False)["trace"]
+            c0r, cr = rttda.ground_state(R, dev.o, dev.v)
+            got = ctx.propagate(wl.pulses, wl.dt, ref.size - 1, c0r, cr).cpu().numpy()[:, 2]
+            out["error_vs_oracle"] = {"rel_trace_err": float(np.max(np.abs(got - ref)) / np.max(np.abs(ref))),
+                                      "steps": int(ref.size - 1), "rhs": "z", "bar": 1e-4,
+                                      "reference": "cached oracle trace (tests/golden/cfg3_trace_z.npz)"}
     print(json.dumps(out), flush=True)
 
 
