@@ -25,6 +25,7 @@ from . import inputs as I
 from . import rttda
 
 AU_FS = 0.02418884326585747
+RK4_LIMIT = 2.5
 
 
 def request_flops(shape: I.Shape, n_steps: int) -> float:
@@ -108,6 +109,7 @@ class Result:
     admitted: float
     finished: float
     trace: Optional[np.ndarray] = None
+    refused: str = ""  # why the request was not propagated (empty when it was)
 
     @property
     def latency(self):
@@ -120,7 +122,7 @@ class Result:
 
 class Server:
     def __init__(self, budget_bytes: int, chunk_steps: int = 128, precision: str = "mixed", device: str = "cuda:0",
-                 keep_traces: bool = True, max_active: int = 64, progress=None):
+                 keep_traces: bool = True, max_active: int = 64, progress=None, stability_steps: int = 20):
         self.budget = int(budget_bytes)
         self.chunk = int(chunk_steps)
         self.precision = precision
@@ -128,6 +130,10 @@ class Server:
         self.keep_traces = keep_traces
         self.max_active = max_active
         self.progress = progress  # called with a line of text when a request retires, or None
+        # Lanczos steps of the time-step check at admission (0: no check).  RK4 is stable for
+        # |lambda dt| <= 2.8 on the imaginary axis; a request whose bound on rho(A) dt exceeds 2.5
+        # is refused before it takes a pool slot.
+        self.stability_steps = int(stability_steps)
         self.pool = rttda.Pool(self.budget)
         self.peak_used = 0
         self.active: List[Slot] = []
@@ -139,7 +145,7 @@ class Server:
         return self.pool.usage()[0]
 
     # ------------------------------------------------------------------------------------
-    def _admit(self, req: I.Request, now: float) -> Slot:
+    def _admit(self, req: I.Request, now: float) -> Optional[Slot]:
         import torch
 
         nb = footprint(req.shape, req.n_steps, self.precision)
@@ -152,6 +158,15 @@ class Server:
             ctx = rttda.Context(dev, max_rhs=1, stream=stream, sync_streams=False)
             c0, c = rttda.ground_state(1, op, vp, device=self.device)
             trace = torch.empty((req.n_steps + 1, 1), dtype=torch.float64, device=self.device)
+        if self.stability_steps > 0:
+            _, bound = ctx.spectral_radius(self.stability_steps)
+            if bound * req.dt > RK4_LIMIT:
+                ctx.close()
+                why = f"rho(A) dt <= {bound * req.dt:.3f} exceeds the RK4 stability limit {RK4_LIMIT}"
+                self.results[req.rid] = Result(req.rid, req.shape.o, req.n_steps, req.arrival, now, now, None, why)
+                if self.progress is not None:
+                    self.progress(f"request {req.rid} refused: {why}")
+                return None
         slot = Slot(req, ctx, dev, c0, c, trace, stream, nb, now)
         slot.pool_slot = self.pool.admit(ctx, [req.pulse], req.dt, req.n_steps, c0, c, trace, footprint=nb)
         self.peak_used = max(self.peak_used, self.used)
@@ -203,7 +218,9 @@ class Server:
                     break
                 if self.used + footprint(r.shape, r.n_steps, self.precision) <= self.budget:
                     self.queue.remove(r)
-                    self.active.append(self._admit(r, clock()))
+                    s = self._admit(r, clock())
+                    if s is not None:
+                        self.active.append(s)
             max_concurrent = max(max_concurrent, len(self.active))
             # next chunk of every resident request whose previous chunk has finished
             issued = self.pool.step(self.chunk) if self.active else 0
@@ -214,13 +231,15 @@ class Server:
                     time.sleep(max(0.0, min(0.01, pending[0].arrival * time_scale - clock())))
         makespan = clock()
         torch.cuda.synchronize()
-        res = [self.results[r.rid] for r in requests]
-        lat = np.array([x.latency for x in res])
-        wait = np.array([x.wait for x in res])
-        flops = sum(request_flops(r.shape, r.n_steps) for r in requests)
-        fs = sum(r.n_steps * r.dt * AU_FS for r in requests)
+        served = [r for r in requests if not self.results[r.rid].refused]
+        res = [self.results[r.rid] for r in served]
+        lat = np.array([x.latency for x in res]) if res else np.zeros(1)
+        wait = np.array([x.wait for x in res]) if res else np.zeros(1)
+        flops = sum(request_flops(r.shape, r.n_steps) for r in served)
+        fs = sum(r.n_steps * r.dt * AU_FS for r in served)
         return {
             "requests": len(requests),
+            "refused": len(requests) - len(served),
             "makespan_s": makespan,
             "p50_latency_s": float(np.percentile(lat, 50)),
             "p99_latency_s": float(np.percentile(lat, 99)),

@@ -49,6 +49,28 @@ def test_alone_equals_mix_and_budget(gpu_lib):
     say(f"   tight budget: max_concurrent {st2['max_concurrent']}")
 
 
+def test_unstable_request_is_refused(gpu_lib):
+    """A request whose time step exceeds the RK4 stability limit for its operator is refused at
+    admission (it takes no slot and no memory); the other requests are served as without it."""
+    from paper_2601_16949_amd import serve
+
+    reqs = small_requests(4, seed=13)
+    say("[serving] unstable request in a mix of 4")
+    base = serve.Server(budget_bytes=1 << 30, chunk_steps=32, precision="mixed")
+    base.run(reqs, realtime=False)
+    bad = reqs[2]
+    bad.dt = 40.0  # rho(A) is at least the lowest excitation (above 0.1 Ha here): rho dt > 4
+    srv = serve.Server(budget_bytes=1 << 30, chunk_steps=32, precision="mixed")
+    st = srv.run(reqs, realtime=False)
+    say(f"   {st['refused']} refused: {srv.results[bad.rid].refused}")
+    assert st["refused"] == 1 and srv.results[bad.rid].refused
+    assert srv.results[bad.rid].trace is None and srv.peak_used <= base.peak_used
+    for r in reqs:
+        if r is not bad:
+            assert not srv.results[r.rid].refused
+            assert np.array_equal(srv.results[r.rid].trace, base.results[r.rid].trace), r.rid
+
+
 def test_probe_request_matches_oracle(gpu_lib):
     import torch
     from paper_2601_16949_amd import serve
