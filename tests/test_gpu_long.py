@@ -42,7 +42,7 @@ def _run_in_parts(ctx, pulses, dt, n, c0, c, parts=4, **kw):
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("precision,tol,peak_tol", [("fp32", 1e-5, 1e-5)])
+@pytest.mark.parametrize("precision,tol,peak_tol", [("fp32", 1e-5, 1e-5), ("mixed", 1e-4, 1e-4)])
 def test_o60_v400_full_trace(gpu_lib, precision, tol, peak_tol):
     import torch
 
