@@ -16,6 +16,13 @@
 // row is XOR-swizzled with bits of the row index so that the 16-byte fragment reads of the MFMA
 // operands (rows n = 0..15 at one logical chunk) spread over all banks.  B_oo^Q rows (o16 floats)
 // are swizzled the same way with the low row bits.
+//
+// Paired slices (OH > 0): a kernel slice of O16 rows holds two real slices of at most OH rows each
+// (rows [0, OH) and [OH, 2 OH)), so that o = 40 runs as 80-row tiles instead of two 48-row ones.
+// The K product then takes the block-diagonal operand diag(B_oo^Q, B_oo^Q): its tile is the
+// OT x OT B_oo^Q tile (OT = OH rounded up to 16), each fragment read with the row and column
+// inside their halves and zeroed where the halves differ, and 16 x 16 tile pairs that lie wholly
+// off the diagonal blocks are skipped at compile time.
 #include <type_traits>
 
 #include "common.h"
@@ -63,39 +70,54 @@ __device__ __forceinline__ void lds_barrier() {
 
 // NWS rows of waves over the slices (2, or 1 for odd slice counts such as the split operator's
 // R real slices), 4 / NWS columns of waves over the B_vv columns
-template <int O16, int WS, int WC, int NB = 3, int NWS = 2>
+// (with OH > 0, KS counts kernel slices, each a pair of real slices)
+template <int O16, int WS, int WC, int NB = 3, int NWS = 2, int OH = 0>
 struct CfgD {
   static constexpr int NWC = 4 / NWS;
   static constexpr int KS = NWS * WS, NT = 16 * WC * NWC, JB = O16 / 16;
   static constexpr int XROWS = KS * O16;
-  static constexpr int NXW = XROWS / 64;  // X load instructions per wave (16 rows each, 4 waves)
-  static constexpr int NBW = NT / 64;     // B_vv load instructions per wave
-  static constexpr int OCH = O16 * O16 / 4;                 // 16-byte chunks of the B_oo tile
-  static constexpr int NOW = (OCH + 255) / 256;             // B_oo load instructions per wave
-  static constexpr int XS = XROWS * KC, BS = NT * KC;       // floats per buffer
-  static constexpr int OS = NOW * 256 * 4;                  // floats (padded to whole instructions)
+  static constexpr int XROWSP = (XROWS + 63) / 64 * 64;  // rows loaded (whole instructions; the rest zero)
+  static constexpr int NXW = XROWSP / 64;  // X load instructions per wave (16 rows each, 4 waves)
+  static constexpr int NBW = NT / 64;      // B_vv load instructions per wave
+  static constexpr int OT = OH ? (OH + 15) / 16 * 16 : O16;  // rows and columns of the B_oo tile
+  static constexpr int OCH = OT * OT / 4;                    // 16-byte chunks of the B_oo tile
+  static constexpr int NOW = (OCH + 255) / 256;              // B_oo load instructions per wave
+  static constexpr int XS = XROWSP * KC, BS = NT * KC;       // floats per buffer
+  static constexpr int OS = NOW * 256 * 4;                   // floats (padded to whole instructions)
   static constexpr size_t LDS = (size_t)(NB * (XS + BS) + OS) * sizeof(float);  // NB chunk buffers
-  static_assert(XROWS % 64 == 0 && NT % 64 == 0, "tile must split into whole load instructions");
+  static_assert(NT % 64 == 0, "tile must split into whole load instructions");
+  static_assert(OH == 0 || (OH % 4 == 0 && 2 * OH <= O16), "paired slices: 16-byte B_oo chunks, both halves in the tile");
 };
+
+// paired slices: does the 16 x 16 tile pair (ib, jb) of diag(B_oo, B_oo) meet a diagonal block?
+template <int OH>
+__host__ __device__ constexpr bool pair_tile_live(int ib, int jb) {
+  if (OH == 0) return true;
+  for (int h = 0; h < 2; ++h) {
+    const int lo = h * OH, hi = (h + 1) * OH;
+    if (16 * ib < hi && 16 * ib + 16 > lo && 16 * jb < hi && 16 * jb + 16 > lo) return true;
+  }
+  return false;
+}
 
 // PIPE: 0 reads each chunk's fragments after its barrier and waits for them before its MFMAs;
 // 1 is the half-chunk software pipeline (described at the loop) over three chunk buffers, loads
 // issued two chunks ahead; 2 the same over two buffers, loads one chunk ahead (less LDS, so four
 // workgroups fit a CU).
 // OCC: workgroups per CU the register budget is sized for (2, or 3 where three fit the LDS).
-template <int O16, int WS, int WC, int PIPE, int OCC, int NWS>
+template <int O16, int WS, int WC, int PIPE, int OCC, int NWS, int OH = 0>
 __global__ __launch_bounds__(256, OCC) void k_exchange_f32_dl(const float *__restrict__ Boo,
                                                          const float *__restrict__ Bvv,
                                                          const float *__restrict__ X, int o, int v, int nq, int ns,
                                                          int n_sg, int n_ct, int nsplit, float scale,
                                                          float *__restrict__ P) {
   constexpr int NB = PIPE == 2 ? 2 : 3;
-  using C = CfgD<O16, WS, WC, NB, NWS>;
-  constexpr int JB = C::JB, NXW = C::NXW, NBW = C::NBW, NOW = C::NOW, NXB = NXW + NBW;
+  using C = CfgD<O16, WS, WC, NB, NWS, OH>;
+  constexpr int JB = C::JB, NXW = C::NXW, NBW = C::NBW, NOW = C::NOW, NXB = NXW + NBW, OT = C::OT;
   extern __shared__ __attribute__((aligned(16))) float ldsd[];
   float *Xs0 = ldsd;                 // [NB][XROWS][16]
   float *Bs0 = Xs0 + NB * C::XS;     // [NB][NT][16]
-  float *Os = Bs0 + NB * C::BS;      // [O16][O16] (+ padding)
+  float *Os = Bs0 + NB * C::BS;      // [OT][OT] (+ padding)
 
   const int total = n_sg * n_ct * nsplit;
   const int per_xcd = (int)gridDim.x / 8;
@@ -135,8 +157,15 @@ __global__ __launch_bounds__(256, OCC) void k_exchange_f32_dl(const float *__res
     for (int k = 0; k < NXW; ++k) {
       const int r0 = (wave * NXW + k) * 16, r = r0 + lrow;
       const int a = a0 + 4 * ((lane & 3) ^ swz(r));
-      const int sl = s_base + r / O16, j = r % O16;
-      const float *src = (sl < ns && j < o && a < v) ? X + ((size_t)sl * o + j) * v + a : zp;
+      int sl = s_base + r / O16, j = r % O16;
+      bool rv = true;
+      if constexpr (OH > 0) {  // kernel slice s_base + r / O16 = real slices 2s (rows < OH) and 2s + 1
+        const int hf = j / OH;
+        sl = 2 * sl + hf;
+        j -= hf * OH;
+        rv = hf < 2 && r < C::XROWS;
+      }
+      const float *src = (rv && sl < ns && j < o && a < v) ? X + ((size_t)sl * o + j) * v + a : zp;
       dma16(src, Xs + r0 * KC);
     }
     const float *Vq = Bvv + (size_t)(live ? q : 0) * v * v;
@@ -159,10 +188,24 @@ __global__ __launch_bounds__(256, OCC) void k_exchange_f32_dl(const float *__res
 #pragma unroll
     for (int k = 0; k < NOW; ++k) {
       const int e0 = (wave * NOW + k) * 64, e = e0 + ln;  // 16-byte chunk index in the tile
-      const int i = e / (O16 / 4), p = e % (O16 / 4);
-      const int jc = 4 * (p ^ swz_o<O16>(i));
+      const int i = e / (OT / 4), p = e % (OT / 4);
+      const int jc = 4 * (p ^ swz_o<OT>(i));
       const float *src = (e < C::OCH && i < o && jc < o) ? Oq + (size_t)i * o + jc : zp;
       dma16(src, Os + e0 * 4);
+    }
+  };
+
+  // K-product operand: the B_oo^Q entries of rows ib*16 + n, columns jb*16 + 4g .. +3 (with paired
+  // slices, of diag(B_oo^Q, B_oo^Q): the tile entry inside the halves, zero across them)
+  auto boo_frag = [&](int ib, int jb) __attribute__((always_inline)) -> f4 {
+    const int i = ib * 16 + n;
+    if constexpr (OH == 0) {
+      return *reinterpret_cast<const f4 *>(&Os[i * O16 + 4 * ((jb * 4 + g) ^ swz_o<O16>(i))]);
+    } else {
+      const int j = jb * 16 + 4 * g;
+      const int hi = i / OH, hj = j / OH, ii = i - hi * OH, jj = j - hj * OH;
+      const f4 e = *reinterpret_cast<const f4 *>(&Os[ii * OT + 4 * ((jj >> 2) ^ swz_o<OT>(ii))]);
+      return (hi == hj && hi < 2) ? e : f4{0.f, 0.f, 0.f, 0.f};
     }
   };
 
@@ -215,20 +258,20 @@ __global__ __launch_bounds__(256, OCC) void k_exchange_f32_dl(const float *__res
       for (int jb = 0; jb < JB; ++jb) {
         f4 ar[JB];
 #pragma unroll
-        for (int ib = 0; ib < JB; ++ib) {
-          const int i = ib * 16 + n;
-          ar[ib] = *reinterpret_cast<const f4 *>(&Os[i * O16 + 4 * ((jb * 4 + g) ^ swz_o<O16>(i))]);
-        }
+        for (int ib = 0; ib < JB; ++ib)
+          if (pair_tile_live<OH>(ib, jb)) ar[ib] = boo_frag(ib, jb);
 #pragma unroll
         for (int t = 0; t < 4; ++t)
 #pragma unroll
           for (int ib = 0; ib < JB; ++ib)
+            if (pair_tile_live<OH>(ib, jb)) {
 #pragma unroll
-            for (int si = 0; si < WS; ++si)
+              for (int si = 0; si < WS; ++si)
 #pragma unroll
-              for (int cb = 0; cb < NCB; ++cb)
-                Kacc[si][ib][cb] =
-                    __builtin_amdgcn_mfma_f32_16x16x4f32(ar[ib][t], Wacc[si][jb][cb][t], Kacc[si][ib][cb], 0, 0, 0);
+                for (int cb = 0; cb < NCB; ++cb)
+                  Kacc[si][ib][cb] =
+                      __builtin_amdgcn_mfma_f32_16x16x4f32(ar[ib][t], Wacc[si][jb][cb][t], Kacc[si][ib][cb], 0, 0, 0);
+            }
       }
 #pragma unroll
       for (int a = 0; a < WS; ++a)
@@ -326,20 +369,20 @@ __global__ __launch_bounds__(256, OCC) void k_exchange_f32_dl(const float *__res
       for (int jb = 0; jb < JB; ++jb) {
         f4 ar[JB];
 #pragma unroll
-        for (int ib = 0; ib < JB; ++ib) {
-          const int i = ib * 16 + n;
-          ar[ib] = *reinterpret_cast<const f4 *>(&Os[i * O16 + 4 * ((jb * 4 + g) ^ swz_o<O16>(i))]);
-        }
+        for (int ib = 0; ib < JB; ++ib)
+          if (pair_tile_live<OH>(ib, jb)) ar[ib] = boo_frag(ib, jb);
 #pragma unroll
         for (int t = 0; t < 4; ++t)
 #pragma unroll
           for (int ib = 0; ib < JB; ++ib)
+            if (pair_tile_live<OH>(ib, jb)) {
 #pragma unroll
-            for (int si = 0; si < WS; ++si)
+              for (int si = 0; si < WS; ++si)
 #pragma unroll
-              for (int cb = 0; cb < NCB; ++cb)
-                Kacc[si][ib][cb] =
-                    __builtin_amdgcn_mfma_f32_16x16x4f32(ar[ib][t], Wacc[si][jb][cb][t], Kacc[si][ib][cb], 0, 0, 0);
+                for (int cb = 0; cb < NCB; ++cb)
+                  Kacc[si][ib][cb] =
+                      __builtin_amdgcn_mfma_f32_16x16x4f32(ar[ib][t], Wacc[si][jb][cb][t], Kacc[si][ib][cb], 0, 0, 0);
+            }
       }
 #pragma unroll
       for (int a = 0; a < WS; ++a)
@@ -448,8 +491,8 @@ __global__ __launch_bounds__(256, OCC) void k_exchange_f32_dl(const float *__res
   float *Pp = P + (size_t)sp * ns * o * v;
 #pragma unroll
   for (int si = 0; si < WS; ++si) {
-    const int sl = s_base + ws * WS + si;
-    if (sl >= ns) continue;
+    const int ks = s_base + ws * WS + si;  // kernel slice
+    if ((OH ? 2 * ks : ks) >= ns) continue;
 #pragma unroll
     for (int ib = 0; ib < JB; ++ib)
 #pragma unroll
@@ -457,32 +500,39 @@ __global__ __launch_bounds__(256, OCC) void k_exchange_f32_dl(const float *__res
         const int c = c_base + (wc * WC + cb) * 16 + n;
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-          const int i = ib * 16 + 4 * g + t;
+          int i = ib * 16 + 4 * g + t, sl = ks;
+          if constexpr (OH > 0) {
+            const int hf = i / OH;
+            sl = 2 * ks + hf;
+            i -= hf * OH;
+            if (hf >= 2 || sl >= ns) continue;
+          }
           if (i < o && c < v) Pp[((size_t)sl * o + i) * v + c] = scale * Kacc[si][ib][cb][t];
         }
       }
   }
 }
 
-template <int O16, int WS, int WC, int PIPE, int OCC, int NWS>
+template <int O16, int WS, int WC, int PIPE, int OCC, int NWS, int OH = 0>
 hipError_t launch_xf32dl(hipStream_t s, const void *Boo, const void *Bvv, const void *X, const void *, int o, int v,
                          int nq, int ns, int nsplit, float scale, float *P, void *, size_t) {
-  using C = CfgD<O16, WS, WC, PIPE == 2 ? 2 : 3, NWS>;
-  if (o > O16 || (v & 3) != 0 || (o & 3) != 0 || v < 3 * KC) return hipErrorInvalidValue;
-  const int n_sg = (ns + C::KS - 1) / C::KS, n_ct = (v + C::NT - 1) / C::NT;
+  using C = CfgD<O16, WS, WC, PIPE == 2 ? 2 : 3, NWS, OH>;
+  if (o > (OH ? OH : O16) || (v & 3) != 0 || (o & 3) != 0 || v < 3 * KC) return hipErrorInvalidValue;
+  const int nks = OH ? (ns + 1) / 2 : ns;  // kernel slices
+  const int n_sg = (nks + C::KS - 1) / C::KS, n_ct = (v + C::NT - 1) / C::NT;
   const int total = n_sg * n_ct * nsplit;
   dim3 grid((total + 7) / 8 * 8);
-  hipLaunchKernelGGL((k_exchange_f32_dl<O16, WS, WC, PIPE, OCC, NWS>), grid, dim3(256), C::LDS, s,
+  hipLaunchKernelGGL((k_exchange_f32_dl<O16, WS, WC, PIPE, OCC, NWS, OH>), grid, dim3(256), C::LDS, s,
                      static_cast<const float *>(Boo), static_cast<const float *>(Bvv), static_cast<const float *>(X), o,
                      v, nq, ns, n_sg, n_ct, nsplit, scale, P);
   return hipGetLastError();
 }
 
-template <int O16, int WS, int WC, int PIPE, int OCC, int NWS>
+template <int O16, int WS, int WC, int PIPE, int OCC, int NWS, int OH = 0>
 hipError_t prepare_xf32dl() {
-  return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_exchange_f32_dl<O16, WS, WC, PIPE, OCC, NWS>),
+  return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_exchange_f32_dl<O16, WS, WC, PIPE, OCC, NWS, OH>),
                              hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)CfgD<O16, WS, WC, PIPE == 2 ? 2 : 3, NWS>::LDS);
+                             (int)CfgD<O16, WS, WC, PIPE == 2 ? 2 : 3, NWS, OH>::LDS);
 }
 
 #define XDLS(O16, WS, WC, PIPE, OCC, NWS, NAME)                                                          \
@@ -496,12 +546,23 @@ hipError_t prepare_xf32dl() {
   XDL(O16, WS, WC, 0, 2, "f32dl_o" #O16 "_ws" #WS "_wc" #WC),                                            \
       XDL(O16, WS, WC, 1, 2, "f32dlp_o" #O16 "_ws" #WS "_wc" #WC)
 
+// paired slices: o16 is the half size OH, ks counts real slices (two per kernel slice)
+#define XDLP(O16, WS, WC, OCC, OH, NAME)                                                                 \
+  ExchangeVariant {                                                                                      \
+    RTTDA_PREC_FP32, OH, 2 * CfgD<O16, WS, WC, 3, 2, OH>::KS, CfgD<O16, WS, WC, 3, 2, OH>::NT, NAME,     \
+        &launch_xf32dl<O16, WS, WC, 1, OCC, 2, OH>, CfgD<O16, WS, WC, 3, 2, OH>::LDS,                    \
+        &prepare_xf32dl<O16, WS, WC, 1, OCC, 2, OH>, 3 * KC, 4, 4, 1, false, 2                            \
+  }
+
 // (o64 ws1 wc2 fits three workgroups per CU in both forms: at most 152 registers, 52 KiB of LDS)
 const ExchangeVariant kF32DlVariants[] = {
     XDL2(32, 1, 2), XDL2(32, 2, 2), XDL2(48, 2, 2), XDL2(64, 1, 2), XDL2(64, 2, 2), XDL2(64, 1, 4), XDL2(96, 1, 2),
     XDL(64, 1, 2, 2, 4, "f32dlq_o64_ws1_wc2"),
     // one slice per workgroup, four columns of waves (odd slice counts: no idle slice row)
     XDLS(64, 1, 2, 1, 2, 1, "f32dlp_o64_ws1_wc2_s1"), XDLS(64, 1, 1, 1, 2, 1, "f32dlp_o64_ws1_wc1_s1"),
+    // two slices of up to 40 rows in one 80-row tile
+    XDLP(80, 1, 2, 2, 40, "f32dlp_p40_ws1_wc2"), XDLP(80, 1, 4, 1, 40, "f32dlp_p40_ws1_wc4"),
+    XDLP(80, 2, 2, 1, 40, "f32dlp_p40_ws2_wc2"),
 };
 
 }  // namespace

@@ -521,7 +521,8 @@ def test_cfg3_batched_equals_single_few_steps(gpu_lib):
     assert np.array_equal(one[:, 0], got[:, 2])
 
 
-@pytest.mark.parametrize("o,v,nq,nrhs,prec", [(60, 400, 23, 3, "fp32"), (40, 300, 9, 5, "fp32"), (32, 96, 7, 2, "fp32"),
+@pytest.mark.parametrize("o,v,nq,nrhs,prec", [(60, 400, 23, 3, "fp32"), (40, 300, 9, 5, "fp32"), (36, 96, 5, 3, "fp32"),
+                                              (32, 96, 7, 2, "fp32"),
                                               (50, 136, 7, 4, "fp32"), (20, 48, 3, 1, "fp32"),
                                               (60, 400, 11, 3, "mixed"), (96, 200, 5, 1, "mixed"),
                                               (30, 96, 6, 2, "mixed"), (50, 136, 2, 4, "mixed"), (40, 104, 5, 1, "mixed"),
