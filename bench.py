@@ -226,6 +226,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--variant", type=int, default=0)
     ap.add_argument("--splits", type=int, default=0)
+    ap.add_argument("--overlap", type=int, default=0, choices=(0, 1, 2),
+                    help="1: the Coulomb pair on a second stream beside the exchange, 2: in order on one "
+                         "stream (times each kernel alone), 0: the library's choice")
     ap.add_argument("--precision", default=None, help="override the workload's precision (fp32 | mixed)")
     ap.add_argument("--integrator", default="rk4", choices=("rk4", "sso"),
                     help="rk4 (4 complex sigma per step) or the split operator sso (2 real sigma per step)")
@@ -275,6 +278,8 @@ def main():
         ctx.set_tuning(exchange_variant=args.variant, exchange_splits=args.splits)
     else:
         tuned = ctx.use_tuned(R, args.integrator)
+    if args.overlap:
+        ctx.set_tuning(overlap=args.overlap)
     # time-step guard: Lanczos bound on rho(A) against the integrator's stability limit
     rho, rho_bound = ctx.spectral_radius(30)
     limit = 2.5 if args.integrator == "rk4" else 2.0

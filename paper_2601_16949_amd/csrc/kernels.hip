@@ -213,6 +213,72 @@ __global__ __launch_bounds__(256) void k_gemv2(const TB *__restrict__ B, const f
   }
 }
 
+// Vector form (ov % 4 == 0): a block covers 256 consecutive ia, four per lane, and its four waves
+// take every fourth Q of the split's range (wave w: Q = qa + w, qa + w + 4, ...), with eight B rows
+// in flight per lane; the wave partials meet in LDS and are summed in wave order.  Each slice's sum
+// depends only on its own d values, so a batch and a single RHS give the same bits.
+template <typename TB, int ST>
+__global__ __launch_bounds__(256) void k_gemv2v(const TB *__restrict__ B, const float *__restrict__ dvec, int nq,
+                                                int ov, int ns, int nsplit, float *__restrict__ P) {
+  constexpr int QCH = 64, U = 8;
+  __shared__ float dsh[QCH][ST];
+  __shared__ float4 red[4][ST][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int e = blockIdx.x * 256 + 4 * lane;
+  const int s0 = blockIdx.y * ST, sp = blockIdx.z;
+  const int qa = (int)((long long)sp * nq / nsplit), qb = (int)((long long)(sp + 1) * nq / nsplit);
+  const bool live = e < ov;  // ov % 4 == 0: the lane's four ia are all inside or all outside
+  float4 acc[ST];
+#pragma unroll
+  for (int b = 0; b < ST; ++b) acc[b] = make_float4(0.f, 0.f, 0.f, 0.f);
+  auto fma4 = [](float4 &a, const float4 &x, float d) __attribute__((always_inline)) {
+    a.x = fmaf(x.x, d, a.x);
+    a.y = fmaf(x.y, d, a.y);
+    a.z = fmaf(x.z, d, a.z);
+    a.w = fmaf(x.w, d, a.w);
+  };
+  for (int qc = qa; qc < qb; qc += QCH) {
+    const int nqc = min(QCH, qb - qc);
+    __syncthreads();
+    for (int k = threadIdx.x; k < QCH * ST; k += 256) {
+      const int qq = k / ST, b = k % ST;
+      dsh[qq][b] = (qq < nqc && s0 + b < ns) ? dvec[(size_t)(qc + qq) * ns + s0 + b] : 0.f;
+    }
+    __syncthreads();
+    if (live) {
+      int qq = wave;
+      for (; qq + 4 * (U - 1) < nqc; qq += 4 * U) {
+        float4 bq[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) bq[u] = load_b4(B, (size_t)(qc + qq + 4 * u) * ov + e);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+          for (int b = 0; b < ST; ++b) fma4(acc[b], bq[u], dsh[qq + 4 * u][b]);
+      }
+      for (; qq < nqc; qq += 4) {
+        const float4 bq = load_b4(B, (size_t)(qc + qq) * ov + e);
+#pragma unroll
+        for (int b = 0; b < ST; ++b) fma4(acc[b], bq, dsh[qq][b]);
+      }
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < ST; ++b) red[wave][b][lane] = acc[b];
+  __syncthreads();
+  // wave w stores slices b = w, w + 4, ...
+  for (int b = wave; b < ST; b += 4) {
+    if (!live || s0 + b >= ns) continue;
+    const float4 r0 = red[0][b][lane], r1 = red[1][b][lane], r2 = red[2][b][lane], r3 = red[3][b][lane];
+    float4 t;
+    t.x = 2.f * ((r0.x + r1.x) + (r2.x + r3.x));
+    t.y = 2.f * ((r0.y + r1.y) + (r2.y + r3.y));
+    t.z = 2.f * ((r0.z + r1.z) + (r2.z + r3.z));
+    t.w = 2.f * ((r0.w + r1.w) + (r2.w + r3.w));
+    *reinterpret_cast<float4 *>(P + ((size_t)sp * ns + s0 + b) * ov + e) = t;
+  }
+}
+
 // ------------------------------------------------------------------------------------------------
 // Field product (FP64), eqs. sc2-sc5 in factorised form, on the FP64 matrix cores:
 //   F_p = X_p mu_vv - mu_oo X_p + sqrt2 mu_ov c0_p      (p = 0, 1: the real and imaginary planes)
@@ -909,6 +975,15 @@ hipError_t launch_gemv2(hipStream_t s, int b_dtype, const void *B, const float *
                         int nsplit, float *P) {
   constexpr int ST = 8;
   dim3 grid((ov + 255) / 256, (ns + ST - 1) / ST, nsplit);
+  if (ov % 4 == 0) {
+    if (b_dtype == RTTDA_BF16)
+      hipLaunchKernelGGL((k_gemv2v<__hip_bfloat16, ST>), grid, dim3(256), 0, s,
+                         static_cast<const __hip_bfloat16 *>(B), dvec, nq, ov, ns, nsplit, P);
+    else
+      hipLaunchKernelGGL((k_gemv2v<float, ST>), grid, dim3(256), 0, s, static_cast<const float *>(B), dvec, nq, ov,
+                         ns, nsplit, P);
+    return hipGetLastError();
+  }
   if (b_dtype == RTTDA_BF16)
     hipLaunchKernelGGL((k_gemv2<__hip_bfloat16, ST>), grid, dim3(256), 0, s, static_cast<const __hip_bfloat16 *>(B),
                        dvec, nq, ov, ns, nsplit, P);
