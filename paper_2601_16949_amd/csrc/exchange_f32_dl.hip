@@ -109,7 +109,7 @@ template <int O16, int WS, int WC, int PIPE, int OCC, int NWS, int OH = 0>
 __global__ __launch_bounds__(256, OCC) void k_exchange_f32_dl(const float *__restrict__ Boo,
                                                          const float *__restrict__ Bvv,
                                                          const float *__restrict__ X, int o, int v, int nq, int ns,
-                                                         int n_sg, int n_ct, int nsplit, float scale,
+                                                         int n_sg, int n_ct, int nsplit, int xres, float scale,
                                                          float *__restrict__ P) {
   constexpr int NB = PIPE == 2 ? 2 : 3;
   using C = CfgD<O16, WS, WC, NB, NWS, OH>;
@@ -123,9 +123,20 @@ __global__ __launch_bounds__(256, OCC) void k_exchange_f32_dl(const float *__res
   const int per_xcd = (int)gridDim.x / 8;
   const int lb = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
   if (lb >= total) return;
-  const int sg = lb % n_sg;
-  const int ct = (lb / n_sg) % n_ct;
-  const int sp = lb / (n_sg * n_ct);
+  // Workgroup order over (slice group, column tile, Q split), consecutive ids on one XCD.  Slice
+  // groups fastest: the workgroups of an XCD that run together share their B_vv^Q tiles in its L2
+  // (the choice when X is small).  xres: slice groups slowest, so that an XCD holds the X tiles of
+  // a few slice groups in its L2 and streams B_vv instead (the choice when X outgrows the L2).
+  int sg, ct, sp;
+  if (xres) {
+    sp = lb % nsplit;
+    ct = (lb / nsplit) % n_ct;
+    sg = lb / (nsplit * n_ct);
+  } else {
+    sg = lb % n_sg;
+    ct = (lb / n_sg) % n_ct;
+    sp = lb / (n_sg * n_ct);
+  }
   const int qa = (int)((long long)sp * nq / nsplit), qb = (int)((long long)(sp + 1) * nq / nsplit);
   const int s_base = sg * C::KS, c_base = ct * C::NT;
 
@@ -521,10 +532,12 @@ hipError_t launch_xf32dl(hipStream_t s, const void *Boo, const void *Bvv, const 
   const int nks = OH ? (ns + 1) / 2 : ns;  // kernel slices
   const int n_sg = (nks + C::KS - 1) / C::KS, n_ct = (v + C::NT - 1) / C::NT;
   const int total = n_sg * n_ct * nsplit;
+  // X (all slices) beyond half of an XCD's 4 MiB L2: keep X resident per XCD, stream B_vv
+  const int xres = (size_t)ns * o * v * sizeof(float) > (size_t)(2u << 20) ? 1 : 0;
   dim3 grid((total + 7) / 8 * 8);
   hipLaunchKernelGGL((k_exchange_f32_dl<O16, WS, WC, PIPE, OCC, NWS, OH>), grid, dim3(256), C::LDS, s,
                      static_cast<const float *>(Boo), static_cast<const float *>(Bvv), static_cast<const float *>(X), o,
-                     v, nq, ns, n_sg, n_ct, nsplit, scale, P);
+                     v, nq, ns, n_sg, n_ct, nsplit, xres, scale, P);
   return hipGetLastError();
 }
 
