@@ -1,6 +1,7 @@
 // Bandwidth- and latency-bound kernels of the RT-TDA step on gfx950:
 // dipole blocks, Coulomb GEMV pair, FP64 field/trace, stage scalars, RK4 epilogue, kick.
 #include <algorithm>
+#include <type_traits>
 
 #include "common.h"
 
@@ -104,7 +105,34 @@ __device__ __forceinline__ float wave_transpose_sum64(float (&v)[64], int lane) 
   return v[0];
 }
 
-template <typename TB, int QT, int ST, bool VEC>
+// One 16-byte load of a B row: EPL values widened to FP32 (FP32: four; BF16: four from an 8-byte load,
+// or eight)
+template <int EPL>
+__device__ __forceinline__ void load_row(const float *p, size_t i, float (&x)[EPL]) {
+  static_assert(EPL == 4, "FP32 rows: four values per 16-byte load");
+  const float4 t = *reinterpret_cast<const float4 *>(p + i);
+  x[0] = t.x, x[1] = t.y, x[2] = t.z, x[3] = t.w;
+}
+template <int EPL>
+__device__ __forceinline__ void load_row(const __hip_bfloat16 *p, size_t i, float (&x)[EPL]) {
+  static_assert(EPL == 4 || EPL == 8, "BF16 rows: four or eight values per load");
+  if constexpr (EPL == 4) {
+    const float4 t = load_b4(p, i);
+    x[0] = t.x, x[1] = t.y, x[2] = t.z, x[3] = t.w;
+  } else {
+    const uint4 u = *reinterpret_cast<const uint4 *>(p + i);  // element 2k in the low half of word k
+    const unsigned w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      x[2 * k] = __uint_as_float(w[k] << 16);
+      x[2 * k + 1] = __uint_as_float(w[k] & 0xffff0000u);
+    }
+  }
+}
+
+// VEC: EPL consecutive ia per lane and load (4: 16 bytes of FP32 or 8 of BF16; 8: 16 bytes of BF16,
+// needs ov % 8 == 0); scalar path otherwise
+template <typename TB, int QT, int ST, bool VEC, int EPL = 4>
 __global__ __launch_bounds__(256) void k_gemv1(const TB *__restrict__ B, const float *__restrict__ X, int nq, int ov,
                                                int ns, int echunk, float *__restrict__ dpart) {
   static_assert(QT * ST <= 64, "one reduced value per lane");
@@ -117,22 +145,27 @@ __global__ __launch_bounds__(256) void k_gemv1(const TB *__restrict__ B, const f
 #pragma unroll
     for (int b = 0; b < ST; ++b) acc[a][b] = 0.f;
   if constexpr (VEC) {
-    for (int e = e0 + 4 * (int)threadIdx.x; e < e1; e += 1024) {
-      float4 xs[ST];
+    for (int e = e0 + EPL * (int)threadIdx.x; e < e1; e += 256 * EPL) {
+      float xs[ST][EPL];
 #pragma unroll
       for (int b = 0; b < ST; ++b)
-        xs[b] = b < nsv ? *reinterpret_cast<const float4 *>(X + (size_t)(s0 + b) * ov + e) : make_float4(0, 0, 0, 0);
+#pragma unroll
+        for (int g = 0; g < EPL / 4; ++g) {
+          const float4 t = b < nsv ? *reinterpret_cast<const float4 *>(X + (size_t)(s0 + b) * ov + e + 4 * g)
+                                   : make_float4(0, 0, 0, 0);
+          xs[b][4 * g] = t.x, xs[b][4 * g + 1] = t.y, xs[b][4 * g + 2] = t.z, xs[b][4 * g + 3] = t.w;
+        }
 #pragma unroll
       for (int a = 0; a < QT; ++a) {
         if (a < nqv) {
-          const float4 bq = load_b4(B, (size_t)(q0 + a) * ov + e);
+          float bq[EPL];
+          load_row<EPL>(B, (size_t)(q0 + a) * ov + e, bq);
 #pragma unroll
           for (int b = 0; b < ST; ++b) {
             float t = acc[a][b];
-            t = fmaf(bq.x, xs[b].x, t);
-            t = fmaf(bq.y, xs[b].y, t);
-            t = fmaf(bq.z, xs[b].z, t);
-            acc[a][b] = fmaf(bq.w, xs[b].w, t);
+#pragma unroll
+            for (int k = 0; k < EPL; ++k) t = fmaf(bq[k], xs[b][k], t);
+            acc[a][b] = t;
           }
         }
       }
@@ -213,30 +246,27 @@ __global__ __launch_bounds__(256) void k_gemv2(const TB *__restrict__ B, const f
   }
 }
 
-// Vector form (ov % 4 == 0): a block covers 256 consecutive ia, four per lane, and its four waves
-// take every fourth Q of the split's range (wave w: Q = qa + w, qa + w + 4, ...), with eight B rows
-// in flight per lane; the wave partials meet in LDS and are summed in wave order.  Each slice's sum
-// depends only on its own d values, so a batch and a single RHS give the same bits.
-template <typename TB, int ST>
+// Vector form (ov % EPL == 0): a block covers 64 EPL consecutive ia, EPL per lane (16 bytes of B:
+// four FP32 or eight BF16 values), and its four waves take every fourth Q of the split's range
+// (wave w: Q = qa + w, qa + w + 4, ...), with eight B rows in flight per lane; the wave partials
+// meet in LDS and are summed in wave order.  Each slice's sum depends only on its own d values, so
+// a batch and a single RHS give the same bits.
+template <typename TB, int ST, int EPL>
 __global__ __launch_bounds__(256) void k_gemv2v(const TB *__restrict__ B, const float *__restrict__ dvec, int nq,
                                                 int ov, int ns, int nsplit, float *__restrict__ P) {
   constexpr int QCH = 64, U = 8;
   __shared__ float dsh[QCH][ST];
   __shared__ float4 red[4][ST][64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int e = blockIdx.x * 256 + 4 * lane;
+  const int e = blockIdx.x * (64 * EPL) + EPL * lane;
   const int s0 = blockIdx.y * ST, sp = blockIdx.z;
   const int qa = (int)((long long)sp * nq / nsplit), qb = (int)((long long)(sp + 1) * nq / nsplit);
-  const bool live = e < ov;  // ov % 4 == 0: the lane's four ia are all inside or all outside
-  float4 acc[ST];
+  const bool live = e < ov;  // ov % EPL == 0: the lane's EPL ia are all inside or all outside
+  float acc[ST][EPL];
 #pragma unroll
-  for (int b = 0; b < ST; ++b) acc[b] = make_float4(0.f, 0.f, 0.f, 0.f);
-  auto fma4 = [](float4 &a, const float4 &x, float d) __attribute__((always_inline)) {
-    a.x = fmaf(x.x, d, a.x);
-    a.y = fmaf(x.y, d, a.y);
-    a.z = fmaf(x.z, d, a.z);
-    a.w = fmaf(x.w, d, a.w);
-  };
+  for (int b = 0; b < ST; ++b)
+#pragma unroll
+    for (int k = 0; k < EPL; ++k) acc[b][k] = 0.f;
   for (int qc = qa; qc < qb; qc += QCH) {
     const int nqc = min(QCH, qb - qc);
     __syncthreads();
@@ -248,34 +278,48 @@ __global__ __launch_bounds__(256) void k_gemv2v(const TB *__restrict__ B, const 
     if (live) {
       int qq = wave;
       for (; qq + 4 * (U - 1) < nqc; qq += 4 * U) {
-        float4 bq[U];
+        float bq[U][EPL];
 #pragma unroll
-        for (int u = 0; u < U; ++u) bq[u] = load_b4(B, (size_t)(qc + qq + 4 * u) * ov + e);
+        for (int u = 0; u < U; ++u) load_row<EPL>(B, (size_t)(qc + qq + 4 * u) * ov + e, bq[u]);
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
-          for (int b = 0; b < ST; ++b) fma4(acc[b], bq[u], dsh[qq + 4 * u][b]);
+          for (int b = 0; b < ST; ++b) {
+            const float d = dsh[qq + 4 * u][b];
+#pragma unroll
+            for (int k = 0; k < EPL; ++k) acc[b][k] = fmaf(bq[u][k], d, acc[b][k]);
+          }
       }
       for (; qq < nqc; qq += 4) {
-        const float4 bq = load_b4(B, (size_t)(qc + qq) * ov + e);
+        float bq[EPL];
+        load_row<EPL>(B, (size_t)(qc + qq) * ov + e, bq);
 #pragma unroll
-        for (int b = 0; b < ST; ++b) fma4(acc[b], bq, dsh[qq][b]);
+        for (int b = 0; b < ST; ++b) {
+          const float d = dsh[qq][b];
+#pragma unroll
+          for (int k = 0; k < EPL; ++k) acc[b][k] = fmaf(bq[k], d, acc[b][k]);
+        }
       }
     }
   }
+  // wave partials through LDS, four values per lane at a time; wave w stores slices w, w + 4, ...
 #pragma unroll
-  for (int b = 0; b < ST; ++b) red[wave][b][lane] = acc[b];
-  __syncthreads();
-  // wave w stores slices b = w, w + 4, ...
-  for (int b = wave; b < ST; b += 4) {
-    if (!live || s0 + b >= ns) continue;
-    const float4 r0 = red[0][b][lane], r1 = red[1][b][lane], r2 = red[2][b][lane], r3 = red[3][b][lane];
-    float4 t;
-    t.x = 2.f * ((r0.x + r1.x) + (r2.x + r3.x));
-    t.y = 2.f * ((r0.y + r1.y) + (r2.y + r3.y));
-    t.z = 2.f * ((r0.z + r1.z) + (r2.z + r3.z));
-    t.w = 2.f * ((r0.w + r1.w) + (r2.w + r3.w));
-    *reinterpret_cast<float4 *>(P + ((size_t)sp * ns + s0 + b) * ov + e) = t;
+  for (int g = 0; g < EPL / 4; ++g) {
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < ST; ++b)
+      red[wave][b][lane] = make_float4(acc[b][4 * g], acc[b][4 * g + 1], acc[b][4 * g + 2], acc[b][4 * g + 3]);
+    __syncthreads();
+    for (int b = wave; b < ST; b += 4) {
+      if (!live || s0 + b >= ns) continue;
+      const float4 r0 = red[0][b][lane], r1 = red[1][b][lane], r2 = red[2][b][lane], r3 = red[3][b][lane];
+      float4 t;
+      t.x = 2.f * ((r0.x + r1.x) + (r2.x + r3.x));
+      t.y = 2.f * ((r0.y + r1.y) + (r2.y + r3.y));
+      t.z = 2.f * ((r0.z + r1.z) + (r2.z + r3.z));
+      t.w = 2.f * ((r0.w + r1.w) + (r2.w + r3.w));
+      *reinterpret_cast<float4 *>(P + ((size_t)sp * ns + s0 + b) * ov + e + 4 * g) = t;
+    }
   }
 }
 
@@ -932,8 +976,10 @@ hipError_t launch_to_bf16x2(hipStream_t s, const double *c, long long n, float *
 int gemv1_chunks(int nq, int ov) {
   // independent of the slice count, so that a batch and a single RHS sum d identically
   if (nq <= 0 || ov <= 0) return 1;
+  // as many ia chunks as keep the grid within one round of three workgroups per CU (the occupancy
+  // of the six- and eight-slice forms' registers), so that no second, partly filled round follows
   const int blocks = (nq + 7) / 8;
-  int es = std::max(1, std::min({(2048 + blocks - 1) / blocks, GEMV1_CHUNKS_MAX, ov / 2048}));
+  int es = std::max(1, std::min({768 / blocks, GEMV1_CHUNKS_MAX, ov / 2048}));
   const int echunk = (((ov + es - 1) / es) + 1023) / 1024 * 1024;
   return (ov + echunk - 1) / echunk;
 }
@@ -944,7 +990,15 @@ static void gemv1_go(hipStream_t s, const TB *B, const float *X, int nq, int ov,
   const bool vec = (ov % 4) == 0;
   const int echunk = nes == 1 ? ov : (((ov + nes - 1) / nes) + 1023) / 1024 * 1024;
   dim3 grid((nq + QT - 1) / QT, (ns + ST - 1) / ST, nes);
-  if (vec)
+  bool done = false;
+  if constexpr (std::is_same<TB, __hip_bfloat16>::value) {
+    if (ov % 8 == 0) {  // 16-byte loads of eight BF16 values
+      hipLaunchKernelGGL((k_gemv1<TB, QT, ST, true, 8>), grid, dim3(256), 0, s, B, X, nq, ov, ns, echunk, dpart);
+      done = true;
+    }
+  }
+  if (done) {
+  } else if (vec)
     hipLaunchKernelGGL((k_gemv1<TB, QT, ST, true>), grid, dim3(256), 0, s, B, X, nq, ov, ns, echunk, dpart);
   else
     hipLaunchKernelGGL((k_gemv1<TB, QT, ST, false>), grid, dim3(256), 0, s, B, X, nq, ov, ns, echunk, dpart);
@@ -975,13 +1029,19 @@ hipError_t launch_gemv2(hipStream_t s, int b_dtype, const void *B, const float *
                         int nsplit, float *P) {
   constexpr int ST = 8;
   dim3 grid((ov + 255) / 256, (ns + ST - 1) / ST, nsplit);
+  if (b_dtype == RTTDA_BF16 && ov % 8 == 0) {
+    dim3 g8((ov + 511) / 512, (ns + ST - 1) / ST, nsplit);
+    hipLaunchKernelGGL((k_gemv2v<__hip_bfloat16, ST, 8>), g8, dim3(256), 0, s,
+                       static_cast<const __hip_bfloat16 *>(B), dvec, nq, ov, ns, nsplit, P);
+    return hipGetLastError();
+  }
   if (ov % 4 == 0) {
     if (b_dtype == RTTDA_BF16)
-      hipLaunchKernelGGL((k_gemv2v<__hip_bfloat16, ST>), grid, dim3(256), 0, s,
+      hipLaunchKernelGGL((k_gemv2v<__hip_bfloat16, ST, 4>), grid, dim3(256), 0, s,
                          static_cast<const __hip_bfloat16 *>(B), dvec, nq, ov, ns, nsplit, P);
     else
-      hipLaunchKernelGGL((k_gemv2v<float, ST>), grid, dim3(256), 0, s, static_cast<const float *>(B), dvec, nq, ov,
-                         ns, nsplit, P);
+      hipLaunchKernelGGL((k_gemv2v<float, ST, 4>), grid, dim3(256), 0, s, static_cast<const float *>(B), dvec, nq,
+                         ov, ns, nsplit, P);
     return hipGetLastError();
   }
   if (b_dtype == RTTDA_BF16)
