@@ -101,3 +101,29 @@ def test_o40_v300_rabi_populations(gpu_lib):
     assert np.all(err_tr < 1e-5)
     assert err_p < 1e-5
     assert ref_pops[:, :, 1:].max() > 0.01  # the pulses move population into the lowest states
+
+
+@pytest.mark.timeout(900)
+def test_o240_v1800_first_steps(gpu_lib):
+    """o240 v1800 N_Q5000 with BF16 factors drawn on the host exactly as the oracle's reference
+    read them (streamed to the device in Q ranges): the z-kick trace of the first steps of the
+    batched x/y/z run against the oracle's direct route."""
+    import torch
+
+    g = _load("cfg3_trace_z.npz")
+    ref = g["trace"]
+    n = ref.size - 1
+    wl = I.workload(3)
+    say(f"[o240 v1800 N_Q5000] drawing the BF16 factors on the host ({wl.shape.nq} Q), {n} reference steps")
+    t = I.upload_factors_streamed(wl.shape, wl.seed, threads=16,
+                                  progress=lambda q: say(f"   {q} Q uploaded") if q % 640 == 0 or q == wl.shape.nq else None)
+    ctx = gpu_lib.Context(gpu_lib.DeviceProblem.from_tensors(wl.shape, t, "mixed"), max_rhs=3)
+    ctx.use_tuned(3)
+    c0, c = gpu_lib.ground_state(3, wl.shape.o, wl.shape.v)
+    tr = ctx.propagate(wl.pulses, wl.dt, n, c0, c)
+    torch.cuda.synchronize()
+    got = tr.cpu().numpy()[:, 2]
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    say(f"   z trace over {n} steps: rel err {err:.2e}")
+    assert ctx.guard() == -1
+    assert err < 1e-4
