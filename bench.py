@@ -50,6 +50,9 @@ TRAFFIC = {
     ("f32dlp_p40_ws1_wc2", "o40_v300_nq1000_gauss_cos_scan64", 40, 128):
         {"file": "exchange_f32_dl.hip", "src": "f238a7e6c53d48d8",
          "fetch_bytes": 6595093.2 * 1024 * 2.0, "write_bytes": 257260.6 * 1024 * 1.0},
+    ("f32dlp_o64_ws1_wc1_s1", "o60_v400_nq1500_kick_xyz", 466, 3):
+        {"file": "exchange_f32_dl.hip", "src": "f238a7e6c53d48d8",
+         "fetch_bytes": 507626.11 * 1024 * 2.0, "write_bytes": 139579.3 * 1024 * 1.0},
     ("bf16x2k64_o64_wc2_w8", "o60_v400_nq1500_kick_xyz", 165, 6):
         {"file": "exchange_bf16_dl.hip", "src": "f90b2171f434b93d",
          "fetch_bytes": 258431.93 * 1024 * 2.0, "write_bytes": 94733.10 * 1024 * 1.0},
@@ -304,8 +307,12 @@ def main():
     fs_h = args.steps * wl.dt * AU_FS * R / (elapsed / 3600.0)
     ex = prof["exchange"]
     ex_avg_ms = ex["ms"] / max(ex["launches"], 1)
-    # one launch covers all slices of one stage: 2R (complex RK4 stage) or R (real half step)
-    ex_flops = R * fx if args.integrator == "rk4" else R * fx / 2
+    # one launch covers all slices of one stage: 2R (complex RK4 stage) or R (real half step);
+    # on the small-problem path that launch also carries the Coulomb partial sums
+    small = tun.get("small_path") == 1
+    ex_flops = R * (fx + (fc if small else 0.0))
+    if args.integrator != "rk4":
+        ex_flops /= 2
     achieved = ex_flops / (ex_avg_ms * 1e-3) / 1e12
     peak = PEAK[wl.precision]
     breakdown = {k: {"launches": d["launches"], "avg_us": round(1e3 * d["ms"] / max(d["launches"], 1), 2),
@@ -329,11 +336,12 @@ def main():
                    "integrator": args.integrator,
                    "precision": wl.precision, "exchange_variant": ctx.variant_name(tun["exchange_variant"]),
                    "exchange_splits": tun["exchange_splits"], "coulomb_splits": tun["coulomb_splits"],
-                   "autotuned": tuned,
+                   "autotuned": tuned, "small_path": bool(tun.get("small_path") == 1),
                    "parallelism": "single GPU, RHS batched"},
         "fs_per_hour": round(fs_h, 3),
         "mfma_frac_step": round(value / 1e3 / peak, 4),
-        "roofline": {"bound": "mfma", "kernel": "exchange", "achieved": round(achieved, 3), "peak": peak,
+        "roofline": {"bound": "mfma", "kernel": "coulomb+exchange partial sums" if small else "exchange",
+                     "achieved": round(achieved, 3), "peak": peak,
                      "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": traffic,
                      # counter bytes over the same launch time, against the 8 TB/s of HBM
                      "traffic_gbs": round(traffic / (ex_avg_ms * 1e-3) / 1e9, 1) if traffic else None,

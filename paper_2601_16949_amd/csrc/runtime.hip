@@ -807,9 +807,12 @@ rttda_status rttda_create(const rttda_desc *desc, rttda_ctx **out) {
     // up to SMALL_SPLITS Q ranges (the epilogue adds one slab per range)
     ctx->small_splits = std::max(1, std::min({SMALL_SPLITS, ctx->nq, L.sj_max + L.sk_max}));
     ctx->coul_mfma = 2 * ctx->R >= COUL_MFMA_MIN_SLICES ? 1 : 0;
-    // opt-in (rttda_tuning.small_path = 1): measured, it cuts a step's launches from 21 to 8 at
-    // o10 v40 but not its time (each of its launches takes 13-16 us)
-    ctx->small = 0;
+    // the default only for the smallest problems (8 launches per RK4 step instead of 21; each of
+    // its launches takes longer, so from about 1.5e7 exchange flops per stage it loses)
+    ctx->small = small_fits(ctx->o, ctx->v, ctx->R) &&
+                         4.0 * ctx->nq * (double)ctx->ov * (ctx->o + ctx->v) * ctx->R <= SMALL_DEFAULT_FLOPS
+                     ? 1
+                     : 0;
   }
   hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&ctx->h_pulses), sizeof(DevPulse) * ctx->R);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->upload_ev, hipEventDisableTiming);
