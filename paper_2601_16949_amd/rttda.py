@@ -15,7 +15,8 @@ from typing import List, Optional, Sequence
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "librttda.so")
+# RTTDA_LIB selects another build of the same library (the host-sanitizer build of the CPU tests)
+LIB_PATH = os.environ.get("RTTDA_LIB") or os.path.join(HERE, "librttda.so")
 
 OK, E_INVAL, E_NOMEM, E_DEVICE, E_STATE, E_UNSTABLE, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 F64, F32, BF16 = 0, 1, 2
