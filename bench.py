@@ -56,11 +56,11 @@ TRAFFIC = {
     ("bf16x2k64_o64_wc2_w8", "o60_v400_nq1500_kick_xyz", 165, 6):
         {"file": "exchange_bf16_dl.hip", "src": "f90b2171f434b93d",
          "fetch_bytes": 258431.93 * 1024 * 2.0, "write_bytes": 94733.10 * 1024 * 1.0},
-    # the GEMM path: one exchange stage is 200 chunks of 25 Q, each a k_xgemm_w + k_boo_w pair
-    ("bf16x2gemm_a256x256w8_b256x128w8", "o240_v1800_nq5000_kick_xyz_mixed", 2, 6):
+    # the GEMM path: one exchange stage is 25 chunks of 200 Q, each a k_xgemm_w + k_boo_w pair
+    ("bf16x2gemm_a256x256w8_b256x128w8", "o240_v1800_nq5000_kick_xyz_mixed", 8, 6):
         {"file": "exchange_bf16_gemm.hip", "src": "7dc7d8bb3f4ee411",
-         "fetch_bytes": 200 * (631754.39 + 163649.59) * 1024 * 2.0,
-         "write_bytes": 200 * (271632.23 + 20838.12) * 1024 * 1.0},
+         "fetch_bytes": 25 * (8459398.4 + 1347847.4) * 1024 * 2.0,
+         "write_bytes": 25 * (2257817.4 + 96479.69) * 1024 * 1.0},
 }
 PEAK = {"fp32": 157.3, "mixed": 2516.6}  # dense MFMA TFLOP/s: FP32, BF16
 HBM_PEAK_GBS = 8000.0

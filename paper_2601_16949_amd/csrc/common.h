@@ -197,7 +197,7 @@ hipError_t launch_corr(hipStream_t s, int R, size_t ov, const double *X, const d
 // for o >= XGEMM_O_MIN with o % 8 == 0 and v % 8 == 0; the scratch holds W hi/lo for up to
 // XGEMM_SCRATCH_MAX bytes' worth of Q values.
 constexpr int XGEMM_O_MIN = 128;
-constexpr size_t XGEMM_SCRATCH_MAX = size_t(256) << 20;
+constexpr size_t XGEMM_SCRATCH_MAX = size_t(2048) << 20;
 
 struct ExchangeVariant {
   int precision;  // RTTDA_PREC_*
