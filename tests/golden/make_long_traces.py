@@ -12,7 +12,7 @@ GPU path reads: FP32- or BF16-rounded factors).
         and 63 of the 64-carrier scan) and E0 = 0.01 and 0.05, dt 0.05, 16000 RK4 steps in the
         eigenbasis: traces, and the populations of the ground state and of the 8 lowest TI-TDA
         states every 8 steps, plus those 8 eigenvectors -> cfg4_rabi_populations.npz
-    python tests/golden/make_long_traces.py cfg3 N
+    python tests/golden/make_long_traces.py cfg3 N [OUT]
         o240 v1800 N_Q5000 (BF16 factors), z first-order kick, dt 0.1: the first N RK4 steps of
         the direct density-fitted route with the factors read per Q range -> cfg3_trace_z.npz
 """
@@ -82,7 +82,7 @@ def cfg4():
                            f"at E0 {CFG4_E0}; pops[:, r, 0] = |c0|^2, pops[:, r, 1:] = eigenstates 1..8"))
 
 
-def cfg3(n_steps):
+def cfg3(n_steps, out=None):
     import concurrent.futures as cf
 
     wl = I.workload(3)
@@ -110,7 +110,7 @@ def cfg3(n_steps):
         trace.append(O.dipole_expectation(blocks, c0, C))
         norms.append(O.norm2(c0, C))
         say(f"step {n + 1}: trace {trace[-1]:.15e}")
-        np.savez(os.path.join(HERE, "cfg3_trace_z.npz"), trace=np.array(trace), norms=np.array(norms), dt=wl.dt,
+        np.savez(out or os.path.join(HERE, "cfg3_trace_z.npz"), trace=np.array(trace), norms=np.array(norms), dt=wl.dt,
                  kappa=p.e0, note=np.array(f"{wl.name}: oracle direct DF route (FP64, BF16-stored factors), z kick, "
                                            f"first {n + 1} RK4 steps"))
 
@@ -121,8 +121,8 @@ if __name__ == "__main__":
         cfg2(sys.argv[2])
     elif which == "cfg4":
         cfg4()
-    elif which == "cfg3":
-        cfg3(int(sys.argv[2]))
+    elif which == "cfg3":  # optional third argument: another output path
+        cfg3(int(sys.argv[2]), sys.argv[3] if len(sys.argv) > 3 else None)
     else:
         raise SystemExit(__doc__)
     say("done")
