@@ -327,7 +327,7 @@ typedef struct rttda_tuning {
                                launch for the whole stage epilogue (o*v <= 2048,
                                2 o v + v^2 + o^2 <= 12288, max_rhs <= 64, n_aux > 0);
                                2 = the general kernels.  The default is 1 where the shape fits
-                               and the exchange has at most 1.5e7 flops per stage at max_rhs
+                               and the exchange has at most 2e7 flops per stage at max_rhs
                                (4 n_aux o v (o + v) max_rhs), else 2                           */
   int32_t coulomb_path;     /* 1 = the Coulomb pair as vector-unit GEMVs, 2 = as skinny GEMMs
                                on the FP32 matrix cores; the default is 2 from 16 RHS

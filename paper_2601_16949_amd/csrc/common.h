@@ -87,9 +87,9 @@ enum : int { EP_RK4 = 0, EP_SIGMA = 1, EP_ENERGY = 2 };
 constexpr int SMALL_OV_MAX = 2048;
 constexpr int SMALL_R_MAX = 64;
 // the small path is the default up to this many exchange flops per stage at max_rhs (measured: at
-// o10 v40 N_Q120 with one RHS it matches the general kernels in FP32 and is 20 % faster in split
-// BF16; at o12 v48 N_Q160 it is slower)
-constexpr double SMALL_DEFAULT_FLOPS = 1.5e7;
+// o10 v40 N_Q120 with one or two RHS it is 10-25 % faster than the general kernels; at o12 v48
+// N_Q160 with one RHS, 2.2e7 flops, it is slower)
+constexpr double SMALL_DEFAULT_FLOPS = 2e7;
 // LDS of the two small-path kernels: the epilogue stages one RHS's X (two planes), mu_vv and mu_oo
 // in FP64, the partial-sum kernel a slice's X and W and one Q's B_vv and B_oo in FP32
 constexpr int SMALL_LDS_DOUBLES = 12288;

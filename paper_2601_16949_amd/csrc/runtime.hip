@@ -808,7 +808,7 @@ rttda_status rttda_create(const rttda_desc *desc, rttda_ctx **out) {
     ctx->small_splits = std::max(1, std::min({SMALL_SPLITS, ctx->nq, L.sj_max + L.sk_max}));
     ctx->coul_mfma = 2 * ctx->R >= COUL_MFMA_MIN_SLICES ? 1 : 0;
     // the default only for the smallest problems (8 launches per RK4 step instead of 21; each of
-    // its launches takes longer, so from about 1.5e7 exchange flops per stage it loses)
+    // its launches takes longer, so from about 2e7 exchange flops per stage it loses)
     ctx->small = small_fits(ctx->o, ctx->v, ctx->R) &&
                          4.0 * ctx->nq * (double)ctx->ov * (ctx->o + ctx->v) * ctx->R <= SMALL_DEFAULT_FLOPS
                      ? 1

@@ -112,13 +112,14 @@ __global__ __launch_bounds__(256) void k_small_2e(const TB *__restrict__ Bov, co
   }
 }
 
-constexpr int EPT = SMALL_OV_MAX / 1024;  // (i, a) elements per thread of k_small_epi
+constexpr int NTE = 512;                  // threads of k_small_epi (two waves per SIMD: no register spills)
+constexpr int EPT = SMALL_OV_MAX / NTE;   // (i, a) elements per thread of k_small_epi
 
-// One workgroup of 1024 threads; the right-hand sides one after another.  The RHS's two planes of
+// One workgroup of NTE threads; the right-hand sides one after another.  The RHS's two planes of
 // X and its dipole blocks are staged in LDS (dynamic, SMALL_LDS_DOUBLES), so the field product's
-// dot products read LDS; the partial slabs are read eight at a time.
+// dot products read LDS; the partial slabs are read sixteen at a time.
 template <int PREC>
-__global__ __launch_bounds__(1024) void k_small_epi(int R, int o, int v, int nslab, int stage, int use_field,
+__global__ __launch_bounds__(NTE) void k_small_epi(int R, int o, int v, int nslab, int stage, int use_field,
                                                     int want_trace, double dt, const DevPulse *__restrict__ pulses,
                                                     DevState *__restrict__ st, const double *__restrict__ D,
                                                     const float *__restrict__ P, const double *__restrict__ moo,
@@ -129,7 +130,7 @@ __global__ __launch_bounds__(1024) void k_small_epi(int R, int o, int v, int nsl
                                                     double *__restrict__ xs0, float *__restrict__ x32,
                                                     __hip_bfloat16 *__restrict__ xhi, __hip_bfloat16 *__restrict__ xlo,
                                                     double *__restrict__ normref) {
-  __shared__ double red[16][5];
+  __shared__ double red[NTE / 64][5];
   __shared__ double tot[5];
   __shared__ int bad;
   extern __shared__ double lds_e[];
@@ -153,16 +154,16 @@ __global__ __launch_bounds__(1024) void k_small_epi(int R, int o, int v, int nsl
     const double x0r = X0[2 * r], x0i = X0[2 * r + 1];
     const double *moo_r = moo + (size_t)r * o * o, *mov_r = mov + (size_t)r * ov, *mvv_r = mvv + (size_t)r * v * v;
     if (need_f) {
-      for (int e = tid; e < 2 * ov; e += 1024) Xl[e] = Xin[(size_t)r * 2 * ov + e];
-      for (int e = tid; e < v * v; e += 1024) Ml[e] = mvv_r[e];
-      for (int e = tid; e < o * o; e += 1024) Ol[e] = moo_r[e];
+      for (int e = tid; e < 2 * ov; e += NTE) Xl[e] = Xin[(size_t)r * 2 * ov + e];
+      for (int e = tid; e < v * v; e += NTE) Ml[e] = mvv_r[e];
+      for (int e = tid; e < o * o; e += NTE) Ol[e] = moo_r[e];
       __syncthreads();
     }
     double sg[EPT][2];
     double pg0 = 0.0, pg1 = 0.0, ptr = 0.0, pnr = 0.0, pen = 0.0;
 #pragma unroll
     for (int kk = 0; kk < EPT; ++kk) {
-      const int ia = tid + 1024 * kk;
+      const int ia = tid + NTE * kk;
       sg[kk][0] = sg[kk][1] = 0.0;
       if (ia >= ov) continue;
       const int i = ia / v, a = ia - i * v;
@@ -170,15 +171,15 @@ __global__ __launch_bounds__(1024) void k_small_epi(int R, int o, int v, int nsl
       const double x[2] = {Xin[i0], Xin[i1]};
       double ps0 = 0.0, ps1 = 0.0;
       int sl = 0;
-      for (; sl + 8 <= nslab; sl += 8) {  // eight slabs' loads in flight, added in order
-        float a[8], b[8];
+      for (; sl + 16 <= nslab; sl += 16) {  // sixteen slabs' loads in flight, added in order
+        float a[16], b[16];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < 16; ++u) {
           a[u] = P[(sl + u) * slab + i0];
           b[u] = P[(sl + u) * slab + i1];
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < 16; ++u) {
           ps0 += (double)a[u];
           ps1 += (double)b[u];
         }
@@ -218,7 +219,7 @@ __global__ __launch_bounds__(1024) void k_small_epi(int R, int o, int v, int nsl
     __syncthreads();
     if (tid < 5) {
       double a = 0.0;
-      for (int w = 0; w < 16; ++w) a += red[w][tid];
+      for (int w = 0; w < NTE / 64; ++w) a += red[w][tid];
       tot[tid] = a;
     }
     __syncthreads();
@@ -263,7 +264,7 @@ __global__ __launch_bounds__(1024) void k_small_epi(int R, int o, int v, int nsl
     // RK4 stage update of this RHS's amplitudes (k = -i sigma: Re k = Im sigma, Im k = -Re sigma)
 #pragma unroll
     for (int kk = 0; kk < EPT; ++kk) {
-      const int ia = tid + 1024 * kk;
+      const int ia = tid + NTE * kk;
       if (sample || ia >= ov) continue;
       const size_t i0 = (size_t)r * 2 * ov + ia, i1 = i0 + ov;
       const double k0 = sg[kk][1], k1 = -sg[kk][0];
@@ -344,10 +345,10 @@ hipError_t launch_small_epi(hipStream_t s, int prec, int R, int o, int v, int ns
   if (!small_shape_ok(o, v) || R > SMALL_R_MAX) return hipErrorInvalidValue;
   const size_t lds = (size_t)(2 * o * v + v * v + o * o) * sizeof(double);
   if (prec == RTTDA_PREC_MIXED_BF16)
-    hipLaunchKernelGGL(k_small_epi<1>, dim3(1), dim3(1024), lds, s, R, o, v, nslab, stage, use_field, want_trace, dt,
+    hipLaunchKernelGGL(k_small_epi<1>, dim3(1), dim3(NTE), lds, s, R, o, v, nslab, stage, use_field, want_trace, dt,
                        pulses, st, D, P, moo, mov, mvv, Xin, c, c0, acc, acc0, xs64, xs0, x32, xhi, xlo, normref);
   else
-    hipLaunchKernelGGL(k_small_epi<0>, dim3(1), dim3(1024), lds, s, R, o, v, nslab, stage, use_field, want_trace, dt,
+    hipLaunchKernelGGL(k_small_epi<0>, dim3(1), dim3(NTE), lds, s, R, o, v, nslab, stage, use_field, want_trace, dt,
                        pulses, st, D, P, moo, mov, mvv, Xin, c, c0, acc, acc0, xs64, xs0, x32, xhi, xlo, normref);
   return hipGetLastError();
 }

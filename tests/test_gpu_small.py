@@ -31,8 +31,8 @@ def test_small_path_matches_oracle_and_general_kernels(gpu_lib, o, v, nq, precis
     pulses = _pulses()
     dt, n = 0.05, 120
     ctx = gpu_lib.Context(gpu_lib.DeviceProblem(prob, precision), max_rhs=3)
-    # the default: the small path only where the exchange has at most 1.5e7 flops per stage
-    small_default = 4.0 * nq * o * v * (o + v) * 3 <= 1.5e7 and o * v <= 2048
+    # the default: the small path only where the exchange has at most 2e7 flops per stage
+    small_default = 4.0 * nq * o * v * (o + v) * 3 <= 2e7 and o * v <= 2048
     assert ctx.get_tuning()["small_path"] == (1 if small_default else 2)
     out = {}
     for mode in (1, 2):
