@@ -532,6 +532,53 @@ class EigenRoute:
             trace[n] = (np.conj(c0) * g).real + np.sum(np.conj(C) * F, axis=(1, 2)).real
         return trace
 
+    def field_free_trace_sso_blocked(self, pulse, dt: float, n_steps: int, c0=1.0 + 0j, C=None, block: int = 256):
+        """The dipole trace of the split-operator route (propagate_sso) for field-free steps after
+        a kick, through the eigenbasis: H = diag(0, A) is real, so q = Re X and p = Im X go to the
+        eigenbasis separately and each mode (q_I, p_I) of frequency w_I follows the SSO mode map
+        M = sso_mode_matrix(w_I dt), whose determinant is 1.  With cos(th) = 1 - a^2/2 (a < 2) the
+        powers are M^n = s_n M - s_(n-1) 1, s_n = sin(n th) / sin(th) (the two-term recurrence of a
+        unimodular 2 x 2 matrix); the ground mode (w = 0) has M = 1.  Each block of steps returns to
+        the amplitude basis and M acts there in factorised form, as in field_free_trace_blocked."""
+        if C is None:
+            C = np.zeros((self.op.o, self.op.v), dtype=np.complex128)
+        blocks = dipole_blocks(self.op, pulse.direction)
+        if pulse.kind in (PULSE_DELTA, PULSE_DELTA_EXACT):
+            c0, C = apply_kick(self.op, blocks, pulse, complex(c0), np.asarray(C, dtype=np.complex128))
+        elif pulse.kind != PULSE_NONE:
+            raise ValueError("field-free route takes only delta or no pulse")
+        y = self.to_eig(c0, C)
+        qy, py = y.real, y.imag  # U is real: the real and imaginary parts transform separately
+        a = self.w * dt
+        if np.any(a[1:] >= 2.0):
+            raise ValueError("split operator unstable: w dt >= 2")
+        m11 = 1.0 - a * a / 2.0
+        m12 = a
+        m21 = -a * (1.0 - a * a / 4.0)
+        th = np.arccos(np.clip(m11, -1.0, 1.0))
+        live = th > 0.0
+        sin_th = np.where(live, np.sin(th), 1.0)
+        Uexc = np.ascontiguousarray(self.U[1:, 1:])
+        o, v = self.op.o, self.op.v
+        moo, mov, mvv = blocks
+        trace = np.empty(n_steps + 1)
+        for n0 in range(0, n_steps + 1, block):
+            n = np.arange(n0, min(n_steps + 1, n0 + block))
+            s_n = np.where(live[None, :], np.sin(np.outer(n, th)) / sin_th[None, :], n[:, None].astype(float))
+            s_m = np.where(live[None, :], np.sin(np.outer(n - 1, th)) / sin_th[None, :], (n[:, None] - 1.0))
+            # M^n = s_n M - s_(n-1) 1 (for w = 0: M = 1 and s_n = n, so M^n = n 1 - (n - 1) 1 = 1)
+            Qy = (s_n * m11 - s_m) * qy + (s_n * m12) * py
+            Py = (s_n * m21) * qy + (s_n * m11 - s_m) * py
+            Xq = np.ascontiguousarray(Qy[:, 1:]) @ Uexc.T
+            Xp = np.ascontiguousarray(Py[:, 1:]) @ Uexc.T
+            Cn = (Xq + 1j * Xp).reshape(n.size, o, v)
+            c0n = Qy[:, 0] + 1j * Py[:, 0]
+            F = ((Xq + 1j * Xp).reshape(n.size * o, v) @ mvv).reshape(n.size, o, v) - np.matmul(moo, Cn) \
+                + SQRT2 * mov[None] * c0n[:, None, None]
+            g = SQRT2 * np.sum(mov[None] * Cn, axis=(1, 2))
+            trace[n] = (np.conj(c0n) * g).real + np.sum(np.conj(Cn) * F, axis=(1, 2)).real
+        return trace
+
     def propagate_rk4_many(self, pulses, dt: float, n_steps: int, n_pop: int = 0, pop_every: int = 1,
                            progress=None):
         """RK4 with fields for several right-hand sides that share one polarisation, run in the

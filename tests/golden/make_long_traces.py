@@ -12,6 +12,9 @@ GPU path reads: FP32- or BF16-rounded factors).
         and 63 of the 64-carrier scan) and E0 = 0.01 and 0.05, dt 0.05, 16000 RK4 steps in the
         eigenbasis: traces, and the populations of the ground state and of the 8 lowest TI-TDA
         states every 8 steps, plus those 8 eigenvectors -> cfg4_rabi_populations.npz
+    python tests/golden/make_long_traces.py cfg2sso fp32|mixed
+        the same shape and kicks through the split operator (eigen route of its mode map) ->
+        cfg2_trace_sso_<precision>.npz
     python tests/golden/make_long_traces.py cfg3 N [OUT]
         o240 v1800 N_Q5000 (BF16 factors), z first-order kick, dt 0.1: the first N RK4 steps of
         the direct density-fitted route with the factors read per Q range -> cfg3_trace_z.npz
@@ -51,6 +54,24 @@ def cfg2(precision):
     np.savez(os.path.join(HERE, f"cfg2_trace_{precision}.npz"), trace=trace, dt=wl.dt, kappa=I.KAPPA,
              w_lowest=route.w[1], w_highest=route.w[-1],
              note=np.array(f"{wl.name} {precision}: oracle eigen route, full dipole trace per direction (x, y, z)"))
+
+
+def cfg2_sso(precision):
+    wl = I.workload(2)
+    shape = I.Shape(wl.shape.o, wl.shape.v, wl.shape.nq, wl.shape.b_scale,
+                    storage="f32" if precision == "fp32" else "bf16")
+    op = O.Operator.from_problem(I.make_problem(shape, wl.seed))
+    say(f"cfg2 split operator {precision}: dense A and eigh at n = {op.o * op.v}")
+    route = O.EigenRoute(op)
+    say(f"eigh done: lowest {route.w[1]:.12f} Ha, highest {route.w[-1]:.12f} Ha")
+    trace = np.empty((wl.n_steps + 1, len(wl.pulses)))
+    for r, p in enumerate(wl.pulses):
+        trace[:, r] = route.field_free_trace_sso_blocked(p, wl.dt, wl.n_steps)
+        say(f"direction {r} done")
+    np.savez(os.path.join(HERE, f"cfg2_trace_sso_{precision}.npz"), trace=trace, dt=wl.dt, kappa=I.KAPPA,
+             w_lowest=route.w[1], w_highest=route.w[-1],
+             note=np.array(f"{wl.name} {precision}: oracle eigen route of the split operator, full dipole trace "
+                           f"per direction (x, y, z)"))
 
 
 CFG4_SCAN = (0, 18, 45, 63)
@@ -119,6 +140,8 @@ if __name__ == "__main__":
     which = sys.argv[1]
     if which == "cfg2":
         cfg2(sys.argv[2])
+    elif which == "cfg2sso":
+        cfg2_sso(sys.argv[2])
     elif which == "cfg4":
         cfg4()
     elif which == "cfg3":  # optional third argument: another output path

@@ -753,3 +753,21 @@ def test_bf16_stored_factors_read_back_exactly():
     np.testing.assert_array_equal(O.apply_A(ops, C), O.apply_A(op, C))
     with pytest.raises(TypeError):
         O.BF16Stored(prob.b_ov)
+
+
+def test_field_free_sso_trace_blocked_equals_direct_split_operator():
+    """The split operator's eigen route (each mode under the SSO mode map, powers by the two-term
+    recurrence of a unimodular 2 x 2 matrix) against the direct step-by-step split operator, for
+    kicks along two axes, over 600 steps in blocks that do not divide the step count."""
+    prob = I.make_problem(I.Shape(6, 14, 20, 0.05), 11)
+    op = O.Operator.from_problem(prob)
+    route = O.EigenRoute(op)
+    for d in [(0.0, 0.0, 1.0), (1.0, 0.0, 0.0)]:
+        p = I.Pulse(kind=I.PULSE_DELTA, e0=1e-3, direction=d)
+        ref, _, _ = O.propagate_sso(op, p, 0.05, 600)
+        got = route.field_free_trace_sso_blocked(p, 0.05, 600, block=97)
+        assert np.max(np.abs(got - ref)) / np.max(np.abs(ref)) < 1e-11
+    # beyond the stability limit the route refuses
+    with pytest.raises(ValueError):
+        route.field_free_trace_sso_blocked(I.Pulse(kind=I.PULSE_DELTA, e0=1e-3, direction=(0, 0, 1)),
+                                           2.5 / route.w[-1], 10)
