@@ -53,9 +53,9 @@ TRAFFIC = {
     ("f32dlp_o64_ws1_wc1_s1", "o60_v400_nq1500_kick_xyz", 466, 3):
         {"file": "exchange_f32_dl.hip", "src": "f238a7e6c53d48d8",
          "fetch_bytes": 507626.11 * 1024 * 2.0, "write_bytes": 139579.3 * 1024 * 1.0},
-    ("bf16x2k64_o64_wc2_w8", "o60_v400_nq1500_kick_xyz", 165, 6):
+    ("bf16x2k64_o64_wc2_w8", "o60_v400_nq1500_kick_xyz", 220, 6):
         {"file": "exchange_bf16_dl.hip", "src": "f90b2171f434b93d",
-         "fetch_bytes": 258431.93 * 1024 * 2.0, "write_bytes": 94733.10 * 1024 * 1.0},
+         "fetch_bytes": 264290.89 * 1024 * 2.0, "write_bytes": 125895.47 * 1024 * 1.0},
     # the GEMM path: one exchange stage is 25 chunks of 200 Q, each a k_xgemm_w + k_boo_w pair
     ("bf16x2gemm_a256x256w8_b256x128w8", "o240_v1800_nq5000_kick_xyz_mixed", 8, 6):
         {"file": "exchange_bf16_gemm.hip", "src": "7dc7d8bb3f4ee411",
