@@ -3,6 +3,7 @@
 
 * o60 v400 N_Q1500, x/y/z kicks, 20000 RK4 steps, in FP32 (dipole trace within 1e-5) and in split
   BF16 (within 1e-4; spectral peaks within 1e-4 Ha), in the launch configuration bench.py times;
+  the same 20000 steps through the split operator;
 * o40 v300 N_Q1000, Gaussian-envelope cosine pulses at four carriers of the 64-carrier scan and
   E0 = 0.01 and 0.05 (resonant Rabi cycling and the two-photon carrier), 16000 steps: traces within
   1e-5 and the populations of the ground state and the 8 lowest TI-TDA states within 1e-5;
@@ -56,6 +57,32 @@ def test_o60_v400_full_trace(gpu_lib, precision, tol, peak_tol):
     say(f"[o60 v400 {precision}] {wl.n_steps} steps, 3 RHS, autotuned {tuned}")
     c0, c = gpu_lib.ground_state(3, shape.o, shape.v)
     got = _run_in_parts(ctx, wl.pulses, wl.dt, wl.n_steps, c0, c).cpu().numpy()
+    assert ctx.guard() == -1
+    for r in range(3):
+        err = np.max(np.abs(got[:, r] - ref[:, r])) / np.max(np.abs(ref[:, r]))
+        pg = SP.peaks(got[:, r], wl.dt, I.KAPPA, omega_max=3.0)
+        po = SP.peaks(ref[:, r], wl.dt, I.KAPPA, omega_max=3.0)
+        dw = max(abs(a - b) for (a, _), (b, _) in zip(pg, po)) if len(pg) == len(po) else float("inf")
+        say(f"   direction {r}: trace rel err {err:.2e}, {len(po)} peaks, max shift {dw:.2e} Ha")
+        assert err < tol
+        assert len(pg) == len(po) and dw < peak_tol
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("precision,tol,peak_tol", [("fp32", 1e-5, 1e-5)])
+def test_o60_v400_full_trace_split_operator(gpu_lib, precision, tol, peak_tol):
+    """The paper's split operator over the same 20000 steps against the oracle's eigen route of the
+    split operator's mode map."""
+    g = _load(f"cfg2_trace_sso_{precision}.npz")
+    ref = g["trace"]
+    wl = I.workload(2)
+    shape = I.Shape(wl.shape.o, wl.shape.v, wl.shape.nq, wl.shape.b_scale, storage="f32" if precision == "fp32" else "bf16")
+    prob = I.make_problem(shape, wl.seed)
+    ctx = gpu_lib.Context(gpu_lib.DeviceProblem(prob, precision), max_rhs=3)
+    tuned = ctx.use_tuned(3, "sso")
+    say(f"[o60 v400 {precision} split operator] {wl.n_steps} steps, 3 RHS, autotuned {tuned}")
+    c0, c = gpu_lib.ground_state(3, shape.o, shape.v)
+    got = _run_in_parts(ctx, wl.pulses, wl.dt, wl.n_steps, c0, c, integrator="sso").cpu().numpy()
     assert ctx.guard() == -1
     for r in range(3):
         err = np.max(np.abs(got[:, r] - ref[:, r])) / np.max(np.abs(ref[:, r]))
