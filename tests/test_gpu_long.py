@@ -69,7 +69,7 @@ def test_o60_v400_full_trace(gpu_lib, precision, tol, peak_tol):
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("precision,tol,peak_tol", [("fp32", 1e-5, 1e-5)])
+@pytest.mark.parametrize("precision,tol,peak_tol", [("fp32", 1e-5, 1e-5), ("mixed", 1e-4, 1e-4)])
 def test_o60_v400_full_trace_split_operator(gpu_lib, precision, tol, peak_tol):
     """The paper's split operator over the same 20000 steps against the oracle's eigen route of the
     split operator's mode map."""
