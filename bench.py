@@ -352,7 +352,7 @@ def main():
                       "lanczos_steps": 30},
         "trace_finite": bool(torch.isfinite(trace).all().item()),
     }
-    if args.graph_compare or args.workload == "cfg1":
+    if args.graph_compare or args.workload in ("cfg1", "cfg2"):
         # the same K steps with the step captured once in a HIP graph and replayed, against
         # direct launches (no profiling events in either; at the launch-bound o10 v40 shape the
         # per-kernel events of the timed run above cost as much as the kernels)
