@@ -49,6 +49,7 @@ MIXED_SIGMA_CASES = [
     (100, 130, 4, 2),
     (130, 96, 5, 2),
     (7, 13, 4, 3),
+    (12, 35, 9, 2),  # o v = 420: four BF16 values per load in the Coulomb pair (o v % 8 = 4)
 ]
 
 SIGMA_TOL = {"fp32": 2e-6, "mixed": 2e-5}
