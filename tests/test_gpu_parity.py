@@ -69,18 +69,23 @@ def test_sigma_matches_oracle(gpu_lib, o, v, nq, nrhs, prec):
     dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
     field = rng.uniform(-0.05, 0.05, nrhs)
     c0d, cd = gpu_lib.to_planes(c0, c)
-    s0d, sd = ctx.sigma(field, dirs, c0d, cd)
-    torch.cuda.synchronize()
-    s0, s = gpu_lib.from_planes(s0d, sd)
-    for r in range(nrhs):
-        blocks = O.dipole_blocks(op, dirs[r])
-        h0, hC = O.apply_H(op, blocks, field[r], c0[r], c[r])
-        scale = max(np.max(np.abs(hC)), abs(h0))
-        err = np.max(np.abs(s[r] - hC)) / scale
-        err0 = abs(s0[r] - h0) / scale
-        say(f"   rhs {r}: rel err {err:.2e}, ground {err0:.2e}")
-        assert err < SIGMA_TOL[prec]
-        assert err0 < 1e-12
+    # where the small-problem path is the default, the general kernels are checked as well
+    modes = (1, 2) if ctx.get_tuning()["small_path"] == 1 else (0,)
+    for mode in modes:
+        if mode:
+            ctx.set_tuning(small_path=mode)
+        s0d, sd = ctx.sigma(field, dirs, c0d, cd)
+        torch.cuda.synchronize()
+        s0, s = gpu_lib.from_planes(s0d, sd)
+        for r in range(nrhs):
+            blocks = O.dipole_blocks(op, dirs[r])
+            h0, hC = O.apply_H(op, blocks, field[r], c0[r], c[r])
+            scale = max(np.max(np.abs(hC)), abs(h0))
+            err = np.max(np.abs(s[r] - hC)) / scale
+            err0 = abs(s0[r] - h0) / scale
+            say(f"   rhs {r}{' (small path)' if mode == 1 else ''}: rel err {err:.2e}, ground {err0:.2e}")
+            assert err < SIGMA_TOL[prec]
+            assert err0 < 1e-12
 
 
 @pytest.mark.parametrize("o,v,nq,nrhs", [(10, 40, 120, 3), (23, 51, 9, 2)])
