@@ -155,16 +155,18 @@ __global__ __launch_bounds__(256) void k_gemv1(const TB *__restrict__ B, const f
                                    : make_float4(0, 0, 0, 0);
           xs[b][4 * g] = t.x, xs[b][4 * g + 1] = t.y, xs[b][4 * g + 2] = t.z, xs[b][4 * g + 3] = t.w;
         }
+      // all QT rows' loads issued before any of their products (rows past nq read row q0)
+      float bq[QT][EPL];
+#pragma unroll
+      for (int a = 0; a < QT; ++a) load_row<EPL>(B, (size_t)(q0 + (a < nqv ? a : 0)) * ov + e, bq[a]);
 #pragma unroll
       for (int a = 0; a < QT; ++a) {
         if (a < nqv) {
-          float bq[EPL];
-          load_row<EPL>(B, (size_t)(q0 + a) * ov + e, bq);
 #pragma unroll
           for (int b = 0; b < ST; ++b) {
             float t = acc[a][b];
 #pragma unroll
-            for (int k = 0; k < EPL; ++k) t = fmaf(bq[k], xs[b][k], t);
+            for (int k = 0; k < EPL; ++k) t = fmaf(bq[a][k], xs[b][k], t);
             acc[a][b] = t;
           }
         }
